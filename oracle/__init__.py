@@ -1,0 +1,31 @@
+"""CPU oracle for the thin-disk B-spline self-gravity method (arXiv 1904.07400).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import, call, link or execute
+anything under ``oracle/``.  The product path (``paper_1904_07400_amd``) never
+does, and the two share no code: no kernels, headers, helpers, tables or
+constant generators.  Inputs come from the separate ``workloads`` module,
+which holds none of the method's arithmetic.
+
+Everything here is plain FP64 on the CPU and uses no FFT:
+
+* ``sample_lattice``     - where sigma is sampled for order k (Sec. 2.2, Sec. 2.3)
+* ``bspline_coeffs``     - sigma -> C by the two tridiagonal systems of
+                           Eqs. (z_system) and (C_system), Thomas algorithm
+* ``weights``            - w^x, w^y of Eq. (eqnwB) by quadrature of their
+                           defining integral (C code, ``csrc/sg_oracle.c``)
+* ``forces``             - F = C * w by direct summation, Eq. (eqnF)
+* ``forces_adjoint``     - the transpose of sigma -> (Fx, Fy)
+* ``disk_force_radial``  - analytic F_R of the D3 / D4 disks (Sec. 3)
+* ``error_norms``        - L1 / L2 / Linf of Eqs. (oneNormErr)-(inftyNormErr)
+* ``antiderivative``     - the closed forms of Appendix A and Eq. (intF) (mpmath)
+
+Readings of the paper that this oracle takes where the text is silent or
+ambiguous are listed in DESIGN.md ("Readings").
+"""
+from .core import (  # noqa: F401
+    sample_lattice, cell_centres, thomas, bspline_coeffs, bspline_apply, bspline_value,
+    weights, weights_at, forces, forces_from_coeffs, forces_sparse, forces_adjoint,
+    coeffs_transpose_solve, disk_force_radial, error_norms, accuracy_order,
+    antiderivative, antiderivative_intF, build,
+)

@@ -1,0 +1,434 @@
+"""Pins of the CPU oracle against things other than itself.
+
+* the closed forms of Appendix A / Eq. (intF): mixed derivative = integrand;
+* the explicit B-splines of Eqs. (Bspline2)/(Bspline3) and the centre values
+  of Eq. (weight_matrix) / the Fig. 1 caption (golden file);
+* the Thomas solve against a dense solve, and against the forward stencil of
+  Eq. (sigmaW);
+* the weights: exact k = 1 closed form (Appendix A, (alpha,beta) = (1,0)),
+  an adaptive library quadrature on every piece for k = 2, 3, the origin
+  piece against the closed forms of Appendix A, symmetries, far-field
+  expansion;
+* the direct sum: brute-force principal-value quadrature of the force
+  integral Eq. (Fx_convolution) applied to the spline interpolant on 8x8
+  grids, the momentum invariant, the adjoint identity;
+* the analytic disk forces of Sec. 3 against a brute-force quadrature of the
+  disk's force integral, continuity at the rim and the far field.
+"""
+import math
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import workloads
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ---------------------------------------------------------- closed forms --
+@pytest.mark.parametrize("ab", [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2), (3, 0), (2, 1),
+                                (1, 2), (0, 3), (4, 0), (3, 1), (2, 2), (1, 3), (0, 4)])
+def test_appendix_a_mixed_derivative(ab):
+    a, b = ab
+    mp.mp.dps = 30
+    for (x, y) in [(0.7, 1.3), (2.1, 0.4), (0.35, 0.9)]:
+        d = mp.diff(lambda u, v: oracle.antiderivative(u, v, a, b), (x, y), (1, 1))
+        f = mp.mpf(x) ** a * mp.mpf(y) ** b / mp.sqrt(mp.mpf(x) ** 2 + mp.mpf(y) ** 2) ** 3
+        assert abs(d - f) < 1e-20 * max(1, abs(f)), (ab, x, y)
+
+
+@pytest.mark.parametrize("ab", [(2, 0), (1, 1), (3, 0), (2, 1), (4, 0), (3, 1), (2, 2), (3, 2),
+                                (2, 3), (5, 0), (4, 1)])
+def test_eq_intF_mixed_derivative(ab):
+    a, b = ab
+    mp.mp.dps = 30
+    for (x, y) in [(0.7, 1.3), (1.6, 0.45)]:
+        d = mp.diff(lambda u, v: oracle.antiderivative_intF(u, v, a, b), (x, y), (1, 1))
+        f = mp.mpf(x) ** a * mp.mpf(y) ** b / mp.sqrt(mp.mpf(x) ** 2 + mp.mpf(y) ** 2) ** 3
+        assert abs(d - f) < 1e-20 * max(1, abs(f)), (ab, x, y)
+
+
+# ------------------------------------------------------------ B-splines --
+def cardinal(k, u):
+    """Explicit uniform-knot B-splines of Eqs. (Bspline1)-(Bspline3) on [0, k)."""
+    u = np.asarray(u, dtype=np.float64)
+    out = np.zeros_like(u)
+    if k == 1:
+        out[(u >= 0) & (u < 1)] = 1.0
+    elif k == 2:
+        m = (u >= 0) & (u < 1)
+        out[m] = u[m]
+        m = (u >= 1) & (u < 2)
+        out[m] = 2 - u[m]
+    elif k == 3:
+        m = (u >= 0) & (u < 1)
+        out[m] = u[m] ** 2 / 2
+        m = (u >= 1) & (u < 2)
+        out[m] = (-2 * u[m] ** 2 + 6 * u[m] - 3) / 2
+        m = (u >= 2) & (u < 3)
+        out[m] = (3 - u[m]) ** 2 / 2
+    return out
+
+
+def test_bspline_explicit_and_centre_values():
+    lines = [l.split() for l in open(os.path.join(HERE, "golden", "bspline_centre_values.txt"))
+             if not l.startswith("#")]
+    centre = [float(v) for v in lines[0][1:]]
+    Wg = np.array([float(v) for v in lines[1][1:]]).reshape(3, 3) / float(lines[2][1])
+    rng = np.random.default_rng(0)
+    for k in (1, 2, 3):
+        t = np.arange(k + 1, dtype=np.float64) * 0.37 - 0.2
+        for u in rng.uniform(0, k, 50):
+            assert abs(oracle.bspline_value(k, t, t[0] + 0.37 * u) - cardinal(k, [u])[0]) < 1e-14
+    t3 = np.array([0.0, 1.0, 2.0, 3.0])
+    vals = [oracle.bspline_value(3, t3, x) for x in (0.5, 1.5, 2.5)]
+    assert np.allclose(vals, centre, rtol=0, atol=1e-15)
+    assert np.allclose(np.outer(vals, vals), Wg, rtol=0, atol=1e-15)
+    # partition of unity on uniform knots
+    for k in (1, 2, 3):
+        for x in rng.uniform(0, 1, 20):
+            s = sum(oracle.bspline_value(k, np.arange(k + 1, dtype=float) - j, x) for j in range(k))
+            assert abs(s - 1) < 1e-14
+
+
+# -------------------------------------------------------- coefficient solve --
+def test_thomas_matches_dense_solve():
+    rng = np.random.default_rng(1)
+    n = 37
+    d = rng.standard_normal((n, 5))
+    T = 6 * np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1)
+    x = oracle.thomas(1.0, 6.0, 1.0, d, axis=0)
+    assert np.allclose(x, np.linalg.solve(T, d), rtol=0, atol=1e-14)
+
+
+def test_coeffs_invert_the_stencil():
+    rng = np.random.default_rng(2)
+    for shape in [(9, 13), (64, 48), (1, 7), (5, 1)]:
+        C = rng.standard_normal(shape)
+        s = oracle.bspline_apply(C, 3)
+        assert np.max(np.abs(oracle.bspline_coeffs(s, 3) - C)) < 1e-13
+        sigma = rng.standard_normal(shape)
+        assert np.max(np.abs(oracle.bspline_apply(oracle.bspline_coeffs(sigma, 3), 3) - sigma)) < 1e-13
+    for k in (1, 2):
+        s = rng.standard_normal((4, 6))
+        assert np.array_equal(oracle.bspline_coeffs(s, k), s)
+
+
+# ----------------------------------------------------------------- weights --
+def _k1_closed(m, n, h=1.0):
+    """k = 1 weight, corner differences of F(x,y,1,0) = -ln(y + r) (Appendix A)
+    over the cell x~ in [(-m-1/2)h, (-m+1/2)h], y~ in [(-n-1/2)h, (-n+1/2)h];
+    valid for m != 0 (the cell does not meet the line x~ = 0 where the
+    antiderivative is singular)."""
+    mp.mp.dps = 50
+    xa, xb = (-m - mp.mpf(1) / 2) * h, (-m + mp.mpf(1) / 2) * h
+    ya, yb = (-n - mp.mpf(1) / 2) * h, (-n + mp.mpf(1) / 2) * h
+    F = lambda x, y: oracle.antiderivative(x, y, 1, 0)
+    return float(F(xb, yb) - F(xa, yb) - F(xb, ya) + F(xa, ya))
+
+
+def test_weights_k1_closed_form():
+    offs = [(1, 0), (2, 1), (1, -3), (5, 17), (17, 5), (100, 30), (-250, 3), (1000, 0),
+            (3000, 2000), (4095, -4095), (-7, 1)]
+    ms, ns = zip(*offs)
+    wx, wy = oracle.weights_at(1, 1.0, 1.0, ms, ns)
+    for (m, n), w in zip(offs, wx):
+        ref = _k1_closed(m, n)
+        assert abs(w - ref) <= 2e-15 * abs(ref), (m, n, w, ref)
+    # w^y by the same formula with the roles of x and y exchanged
+    wx2, wy2 = oracle.weights_at(1, 1.0, 1.0, ns, ms)
+    assert np.allclose(wy2, wx, rtol=1e-15, atol=0)
+
+
+def _piece_poly_1d(k, m, shift):
+    """Knots (cell units) and the explicit cardinal spline as a function."""
+    t0 = -m - 0.5 - shift
+    return [t0 + r for r in range(k + 1)], (lambda x: cardinal(k, [x - t0])[0])
+
+
+@pytest.mark.parametrize("k,m,n", [(2, 1, 2), (2, -3, 0), (2, 0, 3), (3, 2, 1), (3, -1, 3), (3, 4, -2),
+                                   (3, 0, 2)])
+def test_weights_library_quadrature(k, m, n):
+    """Every spline piece integrated by scipy's adaptive quadrature."""
+    shift = (k - 1) // 2
+    tx, bx = _piece_poly_1d(k, m, shift)
+    ty, by = _piece_poly_1d(k, n, shift)
+    tot_x = tot_y = 0.0
+    for r in range(k):
+        for s in range(k):
+            xa, xb, ya, yb = tx[r], tx[r + 1], ty[s], ty[s + 1]
+            assert not (xa < 0 < xb and ya < 0 < yb)
+            fx = lambda y, x: x / (x * x + y * y) ** 1.5 * bx(x) * by(y)
+            fy = lambda y, x: y / (x * x + y * y) ** 1.5 * bx(x) * by(y)
+            tot_x += integrate.dblquad(fx, xa, xb, ya, yb, epsabs=1e-15, epsrel=1e-13)[0]
+            tot_y += integrate.dblquad(fy, xa, xb, ya, yb, epsabs=1e-15, epsrel=1e-13)[0]
+    wx, wy = oracle.weights_at(k, 1.0, 1.0, [m], [n])
+    assert abs(wx[0] - tot_x) < 1e-12 * max(abs(tot_x), 1e-3), (wx[0], tot_x)
+    assert abs(wy[0] - tot_y) < 1e-12 * max(abs(tot_y), 1e-3), (wy[0], tot_y)
+
+
+def _origin_piece_closed(k, m, n):
+    """Principal value over the piece [-1/2,1/2]^2 that holds the singularity:
+    only monomials even in both x~ and y~ survive the symmetric integration
+    (the odd ones cancel in the principal value), each being 4 times the
+    integral over [0,1/2]^2, taken by corner differences of the Appendix A
+    antiderivatives (limits at the axes by a tiny offset at 50 digits)."""
+    mp.mp.dps = 50
+    shift = (k - 1) // 2
+    tx, bx = _piece_poly_1d(k, m, shift)
+    ty, by = _piece_poly_1d(k, n, shift)
+    # polynomial coefficients of the spline pieces on [-1/2, 1/2]
+    nodes = np.array([-0.25, 0.0, 0.25])
+    px = np.polyfit(nodes, [bx(x) for x in nodes], 2)[::-1]   # p0 + p1 x + p2 x^2
+    py = np.polyfit(nodes, [by(y) for y in nodes], 2)[::-1]
+    eps = mp.mpf("1e-40")
+    H = mp.mpf(1) / 2
+
+    def quad_pos(al, be):
+        F = lambda x, y: oracle.antiderivative(x, y, al, be)
+        return F(H, H) - F(eps, H) - F(H, eps) + F(eps, eps)
+
+    wx = mp.mpf(0)
+    for a in range(3):
+        for b in range(3):
+            al, be = a + 1, b          # kernel x~ times x~^a y~^b
+            if al % 2 == 0 and be % 2 == 0 and px[a] != 0 and py[b] != 0:
+                wx += 4 * mp.mpf(px[a]) * mp.mpf(py[b]) * quad_pos(al, be)
+    return float(wx)
+
+
+@pytest.mark.parametrize("k,m,n", [(1, 0, 0), (2, 0, 0), (2, 1, 0), (2, 0, 1), (2, 1, 1), (3, 0, 0),
+                                   (3, 1, 0), (3, -1, 1), (3, 1, 1), (3, 0, 1)])
+def test_weights_origin_piece(k, m, n):
+    """Offsets whose spline has a piece on the singularity: that piece by the
+    closed forms, the other pieces by scipy's adaptive quadrature."""
+    shift = (k - 1) // 2
+    tx, bx = _piece_poly_1d(k, m, shift)
+    ty, by = _piece_poly_1d(k, n, shift)
+    tot = 0.0
+    for r in range(k):
+        for s in range(k):
+            xa, xb, ya, yb = tx[r], tx[r + 1], ty[s], ty[s + 1]
+            if xa < 0 < xb and ya < 0 < yb:
+                continue
+            f = lambda y, x: x / (x * x + y * y) ** 1.5 * bx(x) * by(y)
+            tot += integrate.dblquad(f, xa, xb, ya, yb, epsabs=1e-15, epsrel=1e-13)[0]
+    tot += _origin_piece_closed(k, m, n)
+    wx, _ = oracle.weights_at(k, 1.0, 1.0, [m], [n])
+    assert abs(wx[0] - tot) < 1e-12, (wx[0], tot)
+
+
+def test_weight_symmetries_and_scale():
+    rng = np.random.default_rng(3)
+    ms = rng.integers(-60, 61, 200)
+    ns = rng.integers(-60, 61, 200)
+    for k in (1, 3):
+        wx, wy = oracle.weights_at(k, 1.0, 1.0, ms, ns)
+        wxm, _ = oracle.weights_at(k, 1.0, 1.0, -ms, ns)
+        wxn, _ = oracle.weights_at(k, 1.0, 1.0, ms, -ns)
+        wxt, wyt = oracle.weights_at(k, 1.0, 1.0, ns, ms)
+        s = np.max(np.abs(wx))
+        assert np.max(np.abs(wx + wxm)) < 1e-15 * s
+        assert np.max(np.abs(wx - wxn)) < 1e-15 * s
+        assert np.max(np.abs(wy - wxt)) < 1e-15 * s
+        w0, _ = oracle.weights_at(k, 1.0, 1.0, np.zeros(20, int), np.arange(-10, 10))
+        assert np.max(np.abs(w0)) < 1e-15
+        wh, _ = oracle.weights_at(k, 0.03125, 0.03125, ms, ns)
+        assert np.max(np.abs(wh - wx)) < 1e-14 * s
+    # k = 2: antisymmetric about m = 1/2 and symmetric about n = 1/2
+    wx, _ = oracle.weights_at(2, 1.0, 1.0, ms, ns)
+    wxm, _ = oracle.weights_at(2, 1.0, 1.0, 1 - ms, ns)
+    wxn, _ = oracle.weights_at(2, 1.0, 1.0, ms, 1 - ns)
+    s = np.max(np.abs(wx))
+    assert np.max(np.abs(wx + wxm)) < 1e-15 * s
+    assert np.max(np.abs(wx - wxn)) < 1e-15 * s
+
+
+def test_weights_far_field():
+    """w^x -> -m/R^3 (1 + k/(8R^2) + O(R^-4)) for centred splines: the second
+    moment k/12 of the order-k spline acting on the 2-D Laplacian of x/r^3."""
+    for k in (1, 3):
+        offs = [(20, 0), (30, 40), (100, 7), (400, -300), (1500, 2000), (4000, 100)]
+        ms, ns = zip(*offs)
+        wx, _ = oracle.weights_at(k, 1.0, 1.0, ms, ns)
+        for (m, n), w in zip(offs, wx):
+            R = math.hypot(m, n)
+            base = -m / R ** 3
+            resid = (w / base - 1.0 - k / (8 * R * R)) * R ** 4
+            assert abs(resid) < 5.0, (k, m, n, resid)
+
+
+# ----------------------------------------------------------- direct sum --
+def _brute_force_pv(k, C, domain, i, j):
+    """PV of Eq. (Fx_convolution) for the spline interpolant s = sum C B B, at
+    the centre of cell (i, j), by polar quadrature about the field point,
+    split at every knot line (radially) and every knot-grid vertex
+    (angularly)."""
+    N, M = C.shape
+    x0, x1, y0, y1 = domain
+    hx, hy = (x1 - x0) / M, (y1 - y0) / N
+    shift = (k - 1) // 2
+    Px, Py = x0 + (i + 0.5) * hx, y0 + (j + 0.5) * hy
+    kx = x0 + hx * np.arange(-shift - 1, M + k + 1)
+    ky = y0 + hy * np.arange(-shift - 1, N + k + 1)
+    bx0, bx1, by0, by1 = kx[0], kx[-1], ky[0], ky[-1]
+
+    def s_at(X, Y):
+        ux = (X[:, None] - (x0 + (np.arange(M)[None, :] - shift) * hx)) / hx
+        uy = (Y[:, None] - (y0 + (np.arange(N)[None, :] - shift) * hy)) / hy
+        Bx = cardinal(k, ux.ravel()).reshape(ux.shape)
+        By = cardinal(k, uy.ravel()).reshape(uy.shape)
+        return np.einsum("pi,ji,pj->p", Bx, C, By)
+
+    s0 = s_at(np.array([Px]), np.array([Py]))[0]
+    verts = [(a, b) for a in kx for b in ky]
+    angs = sorted({math.atan2(b - Py, a - Px) % (2 * math.pi) for a, b in verts} | {0.0, 2 * math.pi})
+    gq, gw = np.polynomial.legendre.leggauss(12)
+    tq, tw = np.polynomial.legendre.leggauss(16)
+    total_x = total_y = 0.0
+    for a0, a1 in zip(angs[:-1], angs[1:]):
+        if a1 - a0 < 1e-14:
+            continue
+        for tnode, twt in zip(tq, tw):
+            th = 0.5 * (a0 + a1) + 0.5 * (a1 - a0) * tnode
+            c, s = math.cos(th), math.sin(th)
+            # exit distance from the support box
+            cand = []
+            if c > 1e-15: cand.append((bx1 - Px) / c)
+            if c < -1e-15: cand.append((bx0 - Px) / c)
+            if s > 1e-15: cand.append((by1 - Py) / s)
+            if s < -1e-15: cand.append((by0 - Py) / s)
+            rmax = min(cand)
+            cuts = [0.0, rmax]
+            if abs(c) > 1e-15:
+                cuts += [(t - Px) / c for t in kx if 0 < (t - Px) / c < rmax]
+            if abs(s) > 1e-15:
+                cuts += [(t - Py) / s for t in ky if 0 < (t - Py) / s < rmax]
+            cuts = np.unique(cuts)
+            rs, ws = [], []
+            for r0, r1 in zip(cuts[:-1], cuts[1:]):
+                rs.append(0.5 * (r0 + r1) + 0.5 * (r1 - r0) * gq)
+                ws.append(0.5 * (r1 - r0) * gw)
+            rs = np.concatenate(rs)
+            ws = np.concatenate(ws)
+            vals = (s_at(Px + rs * c, Py + rs * s) - s0) / rs
+            inner = np.dot(ws, vals) + s0 * math.log(rmax)
+            wt = 0.5 * (a1 - a0) * twt
+            total_x += wt * c * inner
+            total_y += wt * s * inner
+    return total_x, total_y
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_direct_sum_brute_force_8x8(k):
+    rng = np.random.default_rng(10 + k)
+    C = rng.uniform(-1, 1, (8, 8))
+    domain = (-1.0, 1.0, -0.5, 1.5)
+    N, M = C.shape
+    wx, wy = oracle.weights(k, M, N, 2.0 / M, 2.0 / N)
+    fx, fy = oracle.forces_from_coeffs(C, wx, wy)
+    scale = max(np.max(np.abs(fx)), np.max(np.abs(fy)))
+    for (i, j) in [(0, 0), (3, 4), (7, 2), (5, 7)]:
+        bx, by = _brute_force_pv(k, C, domain, i, j)
+        assert abs(bx - fx[j, i]) < 1e-11 * scale, (i, j, bx, fx[j, i])
+        assert abs(by - fy[j, i]) < 1e-11 * scale, (i, j, by, fy[j, i])
+
+
+def test_momentum_invariant_and_linearity():
+    rng = np.random.default_rng(5)
+    for k in (1, 3):
+        C = rng.standard_normal((24, 24))
+        wx, wy = oracle.weights(k, 24, 24, 1.0 / 12, 1.0 / 12)
+        fx, fy = oracle.forces_from_coeffs(C, wx, wy)
+        scale = np.sum(np.abs(C) * np.abs(fx))
+        assert abs(np.sum(C * fx)) < 1e-13 * scale
+        assert abs(np.sum(C * fy)) < 1e-13 * scale
+        C2 = rng.standard_normal((24, 24))
+        gx, gy = oracle.forces_from_coeffs(C2, wx, wy)
+        hx, hy = oracle.forces_from_coeffs(2 * C - 3 * C2, wx, wy)
+        assert np.allclose(hx, 2 * fx - 3 * gx, rtol=0, atol=1e-12)
+
+
+def test_sparse_superposition_matches_full_sum():
+    M, N, k = 40, 33, 3
+    i, j, c = workloads.sparse_coeffs(7, M, N, 6)
+    C = np.zeros((N, M))
+    np.add.at(C, (j, i), c)
+    wx, wy = oracle.weights(k, M, N, 2.0 / M, 2.0 / N)
+    cells = workloads.sample_cells(8, M, N, 50)
+    fx, fy = oracle.forces_from_coeffs(C, wx, wy, cells)
+    sx, sy = oracle.forces_sparse(k, 2.0 / M, 2.0 / N, M, i, j, c, cells)
+    assert np.allclose(sx, fx, rtol=0, atol=1e-13)
+    assert np.allclose(sy, fy, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_adjoint_identity(k):
+    rng = np.random.default_rng(20 + k)
+    N, M = 12, 17
+    dom = (-1.0, 1.0, -1.0, 0.5)
+    sigma = rng.standard_normal((N, M))
+    gx = rng.standard_normal((N, M))
+    gy = rng.standard_normal((N, M))
+    fx, fy = oracle.forces(sigma, k, dom)
+    gs = oracle.forces_adjoint(gx, gy, k, dom)
+    lhs = np.sum(fx * gx) + np.sum(fy * gy)
+    rhs = np.sum(sigma * gs)
+    assert abs(lhs - rhs) < 1e-12 * (abs(lhs) + 1)
+
+
+# --------------------------------------------------------- analytic disks --
+def _disk_force_brute(n, alpha, R):
+    """F^x at (R, 0) for the D_n disk (sigma0 = G = 1) by polar PV quadrature."""
+    sig = lambda x, y: np.where(x * x + y * y < alpha * alpha,
+                                np.power(np.maximum(1 - (x * x + y * y) / alpha ** 2, 0), n - 0.5), 0.0)
+    if R < alpha:
+        s0 = (1 - R * R / alpha ** 2) ** (n - 0.5)
+
+        def inner(th):
+            c, s = math.cos(th), math.sin(th)
+            re = -R * c + math.sqrt(alpha * alpha - R * R * s * s)
+            f = lambda r: (sig(R + r * c, r * s) - s0) / r
+            return integrate.quad(f, 0, re, epsabs=1e-14, epsrel=1e-13, limit=200)[0] + s0 * math.log(re)
+
+        return integrate.quad(lambda th: math.cos(th) * inner(th), 0, 2 * math.pi, epsabs=1e-13,
+                              epsrel=1e-12, limit=200)[0]
+    tt = math.asin(alpha / R)
+
+    def inner_out(th):
+        c, s = math.cos(th), math.sin(th)
+        disc = alpha * alpha - R * R * s * s
+        if disc <= 0:
+            return 0.0
+        r1, r2 = -R * c - math.sqrt(disc), -R * c + math.sqrt(disc)
+        return integrate.quad(lambda r: sig(R + r * c, r * s) / r, r1, r2, epsabs=1e-15, epsrel=1e-13,
+                              limit=200)[0]
+
+    return integrate.quad(lambda th: math.cos(th) * inner_out(th), math.pi - tt, math.pi + tt,
+                          epsabs=1e-14, epsrel=1e-12, limit=200)[0]
+
+
+@pytest.mark.parametrize("n", [3, 4])
+def test_disk_forces_against_quadrature(n):
+    alpha = 0.5
+    for R in (0.1, 0.3, 0.45, 0.7, 1.2):
+        ref = _disk_force_brute(n, alpha, R)
+        got = oracle.disk_force_radial(n, np.array([R]), alpha)[0]
+        assert abs(got - ref) < 1e-8 * abs(ref), (n, R, got, ref)
+
+
+def test_disk_forces_rim_and_far_field():
+    a = 0.8
+    for n, rim in ((3, -15 * math.pi ** 2 / 128), (4, -175 * math.pi ** 2 / 2048)):
+        lo = oracle.disk_force_radial(n, np.array([a * (1 - 1e-9)]), a)[0]
+        hi = oracle.disk_force_radial(n, np.array([a * (1 + 1e-9)]), a)[0]
+        assert abs(lo - rim) < 1e-7 and abs(hi - rim) < 1e-7
+        mass = 2 * math.pi * a * a / (2 * n + 1)
+        # F_R -> -G M / R^2 (1 + O((a/R)^2)): the deviation drops 4x per doubling of R
+        dev = [oracle.disk_force_radial(n, np.array([R]), a)[0] / (-mass / R ** 2) - 1 for R in (8.0, 16.0)]
+        assert abs(dev[0]) < 0.05 and 3.9 < dev[0] / dev[1] < 4.1, dev
+        assert oracle.disk_force_radial(n, np.array([0.0]), a)[0] == 0.0
