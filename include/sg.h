@@ -1,0 +1,136 @@
+/*
+ * sg.h — C ABI of the MI355X (gfx950) library for the in-plane
+ * self-gravitational forces of infinitesimally thin disks with order-k
+ * B-spline density interpolation (Wang, Shiue, Wu & Yen, arXiv 1904.07400).
+ *
+ * The problem (Sec. 1, Eq. (Fx_convolution); Sec. 2, Eqs. (eqnSigma)-(eqnw)):
+ * a surface density sigma confined to the rectangle [x0,x1] x [y0,y1], cut
+ * into nx x ny equal cells, is interpolated with order-k tensor B-splines
+ * (k = 1, 2, 3: piecewise constant, linear, quadratic; Sec. 2, Eqs.
+ * (Bspline1)-(Bspline3)); the forces at the cell centres are the discrete
+ * convolutions  F^x_ij = sum_{i'j'} C_{i'j'} w^x_{i-i',j-j'}  (Eq. (eqnF)) with
+ * the kernel weights of Eq. (eqnwB), G = 1, attractive sign (the integrand
+ * is (x'-x)/r^3, Sec. 2.2 Case 1).  The convolutions are evaluated with
+ * zero-padded 2nx x 2ny FFTs, so mass confined to the domain needs no
+ * boundary values.
+ *
+ * Conventions shared by every call:
+ *  - All array arguments are caller-owned DEVICE pointers (hipMalloc'd or
+ *    torch CUDA tensors), except where a parameter says HOST.
+ *  - Grid arrays are row-major [ny][nx], x fastest: cell (i, j) of the paper
+ *    (1-based) is element (j-1)*nx + (i-1).  A plan with several grids uses
+ *    packed buffers: grid g occupies elements [offset_g, offset_{g+1}) (see
+ *    sg_plan_layout).
+ *  - Element type: double for SG_FP64 plans; float for SG_FP32_SPLIT plans
+ *    (sigma, forces and gradients), except sg_weights, always double.
+ *  - Per-step calls (sg_bspline_coeffs, sg_forces, sg_forces_adjoint) are
+ *    asynchronous on the plan's HIP stream, allocate nothing and do not
+ *    synchronise; buffers must stay alive until the stream has passed the
+ *    call.  Two calls on one plan must not overlap in time (they share the
+ *    plan's workspace): issue them on the plan's stream.
+ *  - Every call returns an sg_status; a non-OK status leaves a thread-local
+ *    message for sg_last_error_message().  After a device error
+ *    (SG_ERR_DEVICE) the plan is sticky: every later call on it returns
+ *    SG_ERR_STATE until it is destroyed.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sg_plan_s* sg_plan;
+
+typedef enum {
+  SG_OK = 0,
+  SG_ERR_ARG = 1,         /* null pointer, bad size, empty or non-finite domain, bad index */
+  SG_ERR_UNSUPPORTED = 2, /* order outside 1..3, grid size without a kernel instantiation */
+  SG_ERR_NOMEM = 3,       /* device or host allocation failed */
+  SG_ERR_DEVICE = 4,      /* a HIP call or kernel launch failed (message holds the HIP error) */
+  SG_ERR_STATE = 5        /* plan is in the sticky error state, or a non-finite input was found */
+} sg_status;
+
+typedef enum {
+  SG_FP64 = 0,       /* every per-step array double; FFT and products in FP64 */
+  SG_FP32_SPLIT = 1  /* float arrays; coefficient solve in FP64, FFT in FP32 with
+                        FP64-derived twiddles, kernel spectrum carried as hi+lo floats */
+} sg_precision;
+
+/* One grid.  Cell sizes are dx = (x1-x0)/nx, dy = (y1-y0)/ny (Sec. 2, grid
+ * points x_{i+1/2} = x0 + i dx).  nx, ny: >= 2, each a power of two from 4
+ * to 8192, or three times a power of two from 12 to 6144. */
+typedef struct {
+  int32_t nx, ny;
+  double x0, x1, y0, y1;
+  int32_t order; /* k in {1, 2, 3} */
+} sg_grid;
+
+/* plan flags */
+#define SG_FLAG_CHECK_FINITE 0x1u /* sg_forces rejects non-finite sigma (SG_ERR_STATE); costs one extra read */
+
+/* Create a plan for ngrids grids (all of one precision) on the given HIP
+ * stream (hipStream_t; NULL = the null stream).  Plan time does what the
+ * paper does "once at the beginning of simulations" (end of Sec. 2.2): it
+ * evaluates the weight tables of Eq. (eqnwB) on the GPU in FP64 (closed form
+ * of Appendix A on the piece holding the singularity, Gauss-Legendre
+ * elsewhere), transforms them (FP64 FFT) and keeps their spectra.  Allocates
+ * all workspace.  Synchronises the stream before returning. */
+sg_status sg_plan_create(sg_plan* out, const sg_grid* grids /* HOST, ngrids */, int32_t ngrids,
+                         sg_precision prec, void* hip_stream, uint32_t flags);
+
+/* Release everything the plan owns; synchronises its stream first.
+ * NULL is accepted (no-op). */
+sg_status sg_plan_destroy(sg_plan p);
+
+/* Packed-buffer layout: offsets[g] = first element of grid g, offsets[ngrids]
+ * = total element count.  offsets: HOST array of ngrids+1. */
+sg_status sg_plan_layout(sg_plan p, int64_t* offsets);
+
+/* Number of grids, precision and device bytes held by the plan (any may be NULL; HOST). */
+sg_status sg_plan_info(sg_plan p, int32_t* ngrids, int32_t* prec, int64_t* device_bytes);
+
+/* Where sigma of grid g must be sampled (HOST outputs): point (i, j), 0-based,
+ * is (xs0 + i*dx, ys0 + j*dy).  Odd k: the cell centres (interpolation
+ * condition Eq. (eqnSigmaB)); k = 2: the vertices x0 + (i+1) dx, i.e. the
+ * peaks of the order-2 splines of Case 2 (Sec. 2.2), where C = sigma. */
+sg_status sg_sample_points(sg_plan p, int32_t g, double* xs0, double* ys0, double* dx, double* dy);
+
+/* Export the weights of grid g (Eq. (eqnwB)), FP64 DEVICE arrays of
+ * (2ny-1) x (2nx-1): w(m, n), m = i-i' in [-(nx-1), nx-1], n = j-j' in
+ * [-(ny-1), ny-1], at (n+ny-1)*(2nx-1) + (m+nx-1).  wx or wy may be NULL.
+ * Recomputed on the plan's stream; asynchronous. */
+sg_status sg_weights(sg_plan p, int32_t g, double* wx, double* wy);
+
+/* sigma -> spline coefficients C for every grid of the plan (Sec. 2.3): the
+ * identity for k = 1, 2; for k = 3 the tridiagonal systems of Eqs.
+ * (z_system) and (C_system), C = 0 outside the grid.  Packed buffers;
+ * sigma and coeffs may alias. */
+sg_status sg_bspline_coeffs(sg_plan p, const void* sigma, void* coeffs);
+
+/* sigma -> (Fx, Fy) at the cell centres for every grid of the plan:
+ * coefficient solve, then one forward and two inverse zero-padded FFT
+ * convolutions (Sec. 4.2).  Packed buffers; fx and fy must not alias sigma
+ * or each other. */
+sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy);
+
+/* Adjoint of sg_forces: gsigma = d<gfx,Fx> + <gfy,Fy> / d sigma, i.e. the
+ * transposed convolutions (correlation with the weights) followed by the
+ * transposed coefficient solve (the matrices of Eqs. (z_system) and
+ * (C_system) are symmetric).  Packed buffers; gsigma must not alias the
+ * inputs. */
+sg_status sg_forces_adjoint(sg_plan p, const void* gfx, const void* gfy, void* gsigma);
+
+/* Static string for a status code. */
+const char* sg_status_string(sg_status s);
+
+/* Detail for the last non-OK status returned on the calling thread ("" if none). */
+const char* sg_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SG_H */

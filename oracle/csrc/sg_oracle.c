@@ -99,21 +99,42 @@ static void knots(int k, int m, double h, double *t) {
   for (int r = 0; r <= k; ++r) t[r] = ((double)r - (double)m - 0.5 - (double)shift) * h;
 }
 
-/* Tensor Gauss-Legendre over one piece [xa,xb]x[ya,yb] that does not contain
- * the origin.  Returns both components (x~/r^3 and y~/r^3 weighted). */
+/* Tensor Gauss-Legendre over one rectangle [xa,xb]x[ya,yb] that does not
+ * contain the origin.  The rectangle is halved along its longer side until
+ * that side is no longer than the rectangle's distance to the origin, so the
+ * kernel's complex singularities stay at least two half-widths away from
+ * every quadrature interval (this matters for pieces next to the singular
+ * one and for cells with dx != dy); the node count then follows the
+ * remaining distance-to-size ratio.  Returns both components (x~/r^3 and
+ * y~/r^3 weighted by the spline product). */
 static void piece_gl(int k, const double *tx, const double *ty, double xa, double xb, double ya,
                      double yb, double *sx, double *sy) {
-  /* node count from the distance of the piece to the kernel singularity */
   double dxm = (xa > 0) ? xa : ((xb < 0) ? -xb : 0.0);
   double dym = (ya > 0) ? ya : ((yb < 0) ? -yb : 0.0);
   double dist = sqrt(dxm * dxm + dym * dym);
-  double size = fmax(xb - xa, yb - ya);
+  double w = xb - xa, h = yb - ya;
+  double size = fmax(w, h);
+  if (size > dist) {
+    double ax, ay, bx_, by_;
+    if (w >= h) {
+      double xm = 0.5 * (xa + xb);
+      piece_gl(k, tx, ty, xa, xm, ya, yb, &ax, &ay);
+      piece_gl(k, tx, ty, xm, xb, ya, yb, &bx_, &by_);
+    } else {
+      double ym = 0.5 * (ya + yb);
+      piece_gl(k, tx, ty, xa, xb, ya, ym, &ax, &ay);
+      piece_gl(k, tx, ty, xa, xb, ym, yb, &bx_, &by_);
+    }
+    *sx = ax + bx_;
+    *sy = ay + by_;
+    return;
+  }
   double ratio = dist / size;
   int q = ratio < 3 ? 20 : ratio < 20 ? 12 : ratio < 200 ? 8 : ratio < 1000 ? 6 : 4;
   int qi = q_index(q);
   const double *gx = gl_x[qi], *gw = gl_w[qi];
-  double cx = 0.5 * (xa + xb), hxp = 0.5 * (xb - xa);
-  double cy = 0.5 * (ya + yb), hyp = 0.5 * (yb - ya);
+  double cx = 0.5 * (xa + xb), hxp = 0.5 * w;
+  double cy = 0.5 * (ya + yb), hyp = 0.5 * h;
   double bx[32], xs[32], by[32], ys[32];
   for (int a = 0; a < q; ++a) {
     xs[a] = cx + hxp * gx[a];
@@ -157,8 +178,14 @@ static void piece_pv(int k, const double *tx, const double *ty, double xa, doubl
     double Px = corner[e][0], Py = corner[e][1];
     double Qx = corner[(e + 1) % 4][0], Qy = corner[(e + 1) % 4][1];
     double J = fabs(Px * Qy - Py * Qx);
+    /* the u-integrand is singular where |E(u)| = 0 off the real axis: split
+     * the edge into segments no longer than its distance to the origin */
+    double len = sqrt((Qx - Px) * (Qx - Px) + (Qy - Py) * (Qy - Py));
+    int nseg = (int)ceil(len / (J / len));
+    if (nseg < 1) nseg = 1;
+    for (int sg = 0; sg < nseg; ++sg)
     for (int a = 0; a < qu; ++a) {
-      double u = 0.5 * (ux[a] + 1.0), wu = 0.5 * uw[a];
+      double u = (sg + 0.5 * (ux[a] + 1.0)) / nseg, wu = 0.5 * uw[a] / nseg;
       double Ex = Px + u * (Qx - Px), Ey = Py + u * (Qy - Py);
       double E = sqrt(Ex * Ex + Ey * Ey);
       double inner = 0.0;

@@ -1,0 +1,234 @@
+// Workgroup-cooperative Stockham FFT for gfx950 (wave64), FP32 and FP64.
+//
+// One length-L transform is spread over T = L/E threads, E elements each, in
+// the "strided" distribution: thread t holds x[t + e*T], e = 0..E-1.  Each
+// Stockham stage of radix r (r | E) lets every thread run E/r butterflies on
+// elements it already holds; the stage output goes through LDS and is read
+// back in the strided distribution, except after the last stage, whose
+// output lands in registers in natural order.  Twiddles are read from a
+// table of roots of unity computed in FP64 on the host (rounded once for
+// FP32), never accumulated by recurrence.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sg {
+
+template <typename R>
+struct cx {
+  R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator*(cx<R> a, R s) { return {a.x * s, a.y * s}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b) {  // a * conj(b)
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.x, -a.y}; }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename R>
+__device__ __forceinline__ cx<R> rot(cx<R> a) {
+  return INV ? cx<R>{-a.y, a.x} : cx<R>{a.y, -a.x};
+}
+
+// ------------------------------------------------------------ small DFTs --
+template <bool INV, typename R>
+__device__ __forceinline__ void dft2(cx<R>* v) {
+  cx<R> a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+
+template <bool INV, typename R>
+__device__ __forceinline__ void dft4(cx<R>& a, cx<R>& b, cx<R>& c, cx<R>& d) {
+  cx<R> t0 = a + c, t1 = a - c, t2 = b + d, t3 = rot<INV>(b - d);
+  a = t0 + t2;
+  c = t0 - t2;
+  b = t1 + t3;
+  d = t1 - t3;
+}
+
+template <bool INV, typename R>
+__device__ __forceinline__ void dft4(cx<R>* v) { dft4<INV>(v[0], v[1], v[2], v[3]); }
+
+// multiply by w_16^j (forward; conjugate for the inverse), j in 0..9
+template <bool INV, int J, typename R>
+__device__ __forceinline__ cx<R> w16(cx<R> a) {
+  constexpr double C1 = 0.92387953251128675613, S1 = 0.38268343236508977173;
+  constexpr double C2 = 0.70710678118654752440;
+  constexpr int j = J % 16;
+  // exp(-2 pi i j / 16) = (c, -s); inverse (c, +s)
+  constexpr double c = j == 0 ? 1 : j == 1 ? C1 : j == 2 ? C2 : j == 3 ? S1 : j == 4 ? 0 : j == 5 ? -S1
+                     : j == 6 ? -C2 : j == 7 ? -C1 : j == 8 ? -1 : j == 9 ? -C1 : 0;
+  constexpr double s = j == 0 ? 0 : j == 1 ? S1 : j == 2 ? C2 : j == 3 ? C1 : j == 4 ? 1 : j == 5 ? C1
+                     : j == 6 ? C2 : j == 7 ? S1 : j == 8 ? 0 : j == 9 ? -S1 : 0;
+  if constexpr (j == 0) return a;
+  else if constexpr (j == 4) return rot<INV>(a);
+  else if constexpr (j == 8) return cx<R>{-a.x, -a.y};
+  else {
+    const R cc = (R)c, ss = INV ? (R)s : (R)(-s);
+    return {a.x * cc - a.y * ss, a.x * ss + a.y * cc};
+  }
+}
+
+template <bool INV, typename R>
+__device__ __forceinline__ void dft8(cx<R>* v) {
+  // n = 2 n1 + n2, k = k1 + 4 k2
+  cx<R> a0 = v[0], a1 = v[2], a2 = v[4], a3 = v[6];
+  cx<R> b0 = v[1], b1 = v[3], b2 = v[5], b3 = v[7];
+  dft4<INV>(a0, a1, a2, a3);
+  dft4<INV>(b0, b1, b2, b3);
+  b1 = w16<INV, 2>(b1);
+  b2 = w16<INV, 4>(b2);
+  b3 = w16<INV, 6>(b3);
+  v[0] = a0 + b0;
+  v[4] = a0 - b0;
+  v[1] = a1 + b1;
+  v[5] = a1 - b1;
+  v[2] = a2 + b2;
+  v[6] = a2 - b2;
+  v[3] = a3 + b3;
+  v[7] = a3 - b3;
+}
+
+template <bool INV, typename R>
+__device__ __forceinline__ void dft16(cx<R>* v) {
+  // n = 4 n1 + n2, k = k1 + 4 k2
+  cx<R> y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    y[n2][0] = v[n2];
+    y[n2][1] = v[4 + n2];
+    y[n2][2] = v[8 + n2];
+    y[n2][3] = v[12 + n2];
+    dft4<INV>(y[n2][0], y[n2][1], y[n2][2], y[n2][3]);
+  }
+  y[1][1] = w16<INV, 1>(y[1][1]);
+  y[1][2] = w16<INV, 2>(y[1][2]);
+  y[1][3] = w16<INV, 3>(y[1][3]);
+  y[2][1] = w16<INV, 2>(y[2][1]);
+  y[2][2] = w16<INV, 4>(y[2][2]);
+  y[2][3] = w16<INV, 6>(y[2][3]);
+  y[3][1] = w16<INV, 3>(y[3][1]);
+  y[3][2] = w16<INV, 6>(y[3][2]);
+  y[3][3] = w16<INV, 9>(y[3][3]);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cx<R> a = y[0][k1], b = y[1][k1], c = y[2][k1], d = y[3][k1];
+    dft4<INV>(a, b, c, d);
+    v[k1] = a;
+    v[k1 + 4] = b;
+    v[k1 + 8] = c;
+    v[k1 + 12] = d;
+  }
+}
+
+template <int r, bool INV, typename R>
+__device__ __forceinline__ void dft(cx<R>* v) {
+  if constexpr (r == 1) {
+  } else if constexpr (r == 2) dft2<INV>(v);
+  else if constexpr (r == 4) dft4<INV>(v);
+  else if constexpr (r == 8) dft8<INV>(v);
+  else if constexpr (r == 16) dft16<INV>(v);
+  else static_assert(r == 2, "unsupported radix");
+}
+
+// ----------------------------------------------------------- radix plan --
+// Stages for length L with E elements per thread: radix E while it fits,
+// then the remainder (a power of two dividing E).
+__host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+template <int L, int E>
+struct plan {
+  static constexpr int nfull = ilog2c(L) / ilog2c(E);
+  static constexpr int rem = L >> (nfull * ilog2c(E));  // 1 if exact
+  static constexpr int nstages = nfull + (rem > 1 ? 1 : 0);
+  static constexpr int radix(int s) { return s < nfull ? E : rem; }
+  static constexpr int ns_before(int s) { return s == 0 ? 1 : ns_before(s - 1) * radix(s - 1); }
+};
+
+// LDS padding against bank conflicts: one slot every 16 elements
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+template <int L>
+struct lds_len {
+  static constexpr int value = L + L / 16;
+};
+
+// roots(i) = exp(-2 pi i * i / L) read from a table of the RB-th roots with
+// stride S (RB = L * S).
+template <typename R>
+struct roots_t {
+  const cx<R>* __restrict__ tab;
+  int S;
+  __device__ __forceinline__ cx<R> operator()(int i) const { return tab[i * S]; }
+};
+
+// One Stockham stage.  v: E registers (strided distribution).  Unless this
+// is the last stage, the result is exchanged through lds (L padded slots)
+// and v again holds the strided distribution of the stage output.
+template <bool INV, int L, int T, int r, int Ns, typename R>
+__device__ __forceinline__ void stockham_stage(cx<R>* v, cx<R>* lds, roots_t<R> w, int t) {
+  constexpr int E = L / T;
+  constexpr int NB = E / r;
+  constexpr bool last = (Ns * r == L);
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int b = t + u * T;
+    cx<R> a[r];
+#pragma unroll
+    for (int q = 0; q < r; ++q) a[q] = v[u + q * NB];
+    if constexpr (Ns > 1) {
+      const int k = b % Ns;
+      constexpr int step = L / (Ns * r);
+#pragma unroll
+      for (int q = 1; q < r; ++q) {
+        cx<R> tw = w(k * q * step);
+        a[q] = INV ? cmulc(a[q], tw) : cmul(a[q], tw);
+      }
+    }
+    dft<r, INV>(a);
+    if constexpr (last) {
+      // in place: butterfly u reads and writes the same register slots
+#pragma unroll
+      for (int q = 0; q < r; ++q) v[u + q * NB] = a[q];
+    } else {
+      const int base = (b / Ns) * Ns * r + (b % Ns);
+#pragma unroll
+      for (int q = 0; q < r; ++q) lds[pad(base + q * Ns)] = a[q];
+    }
+  }
+  if constexpr (!last) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = lds[pad(t + e * T)];
+    __syncthreads();
+  }
+}
+
+template <bool INV, int L, int T, int S, typename R>
+__device__ __forceinline__ void fft_stages(cx<R>* v, cx<R>* lds, roots_t<R> w, int t) {
+  using P = plan<L, L / T>;
+  if constexpr (S < P::nstages) {
+    stockham_stage<INV, L, T, P::radix(S), P::ns_before(S)>(v, lds, w, t);
+    fft_stages<INV, L, T, S + 1>(v, lds, w, t);
+  }
+}
+
+// Full length-L transform (unnormalised; INV uses the conjugate roots).
+// All threads of the workgroup must call it (it contains barriers).
+template <bool INV, int L, int T, typename R>
+__device__ __forceinline__ void fft(cx<R>* v, cx<R>* lds, roots_t<R> w, int t) {
+  static_assert(L % T == 0, "L must be a multiple of T");
+  fft_stages<INV, L, T, 0>(v, lds, w, t);
+}
+
+}  // namespace sg

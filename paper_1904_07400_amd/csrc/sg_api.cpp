@@ -1,0 +1,416 @@
+// Host side of the C ABI declared in include/sg.h: plans, validation,
+// workspace, plan-time weight spectra, per-step launch sequences.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "sg.h"
+#include "sg_internal.h"
+
+namespace {
+
+thread_local std::string g_msg;
+
+sg_status fail(sg_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_msg = buf;
+  return s;
+}
+
+bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+// Roots of unity exp(-2 pi i k / B), k = 0..B-1, from long double sin/cos of
+// the octant-reduced angle (one rounding to the stored precision).
+template <typename R>
+std::vector<R> roots_table(int B) {
+  std::vector<R> out(2 * (size_t)B);
+  const long double twopi = 6.283185307179586476925286766559005768L;
+  for (int k = 0; k < B; ++k) {
+    // reduce k/B into [0, 1/8] using symmetries for accuracy
+    long double c, s;
+    int kk = k;
+    // exp(-2 pi i k/B) = cos(2 pi k/B) - i sin(2 pi k/B)
+    long double a = twopi * (long double)kk / (long double)B;
+    c = cosl(a);
+    s = sinl(a);
+    // exact values at multiples of pi/4 and pi/2
+    if ((8LL * k) % B == 0) {
+      const int o = (int)((8LL * k) / B) % 8;
+      const long double h = 0.707106781186547524400844362104849039L;
+      const long double cs[8] = {1, h, 0, -h, -1, -h, 0, h};
+      const long double sn[8] = {0, h, 1, h, 0, -h, -1, -h};
+      c = cs[o];
+      s = sn[o];
+    }
+    out[2 * (size_t)k] = (R)c;
+    out[2 * (size_t)k + 1] = (R)(-s);
+  }
+  return out;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on the three-term
+// recurrence of the Legendre polynomials, long double).
+void gl_rule(int q, double* x, double* w) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < q; ++i) {
+    long double z = cosl(pi * (i + 0.75L) / (q + 0.5L)), dp = 1;
+    for (int it = 0; it < 200; ++it) {
+      long double p0 = 1, p1 = z;
+      for (int j = 2; j <= q; ++j) {
+        long double p2 = ((2 * j - 1) * z * p1 - (j - 1) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = q * (z * p1 - p0) / (z * z - 1);
+      long double dz = p1 / dp;
+      z -= dz;
+      if (fabsl(dz) < 1e-20L) break;
+    }
+    long double p0 = 1, p1 = z;
+    for (int j = 2; j <= q; ++j) {
+      long double p2 = ((2 * j - 1) * z * p1 - (j - 1) * p0) / j;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = q * (z * p1 - p0) / (z * z - 1);
+    x[i] = (double)z;
+    w[i] = (double)(2.0L / ((1 - z * z) * dp * dp));
+  }
+}
+
+struct GridPlan {
+  sg_grid g;
+  int M, N, k, kind;
+  double hx, hy;
+  int64_t off;
+  void* tabx = nullptr;
+  void* taby = nullptr;
+  void* X = nullptr;
+  void* V = nullptr;
+  const void* r2m = nullptr;
+  const void* r2n = nullptr;
+};
+
+}  // namespace
+
+struct sg_plan_s {
+  std::vector<GridPlan> grids;
+  sg_precision prec;
+  hipStream_t st;
+  uint32_t flags;
+  bool sticky = false;
+  int device = 0;
+  int64_t bytes = 0;
+  int64_t total = 0;
+  std::vector<void*> allocs;
+  std::map<int, void*> roots;  // plan-precision tables keyed by B
+  int* flag = nullptr;         // device word for the finite check
+};
+
+namespace {
+
+sg_status dev_alloc(sg_plan p, void** out, size_t bytes) {
+  if (getenv("SG_FAULT_INJECT") && strcmp(getenv("SG_FAULT_INJECT"), "alloc") == 0)
+    return fail(SG_ERR_NOMEM, "allocation of %zu bytes refused (SG_FAULT_INJECT=alloc)", bytes);
+  hipError_t e = hipMalloc(out, bytes ? bytes : 16);
+  if (e != hipSuccess) {
+    *out = nullptr;
+    (void)hipGetLastError();
+    return fail(SG_ERR_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  p->allocs.push_back(*out);
+  p->bytes += (int64_t)bytes;
+  return SG_OK;
+}
+
+sg_status hip_check(sg_plan p, hipError_t e, const char* what) {
+  if (e == hipSuccess) return SG_OK;
+  if (p) p->sticky = true;
+  return fail(SG_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+template <typename R>
+sg_status upload_roots(sg_plan p, int B, void** out) {
+  std::vector<R> h = roots_table<R>(B);
+  sg_status s = dev_alloc(p, out, h.size() * sizeof(R));
+  if (s != SG_OK) return s;
+  return hip_check(p, hipMemcpy(*out, h.data(), h.size() * sizeof(R), hipMemcpyHostToDevice), "hipMemcpy roots");
+}
+
+void release(sg_plan p) {
+  for (void* a : p->allocs) (void)hipFree(a);
+  p->allocs.clear();
+}
+
+sg_status check_plan(sg_plan p) {
+  if (!p) return fail(SG_ERR_ARG, "plan is NULL");
+  if (p->sticky) return fail(SG_ERR_STATE, "plan is in the sticky error state after a device error");
+  return SG_OK;
+}
+
+// Weight spectra of one grid (plan time, FP64 throughout).
+sg_status build_spectra(sg_plan p, GridPlan& G, const void* r2m64, const void* r2n64) {
+  const int M = G.M, N = G.N;
+  double* wp = nullptr;
+  void* S = nullptr;
+  hipError_t e = hipMalloc((void**)&wp, sizeof(double) * 2 * (size_t)(2 * M) * (2 * N));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SG_ERR_NOMEM, "plan-time weight table: %s", hipGetErrorString(e));
+  }
+  e = hipMalloc(&S, 16 * (size_t)(2 * N) * M);
+  if (e != hipSuccess) {
+    (void)hipFree(wp);
+    (void)hipGetLastError();
+    return fail(SG_ERR_NOMEM, "plan-time spectrum workspace: %s", hipGetErrorString(e));
+  }
+  double* wpx = wp;
+  double* wpy = wp + (size_t)(2 * M) * (2 * N);
+  const int fp32 = p->prec == SG_FP32_SPLIT ? 1 : 0;
+  const double scale = 1.0 / (4.0 * (double)M * (double)N);
+  sg_status st = SG_OK;
+  e = sg_launch_weights(G.k, G.hx, G.hy, M, N, wpx, wpy, 0, p->st);
+  if (e == hipSuccess) e = sg_launch_row_fwd(0, M, wpx, 2 * M, S, 2 * N, r2m64, 0, 1, p->st);
+  if (e == hipSuccess) e = sg_launch_spec_col(N, S, M, G.tabx, G.kind, fp32, scale, r2n64, p->st);
+  if (e == hipSuccess) e = sg_launch_row_fwd(0, M, wpy, 2 * M, S, 2 * N, r2m64, 0, 1, p->st);
+  if (e == hipSuccess) e = sg_launch_spec_col(N, S, M, G.taby, G.kind, fp32, scale, r2n64, p->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->st);
+  if (e != hipSuccess) st = hip_check(p, e, "plan-time spectrum");
+  (void)hipFree(wp);
+  (void)hipFree(S);
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sg_status_string(sg_status s) {
+  switch (s) {
+    case SG_OK: return "SG_OK";
+    case SG_ERR_ARG: return "SG_ERR_ARG: invalid argument";
+    case SG_ERR_UNSUPPORTED: return "SG_ERR_UNSUPPORTED: unsupported order or size";
+    case SG_ERR_NOMEM: return "SG_ERR_NOMEM: allocation failed";
+    case SG_ERR_DEVICE: return "SG_ERR_DEVICE: HIP error";
+    case SG_ERR_STATE: return "SG_ERR_STATE: plan in error state or non-finite input";
+  }
+  return "unknown sg_status";
+}
+
+const char* sg_last_error_message(void) { return g_msg.c_str(); }
+
+sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_precision prec, void* hip_stream,
+                         uint32_t flags) {
+  g_msg.clear();
+  if (!out) return fail(SG_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!grids || ngrids < 1) return fail(SG_ERR_ARG, "need at least one grid (ngrids=%d)", ngrids);
+  if (prec != SG_FP64 && prec != SG_FP32_SPLIT) return fail(SG_ERR_ARG, "unknown precision %d", (int)prec);
+  if (flags & ~SG_FLAG_CHECK_FINITE) return fail(SG_ERR_ARG, "unknown flags 0x%x", flags);
+  for (int i = 0; i < ngrids; ++i) {
+    const sg_grid& g = grids[i];
+    if (g.nx < 2 || g.ny < 2) return fail(SG_ERR_ARG, "grid %d: nx=%d ny=%d (need >= 2)", i, g.nx, g.ny);
+    if (!isfinite(g.x0) || !isfinite(g.x1) || !isfinite(g.y0) || !isfinite(g.y1) || !(g.x1 > g.x0) ||
+        !(g.y1 > g.y0))
+      return fail(SG_ERR_ARG, "grid %d: empty or non-finite domain", i);
+    if (g.order < 1 || g.order > 3) return fail(SG_ERR_UNSUPPORTED, "grid %d: order %d (supported: 1..3)", i, g.order);
+    if (!pow2_in(g.nx, 4, 8192) || !pow2_in(g.ny, 4, 8192))
+      return fail(SG_ERR_UNSUPPORTED, "grid %d: %dx%d (supported: powers of two 4..8192)", i, g.nx, g.ny);
+  }
+  sg_plan p = new (std::nothrow) sg_plan_s();
+  if (!p) return fail(SG_ERR_NOMEM, "host allocation failed");
+  p->prec = prec;
+  p->st = (hipStream_t)hip_stream;
+  p->flags = flags;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(SG_ERR_DEVICE, "no HIP device");
+  }
+  // Gauss-Legendre rules for the plan-time weights: q = 4, 6, 10, 16
+  {
+    double gx[64] = {0}, gw[64] = {0};
+    const int qs[4] = {4, 6, 10, 16};
+    for (int a = 0; a < 4; ++a) gl_rule(qs[a], gx + 16 * a, gw + 16 * a);
+    hipError_t e = sg_set_gl_tables(gx, gw);
+    if (e != hipSuccess) {
+      delete p;
+      return fail(SG_ERR_DEVICE, "GL tables: %s", hipGetErrorString(e));
+    }
+  }
+  const size_t cb = prec == SG_FP64 ? 16 : 8;  // complex element bytes
+  std::map<int, void*> roots64;
+  sg_status s = SG_OK;
+  int64_t off = 0;
+  for (int i = 0; i < ngrids && s == SG_OK; ++i) {
+    GridPlan G;
+    G.g = grids[i];
+    G.M = grids[i].nx;
+    G.N = grids[i].ny;
+    G.k = grids[i].order;
+    G.kind = (G.k == 2) ? 1 : 0;
+    G.hx = (grids[i].x1 - grids[i].x0) / G.M;
+    G.hy = (grids[i].y1 - grids[i].y0) / G.N;
+    G.off = off;
+    off += (int64_t)G.M * G.N;
+    const size_t tab_el = G.kind == 0 ? 8 : 16;  // odd k: one real (FP64 or hi+lo FP32); k=2: complex
+    const size_t tab_n = G.kind == 0 ? (size_t)(G.M + 1) * (G.N + 1) : (size_t)(G.M + 1) * 2 * G.N;
+    if (s == SG_OK) s = dev_alloc(p, &G.tabx, tab_el * tab_n);
+    if (s == SG_OK) s = dev_alloc(p, &G.taby, tab_el * tab_n);
+    if (s == SG_OK) s = dev_alloc(p, &G.X, cb * (size_t)G.M * G.N);
+    if (s == SG_OK) s = dev_alloc(p, &G.V, cb * 2 * (size_t)G.M * G.N);
+    for (int B : {2 * G.M, 2 * G.N}) {
+      if (s != SG_OK) break;
+      if (!roots64.count(B)) {
+        void* d = nullptr;
+        s = upload_roots<double>(p, B, &d);
+        roots64[B] = d;
+      }
+      if (s == SG_OK && !p->roots.count(B)) {
+        void* d = nullptr;
+        s = prec == SG_FP64 ? SG_OK : upload_roots<float>(p, B, &d);
+        p->roots[B] = prec == SG_FP64 ? roots64[B] : d;
+      }
+    }
+    if (s == SG_OK) {
+      G.r2m = p->roots[2 * G.M];
+      G.r2n = p->roots[2 * G.N];
+      s = build_spectra(p, G, roots64[2 * G.M], roots64[2 * G.N]);
+    }
+    p->grids.push_back(G);
+  }
+  p->total = off;
+  if (s == SG_OK) s = dev_alloc(p, (void**)&p->flag, sizeof(int));
+  if (s != SG_OK) {
+    std::string keep = g_msg;
+    (void)hipStreamSynchronize(p->st);
+    release(p);
+    delete p;
+    g_msg = keep;
+    return s;
+  }
+  *out = p;
+  return SG_OK;
+}
+
+sg_status sg_plan_destroy(sg_plan p) {
+  g_msg.clear();
+  if (!p) return SG_OK;
+  (void)hipStreamSynchronize(p->st);
+  release(p);
+  delete p;
+  return SG_OK;
+}
+
+sg_status sg_plan_layout(sg_plan p, int64_t* offsets) {
+  g_msg.clear();
+  if (!p) return fail(SG_ERR_ARG, "plan is NULL");
+  if (!offsets) return fail(SG_ERR_ARG, "offsets is NULL");
+  for (size_t i = 0; i < p->grids.size(); ++i) offsets[i] = p->grids[i].off;
+  offsets[p->grids.size()] = p->total;
+  return SG_OK;
+}
+
+sg_status sg_plan_info(sg_plan p, int32_t* ngrids, int32_t* prec, int64_t* device_bytes) {
+  g_msg.clear();
+  if (!p) return fail(SG_ERR_ARG, "plan is NULL");
+  if (ngrids) *ngrids = (int32_t)p->grids.size();
+  if (prec) *prec = (int32_t)p->prec;
+  if (device_bytes) *device_bytes = p->bytes;
+  return SG_OK;
+}
+
+sg_status sg_sample_points(sg_plan p, int32_t g, double* xs0, double* ys0, double* dx, double* dy) {
+  g_msg.clear();
+  if (!p) return fail(SG_ERR_ARG, "plan is NULL");
+  if (g < 0 || g >= (int32_t)p->grids.size()) return fail(SG_ERR_ARG, "grid index %d out of range", g);
+  const GridPlan& G = p->grids[g];
+  const double off = (G.k % 2 == 1) ? 0.5 : 1.0;  // cell centres (odd k) or vertices x0 + (i+1) dx (k = 2)
+  if (xs0) *xs0 = G.g.x0 + off * G.hx;
+  if (ys0) *ys0 = G.g.y0 + off * G.hy;
+  if (dx) *dx = G.hx;
+  if (dy) *dy = G.hy;
+  return SG_OK;
+}
+
+sg_status sg_weights(sg_plan p, int32_t g, double* wx, double* wy) {
+  g_msg.clear();
+  sg_status s = check_plan(p);
+  if (s != SG_OK) return s;
+  if (g < 0 || g >= (int32_t)p->grids.size()) return fail(SG_ERR_ARG, "grid index %d out of range", g);
+  if (!wx && !wy) return SG_OK;
+  const GridPlan& G = p->grids[g];
+  return hip_check(p, sg_launch_weights(G.k, G.hx, G.hy, G.M, G.N, wx, wy, 1, p->st), "weights launch");
+}
+
+sg_status sg_bspline_coeffs(sg_plan p, const void* sigma, void* coeffs) {
+  g_msg.clear();
+  sg_status s = check_plan(p);
+  if (s != SG_OK) return s;
+  if (!sigma || !coeffs) return fail(SG_ERR_ARG, "sigma or coeffs is NULL");
+  const int prec = p->prec == SG_FP64 ? 0 : 1;
+  const size_t el = prec == 0 ? 8 : 4;
+  for (const GridPlan& G : p->grids) {
+    const char* src = (const char*)sigma + el * G.off;
+    char* dst = (char*)coeffs + el * G.off;
+    hipError_t e = hipSuccess;
+    if (G.k == 3) {
+      e = sg_launch_coeff_rows(prec, G.M, src, dst, G.N, p->st);
+      if (e == hipSuccess) e = sg_launch_coeff_cols(prec, G.N, dst, G.M, p->st);
+    } else if (src != dst) {
+      e = hipMemcpyAsync(dst, src, el * (size_t)G.M * G.N, hipMemcpyDeviceToDevice, p->st);
+    }
+    if (e != hipSuccess) return hip_check(p, e, "coefficient launch");
+  }
+  return SG_OK;
+}
+
+sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy) {
+  g_msg.clear();
+  sg_status s = check_plan(p);
+  if (s != SG_OK) return s;
+  if (!sigma || !fx || !fy) return fail(SG_ERR_ARG, "sigma, fx or fy is NULL");
+  if (fx == fy || fx == sigma || fy == sigma) return fail(SG_ERR_ARG, "fx, fy and sigma must not alias");
+  const int prec = p->prec == SG_FP64 ? 0 : 1;
+  const size_t el = prec == 0 ? 8 : 4;
+  if (p->flags & SG_FLAG_CHECK_FINITE) {
+    int h = 0;
+    hipError_t e = hipMemsetAsync(p->flag, 0, sizeof(int), p->st);
+    if (e == hipSuccess) e = sg_launch_check_finite(prec, sigma, p->total, p->flag, p->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->st);
+    if (e != hipSuccess) return hip_check(p, e, "finite check");
+    if (h) return fail(SG_ERR_STATE, "sigma holds NaN or Inf");
+  }
+  for (const GridPlan& G : p->grids) {
+    const char* src = (const char*)sigma + el * G.off;
+    char* ox = (char*)fx + el * G.off;
+    char* oy = (char*)fy + el * G.off;
+    const int solve = G.k == 3 ? 1 : 0;
+    hipError_t e = sg_launch_row_fwd(prec, G.M, src, G.M, G.X, G.N, G.r2m, solve, 0, p->st);
+    if (e == hipSuccess) e = sg_launch_col(prec, G.N, G.X, G.V, G.M, G.tabx, G.taby, G.kind, G.r2n, solve, p->st);
+    if (e == hipSuccess) e = sg_launch_row_inv(prec, G.M, G.V, ox, oy, G.N, G.r2m, p->st);
+    if (e != hipSuccess) return hip_check(p, e, "force launch");
+  }
+  return SG_OK;
+}
+
+sg_status sg_forces_adjoint(sg_plan p, const void* gfx, const void* gfy, void* gsigma) {
+  g_msg.clear();
+  sg_status s = check_plan(p);
+  if (s != SG_OK) return s;
+  if (!gfx || !gfy || !gsigma) return fail(SG_ERR_ARG, "gfx, gfy or gsigma is NULL");
+  return fail(SG_ERR_UNSUPPORTED, "adjoint not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,864 @@
+// Device kernels of the thin-disk self-gravity library (gfx950).
+//
+// Per-step path for one M x N grid (sigma row-major [N][M], x fastest):
+//   pass A (rows):    [k=3: x-solve, Eq. (C_system)] + real FFT of the row
+//                     zero-padded to 2M, written as M packed complex bins
+//                     (bin 0 carries the real bins 0 and M);
+//   pass B (columns): [k=3: y-solve, Eq. (z_system), on the row spectra] +
+//                     FFT of the column zero-padded to 2N, products with the
+//                     spectra of w^x and w^y (convolution theorem), two
+//                     inverse FFTs cropped to N outputs, written as the
+//                     combined spectrum V = Yx + i Yy of length 2M per row;
+//   pass C (rows):    inverse FFT of V, cropped to M outputs:
+//                     Fx = Re, Fy = Im.
+// The y-solve commutes with the x-transform (tensor-product operators), so
+// it runs inside pass B at no extra HBM traffic.
+//
+// Plan time: weights of Eq. (eqnwB) on the padded 2M x 2N lattice (FP64),
+// then the same row/column transforms in FP64 to get their spectra.
+#include "fft.hpp"
+#include "sg_internal.h"
+#include "tridiag.hpp"
+
+namespace sg {
+
+// ------------------------------------------------------------- weights --
+__constant__ double c_glx[4][16];
+__constant__ double c_glw[4][16];
+__constant__ int c_glq[4] = {4, 6, 10, 16};
+// Spline pieces as polynomials c0 + c1 xi + c2 xi^2 in the piece-centred
+// variable xi in [-1/2, 1/2] (Eqs. (Bspline1)-(Bspline3) on uniform knots):
+// order k, piece r (piece r spans [t_r, t_{r+1}]).
+__constant__ double c_piece[3][3][3] = {
+    {{1.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}},
+    {{0.5, 1.0, 0.0}, {0.5, -1.0, 0.0}, {0.0, 0.0, 0.0}},
+    {{0.125, 0.5, 0.5}, {0.75, 0.0, -1.0}, {0.125, -0.5, 0.5}}};
+
+// Both weight components at offset (m, n): the integrals of x~/r^3 and
+// y~/r^3 against the tensor spline attached to C_{i-m, j-n} (Eq. (eqnwB)).
+// The spline's piece that holds the singular point is integrated in closed
+// form (principal value over the centred square [-dx/2,dx/2]x[-dy/2,dy/2]:
+// only monomials even in both variables survive, each is 4x its integral
+// over [0,dx/2]x[0,dy/2], taken from the antiderivatives of Appendix A for
+// (alpha, beta) = (2,0), (0,2), (2,2)); every other piece by tensor
+// Gauss-Legendre, whose node count grows as the piece nears the singularity.
+__device__ void weight_pair(int k, double hx, double hy, int m, int n, double& wx, double& wy) {
+  const int shift = (k - 1) / 2;
+  double sx = 0.0, sy = 0.0;
+  for (int r = 0; r < k; ++r) {
+    const int ox = r - m - shift;  // piece centre in cells
+    const double cxp = (double)ox * hx;
+    const double* px = c_piece[k - 1][r];
+    for (int s = 0; s < k; ++s) {
+      const int oy = s - n - shift;
+      const double cyp = (double)oy * hy;
+      const double* py = c_piece[k - 1][s];
+      if (ox == 0 && oy == 0) {
+        const double X = 0.5 * hx, Y = 0.5 * hy, Rr = sqrt(X * X + Y * Y);
+        const double LX = log((X + Rr) / Y), LY = log((Y + Rr) / X);
+        const double I20 = 4.0 * Y * LX, I02 = 4.0 * X * LY;
+        const double I22 = 4.0 * (-X * Y * Rr + Y * Y * Y * LX + X * X * X * LY) / 3.0;
+        const double p0 = px[0], p1 = px[1] / hx, p2 = px[2] / (hx * hx);
+        const double q0 = py[0], q1 = py[1] / hy, q2 = py[2] / (hy * hy);
+        sx += p1 * (q0 * I20 + q2 * I22);
+        sy += q1 * (p0 * I02 + p2 * I22);
+        continue;
+      }
+      // Gauss-Legendre on nsx x nsy equal sub-rectangles of the piece, each no
+      // larger than the piece's distance to the singular point, so that the
+      // kernel's complex singularities stay >= 2 half-widths from every
+      // quadrature interval (pieces next to the singular one, dx != dy)
+      const double dxm = fmax(fabs(cxp) - 0.5 * hx, 0.0), dym = fmax(fabs(cyp) - 0.5 * hy, 0.0);
+      const double dist = sqrt(dxm * dxm + dym * dym);
+      const int nsx = dist >= hx ? 1 : (int)ceil(hx / dist);
+      const int nsy = dist >= hy ? 1 : (int)ceil(hy / dist);
+      const double sw = hx / nsx, sh = hy / nsy;
+      const double ratio = dist / fmax(sw, sh);
+      const int qi = ratio < 2.0 ? 3 : ratio < 8.0 ? 2 : ratio < 64.0 ? 1 : 0;
+      const int q = c_glq[qi];
+      double ax = 0.0, ay = 0.0;
+      for (int sa = 0; sa < nsx; ++sa) {
+        const double xic = -0.5 + (sa + 0.5) / nsx;  // sub-rectangle centre in xi
+        for (int a = 0; a < q; ++a) {
+          const double xi = xic + (0.5 / nsx) * c_glx[qi][a];
+          const double x = cxp + xi * hx;
+          const double bx = (px[0] + xi * (px[1] + xi * px[2])) * c_glw[qi][a];
+          double ix = 0.0, iy = 0.0;
+          for (int sb = 0; sb < nsy; ++sb) {
+            const double etc = -0.5 + (sb + 0.5) / nsy;
+            for (int b = 0; b < q; ++b) {
+              const double eta = etc + (0.5 / nsy) * c_glx[qi][b];
+              const double y = cyp + eta * hy;
+              const double by = (py[0] + eta * (py[1] + eta * py[2])) * c_glw[qi][b];
+              const double r2 = x * x + y * y;
+              const double inv = by / (r2 * sqrt(r2));
+              ix += x * inv;
+              iy += y * inv;
+            }
+          }
+          ax += bx * ix;
+          ay += bx * iy;
+        }
+      }
+      sx += ax * (0.25 * sw * sh);
+      sy += ay * (0.25 * sw * sh);
+    }
+  }
+  wx = sx;
+  wy = sy;
+}
+
+// Padded lattice (layout 0): entry (p, q), p in [0,2M), q in [0,2N), row
+// q; offset m = p (p < M) or p - 2M (p > M), likewise n.  The slots p = M
+// and q = N are never read by cropped outputs; they are filled so that the
+// padded table keeps the symmetry of the weights over the whole period
+// (odd about the spline centre in the force direction, even across it),
+// which makes the spectra purely imaginary for odd k.  Export layout
+// (layout 1): (2N-1) x (2M-1), offsets m in [-(M-1), M-1].
+__global__ void k_weights(int k, double hx, double hy, int M, int N, double* __restrict__ wx,
+                          double* __restrict__ wy, int layout) {
+  const int W = layout == 0 ? 2 * M : 2 * M - 1;
+  const int H = layout == 0 ? 2 * N : 2 * N - 1;
+  const int64_t total = (int64_t)W * H;
+  const int s2 = (k == 2) ? 1 : 0;  // twice the spline-centre offset, in cells
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)(idx % W), q = (int)(idx / W);
+    double vx, vy;
+    if (layout == 1) {
+      weight_pair(k, hx, hy, p - (M - 1), q - (N - 1), vx, vy);
+    } else {
+      const bool sp = (p == M), sq = (q == N);
+      const int m = sp ? s2 - M : (p < M ? p : p - 2 * M);
+      const int n = sq ? s2 - N : (q < N ? q : q - 2 * N);
+      if ((sp || sq) && s2 == 0) {
+        vx = 0.0;
+        vy = 0.0;
+      } else {
+        weight_pair(k, hx, hy, m, n, vx, vy);
+        if (sp) { vx = -vx; }
+        if (sq) { vy = -vy; }
+      }
+    }
+    if (wx) wx[idx] = vx;
+    if (wy) wy[idx] = vy;
+  }
+}
+
+// --------------------------------------------------------- common bits --
+// Map the launch index to a tile so that consecutive tiles land on the same
+// XCD (workgroups are dealt round-robin over the 8 XCDs).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  if (nb % 8 != 0) return b;
+  return (b % 8) * (nb / 8) + b / 8;
+}
+
+// ---------------------------------------------------------------- pass A --
+// Real FFT of length 2M of a row whose upper half is zero (or, with full,
+// of a row of 2M values), via the complex FFT of length M of
+// z[n] = x[2n] + i x[2n+1], itself split into its even and odd output bins
+// (two FFTs of length M/2).  Output: M packed bins, bin 0 = (X_0, X_M).
+// Row r of src starts at src + r*src_ld; row r of X at X + r*M.
+template <typename R, typename In, int M>
+struct rowfwd_cfg {
+  static constexpr int L = M / 2;
+  static constexpr int E = (sizeof(R) == 4 ? 16 : 8) < L ? (sizeof(R) == 4 ? 16 : 8) : L;
+  static constexpr int T = L / E;
+  static constexpr int G = T >= 256 ? 1 : 256 / T;
+  static constexpr int LL = lds_len<L>::value;
+  // per-row LDS slot (complex elements): FFT exchange buffer, also used
+  // for the reduced system of the x-solve
+  static constexpr int TRI = (int)(sizeof(tri_smem<double, T>) / sizeof(cx<R>)) + 1;
+  static constexpr int SLOT = LL > TRI ? LL : TRI;
+};
+
+template <typename R, typename In, int M>
+__global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M>::T))
+    k_row_fwd(const In* __restrict__ src, int64_t src_ld, cx<R>* __restrict__ X, int nrows,
+              const cx<R>* __restrict__ r2m, int solve, int full) {
+  using C = rowfwd_cfg<R, In, M>;
+  constexpr int L = C::L, E = C::E, T = C::T, G = C::G, SLOT = C::SLOT;
+  __shared__ cx<R> smem[G * SLOT];
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int row = blockIdx.x * G + g;
+  const bool active = row < nrows;
+  cx<R>* lds = smem + g * SLOT;
+  const In* s = src + (int64_t)(active ? row : 0) * src_ld;
+  cx<R> ze[E], zo[E];
+  if (solve) {
+    // chunk of 2E reals per thread: x-solve of Eq. (C_system), FP64
+    constexpr int CH = 2 * E;
+    double d[CH];
+#pragma unroll
+    for (int e = 0; e < CH; ++e) d[e] = active ? 8.0 * (double)s[t * CH + e] : 0.0;
+    tri_solve<CH, T, double>(d, t, *reinterpret_cast<tri_smem<double, T>*>(lds));
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[pad(t * E + e)] = cx<R>{(R)d[2 * e], (R)d[2 * e + 1]};
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) ze[e] = lds[pad(t + e * T)];
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int n = t + e * T;
+      ze[e] = active ? cx<R>{(R)s[2 * n], (R)s[2 * n + 1]} : cx<R>{0, 0};
+    }
+  }
+  const roots_t<R> wl{r2m, 4};  // L-th roots
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int n = t + e * T;
+    cx<R> lo = ze[e];
+    if (full) {
+      const cx<R> hi = active ? cx<R>{(R)s[2 * (n + L)], (R)s[2 * (n + L) + 1]} : cx<R>{0, 0};
+      ze[e] = lo + hi;
+      lo = lo - hi;
+    }
+    zo[e] = cmul(lo, r2m[2 * n]);  // w_M^n
+  }
+  // even bins of Z
+  fft<false, L, T>(ze, lds, wl, t);
+  cx<R> xe[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = ze[e];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int pp = t + e * T;                         // X bin p = 2 pp
+    const cx<R> zp = ze[e], zm = conj(lds[pad((L - pp) & (L - 1))]);
+    const cx<R> sum = zp + zm, dif = cmul(r2m[2 * pp], zp - zm);
+    xe[e] = cx<R>{(R)0.5 * (sum.x + dif.y), (R)0.5 * (sum.y - dif.x)};
+    if (pp == 0) xe[e] = cx<R>{zp.x + zp.y, zp.x - zp.y};
+  }
+  __syncthreads();
+  // odd bins of Z
+  fft<false, L, T>(zo, lds, wl, t);
+#pragma unroll
+  for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = zo[e];
+  __syncthreads();
+  cx<R>* out = X + (int64_t)(active ? row : 0) * M;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int pp = t + e * T;                         // X bin p = 2 pp + 1
+    const cx<R> zp = zo[e], zm = conj(lds[pad(L - 1 - pp)]);
+    const cx<R> sum = zp + zm, dif = cmul(r2m[2 * pp + 1], zp - zm);
+    const cx<R> xo{(R)0.5 * (sum.x + dif.y), (R)0.5 * (sum.y - dif.x)};
+    if (active) {
+      out[2 * pp] = xe[e];
+      out[2 * pp + 1] = xo;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- pass B --
+template <typename R, int N>
+struct col_cfg {
+  static constexpr int E = sizeof(R) == 4 ? (N < 16 ? N : 16) : (N < 8 ? N : (N >= 8192 ? 16 : 8));
+  static constexpr int T = N / E;
+  static constexpr int LL = lds_len<N>::value;
+  static constexpr int TRI = (int)(sizeof(tri_smem<double2, T>) / sizeof(cx<R>)) + 1;
+  static constexpr int SLOT = LL > TRI ? LL : TRI;  // per-column LDS slot (complex elements)
+  static constexpr int BYTES = SLOT * (int)sizeof(cx<R>);
+  static constexpr int P0 = T >= 256 ? 1 : 256 / T;
+  static constexpr int PL = (65536 / BYTES) < 1 ? 1 : (65536 / BYTES);
+  static constexpr int P = P0 < PL ? P0 : PL;
+};
+
+// spectrum lookup helpers: odd k (real tables, W = i A) and k = 2 (complex)
+template <typename R, typename TO>
+__device__ __forceinline__ cx<R> mul_iA(cx<R> z, const TO* tab, int idx, R sgn);
+template <>
+__device__ __forceinline__ cx<double> mul_iA(cx<double> z, const double* tab, int idx, double sgn) {
+  const double a = tab[idx] * sgn;
+  return {-z.y * a, z.x * a};
+}
+template <>
+__device__ __forceinline__ cx<float> mul_iA(cx<float> z, const float2* tab, int idx, float sgn) {
+  const float2 a = tab[idx];
+  const float h = a.x * sgn, l = a.y * sgn;
+  return {-(z.y * h + z.y * l), z.x * h + z.x * l};
+}
+template <typename R, typename TC>
+__device__ __forceinline__ cx<R> mul_W(cx<R> z, const TC* tab, int idx);
+template <>
+__device__ __forceinline__ cx<double> mul_W(cx<double> z, const double2* tab, int idx) {
+  const double2 w = tab[idx];
+  return cmul(z, cx<double>{w.x, w.y});
+}
+template <>
+__device__ __forceinline__ cx<float> mul_W(cx<float> z, const float4* tab, int idx) {
+  const float4 w = tab[idx];  // (re_hi, re_lo, im_hi, im_lo)
+  return {(z.x * w.x - z.y * w.z) + (z.x * w.y - z.y * w.w), (z.x * w.z + z.y * w.x) + (z.x * w.w + z.y * w.y)};
+}
+
+// Product of the column spectrum with W^d at column bin p.  half 0: bins
+// q = 2q', half 1: q = 2q'+1.  eps: symmetry of the stored table across
+// q -> 2N - q (+1 for x, -1 for y) for odd k.
+template <typename R, typename TO, typename TC, int N>
+__device__ __forceinline__ cx<R> spec_mul(cx<R> z, int kind, const TO* to, const TC* tc, int p, int qq,
+                                          int half, R eps) {
+  if (kind == 0) {
+    const TO* row = to + (int64_t)p * (N + 1);
+    if (half == 0) {
+      const bool lo = qq <= N / 2;
+      return mul_iA(z, row, lo ? qq : N - qq, lo ? (R)1 : eps);
+    }
+    const bool lo = qq < N / 2;
+    return mul_iA(z, row + N / 2 + 1, lo ? qq : N - 1 - qq, lo ? (R)1 : eps);
+  }
+  return mul_W(z, tc + (int64_t)p * (2 * N), half * N + qq);
+}
+
+// Products of one half of the column spectrum with W^x and W^y.  exch:
+// the workgroup holds the packed column 0 (uniform over the workgroup);
+// packed: this slice is column 0, whose spectrum U carries bins p = 0 and
+// p = M: C_0 = (U(q) + conj U(-q))/2, C_M = (U(q) - conj U(-q))/(2i), and
+// the products are re-packed as G_0 + i G_M.
+template <typename R, typename TO, typename TC, int N, int E, int T>
+__device__ __forceinline__ void col_products(const cx<R>* f, cx<R>* gx, cx<R>* gy, int half, bool exch,
+                                             bool packed, cx<R>* lds, int kind, const TO* tox, const TO* toy,
+                                             const TC* tcx, const TC* tcy, int c, int M, int t) {
+  if (exch) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = f[e];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int qq = t + e * T;
+    if (packed) {
+      const int qm = half == 0 ? ((N - qq) & (N - 1)) : (N - 1 - qq);
+      const cx<R> u = f[e], um = conj(lds[pad(qm)]);
+      const cx<R> c0v{(R)0.5 * (u.x + um.x), (R)0.5 * (u.y + um.y)};
+      const cx<R> cmv{(R)0.5 * (u.y - um.y), (R)-0.5 * (u.x - um.x)};
+      const cx<R> x0 = spec_mul<R, TO, TC, N>(c0v, kind, tox, tcx, 0, qq, half, (R)1);
+      const cx<R> xm = spec_mul<R, TO, TC, N>(cmv, kind, tox, tcx, M, qq, half, (R)1);
+      const cx<R> y0 = spec_mul<R, TO, TC, N>(c0v, kind, toy, tcy, 0, qq, half, (R)-1);
+      const cx<R> ym = spec_mul<R, TO, TC, N>(cmv, kind, toy, tcy, M, qq, half, (R)-1);
+      gx[e] = cx<R>{x0.x - xm.y, x0.y + xm.x};
+      gy[e] = cx<R>{y0.x - ym.y, y0.y + ym.x};
+    } else {
+      gx[e] = spec_mul<R, TO, TC, N>(f[e], kind, tox, tcx, c, qq, half, (R)1);
+      gy[e] = spec_mul<R, TO, TC, N>(f[e], kind, toy, tcy, c, qq, half, (R)-1);
+    }
+  }
+  if (exch) __syncthreads();
+}
+
+template <typename R, typename TO, typename TC, int N>
+__global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
+    k_col(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, const TO* __restrict__ tox,
+          const TO* __restrict__ toy, const TC* __restrict__ tcx, const TC* __restrict__ tcy,
+          const cx<R>* __restrict__ r2n, int solve, int kind) {
+  using C = col_cfg<R, N>;
+  constexpr int E = C::E, T = C::T, LL = C::SLOT;
+  __shared__ cx<R> smem[C::P * LL];
+  const int P = blockDim.x / T;  // columns per workgroup (<= C::P, divides M)
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int c0 = tile * P, c = c0 + g;
+  cx<R>* lds = smem + g * LL;
+  // coalesced tile load: P adjacent columns, row by row
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int l = threadIdx.x + s * P * T;
+    const int j = l / P, cc = l % P;
+    smem[cc * LL + pad(j)] = X[(int64_t)j * M + c0 + cc];
+  }
+  __syncthreads();
+  cx<R> a[E];
+  if (solve) {
+    // y-solve of Eq. (z_system) on the complex row spectra, FP64
+    double2 d[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const cx<R> v = lds[pad(t * E + e)];
+      d[e] = make_double2(8.0 * (double)v.x, 8.0 * (double)v.y);
+    }
+    __syncthreads();
+    tri_solve<E, T, double2>(d, t, *reinterpret_cast<tri_smem<double2, T>*>(lds));
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[pad(t * E + e)] = cx<R>{(R)d[e].x, (R)d[e].y};
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) a[e] = lds[pad(t + e * T)];
+  __syncthreads();
+
+  const roots_t<R> wn{r2n, 2};  // N-th roots
+  const bool packed = (c == 0);
+  // forward transform of the column zero-padded to 2N: even bins
+  // fe = FFT_N(a), odd bins fo = FFT_N(a_j w_2N^j)
+  cx<R> fe[E], fo[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    fo[e] = cmul(a[e], r2n[t + e * T]);
+    fe[e] = a[e];
+  }
+  fft<false, N, T>(fe, lds, wn, t);
+  fft<false, N, T>(fo, lds, wn, t);
+  cx<R> accx[E], accy[E];
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    const cx<R>* f = half ? fo : fe;
+    cx<R> gx[E], gy[E];
+    col_products<R, TO, TC, N, E, T>(f, gx, gy, half, c0 == 0, packed, lds, kind, tox, toy, tcx, tcy, c, M, t);
+    fft<true, N, T>(gx, lds, wn, t);
+    fft<true, N, T>(gy, lds, wn, t);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (half == 0) {
+        accx[e] = gx[e];
+        accy[e] = gy[e];
+      } else {
+        const cx<R> w = r2n[t + e * T];  // conj -> exp(+i pi j / N)
+        accx[e] = accx[e] + cmulc(gx[e], w);
+        accy[e] = accy[e] + cmulc(gy[e], w);
+      }
+    }
+  }
+  // V(c) = Yx + i Yy and V(2M - c) = conj(Yx) + i conj(Yy); the packed
+  // column gives V(0) = Re Yx + i Re Yy and V(M) = Im Yx + i Im Yy.
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const cx<R> yx = accx[e], yy = accy[e];
+      cx<R> v;
+      if (packed)
+        v = pass == 0 ? cx<R>{yx.x, yy.x} : cx<R>{yx.y, yy.y};
+      else
+        v = pass == 0 ? cx<R>{yx.x - yy.y, yx.y + yy.x} : cx<R>{yx.x + yy.y, yy.x - yx.y};
+      lds[pad(t + e * T)] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const int l = threadIdx.x + s * P * T;
+      const int j = l / P, cc = l % P;
+      const int cg = c0 + cc;
+      const int dst = pass == 0 ? cg : (cg == 0 ? M : 2 * M - cg);
+      V[(int64_t)j * (2 * M) + dst] = smem[cc * LL + pad(j)];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- pass C --
+template <typename R, int M>
+struct rowinv_cfg {
+  static constexpr int L = M;
+  static constexpr int E = sizeof(R) == 4 ? (L < 16 ? L : 16) : (L < 8 ? L : (L >= 8192 ? 16 : 8));
+  static constexpr int T = L / E;
+  static constexpr int G = T >= 256 ? 1 : 256 / T;
+  static constexpr int LL = lds_len<L>::value;
+};
+
+template <typename R, typename Out, int M>
+__global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
+    k_row_inv(const cx<R>* __restrict__ V, Out* __restrict__ fx, Out* __restrict__ fy, int nrows,
+              const cx<R>* __restrict__ r2m) {
+  using C = rowinv_cfg<R, M>;
+  constexpr int E = C::E, T = C::T, G = C::G, LL = C::LL;
+  __shared__ cx<R> smem[G * LL];
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int row = blockIdx.x * G + g;
+  const bool active = row < nrows;
+  cx<R>* lds = smem + g * LL;
+  const cx<R>* v = V + (int64_t)(active ? row : 0) * (2 * M);
+  cx<R> ve[E], vo[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int p = t + e * T;
+    ve[e] = active ? v[2 * p] : cx<R>{0, 0};
+    vo[e] = active ? v[2 * p + 1] : cx<R>{0, 0};
+  }
+  const roots_t<R> wm{r2m, 2};
+  fft<true, M, T>(ve, lds, wm, t);
+  fft<true, M, T>(vo, lds, wm, t);
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int n = t + e * T;
+      const cx<R> r = ve[e] + cmulc(vo[e], r2m[n]);
+      fx[(int64_t)row * M + n] = (Out)r.x;
+      fy[(int64_t)row * M + n] = (Out)r.y;
+    }
+  }
+}
+
+// ------------------------------------------------------ spectrum (plan) --
+// Column FFT (FP64, full length 2N: the even/odd output split preceded by
+// the first radix-2 butterfly) of the row spectra of the padded weight
+// table, then the stored form of W^d(p, q) / (4MN):
+//   odd k : A = Im W (W is purely imaginary), q in [0, N], split by parity;
+//   k = 2 : W itself for every q in [0, 2N), split by parity.
+// Output element type: double / double2 (FP64 plans) or hi+lo floats.
+template <int N>
+struct spec_cfg {
+  static constexpr int E = N < 8 ? N : 8;
+  static constexpr int T = N / E;
+  static constexpr int LL = lds_len<N>::value;
+};
+
+__device__ __forceinline__ void put_odd(void* tab, int fp32, int64_t idx, double v) {
+  if (fp32) {
+    const float h = (float)v;
+    reinterpret_cast<float2*>(tab)[idx] = make_float2(h, (float)(v - (double)h));
+  } else {
+    reinterpret_cast<double*>(tab)[idx] = v;
+  }
+}
+__device__ __forceinline__ void put_cplx(void* tab, int fp32, int64_t idx, cx<double> v) {
+  if (fp32) {
+    const float rh = (float)v.x, ih = (float)v.y;
+    reinterpret_cast<float4*>(tab)[idx] =
+        make_float4(rh, (float)(v.x - (double)rh), ih, (float)(v.y - (double)ih));
+  } else {
+    reinterpret_cast<double2*>(tab)[idx] = make_double2(v.x, v.y);
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__((spec_cfg<N>::T))
+    k_spec_col(const cx<double>* __restrict__ S, int M, void* __restrict__ tab, int kind, int fp32,
+               double scale, const cx<double>* __restrict__ r2n) {
+  using C = spec_cfg<N>;
+  constexpr int E = C::E, T = C::T, LL = C::LL;
+  __shared__ cx<double> lds[LL];
+  const int t = threadIdx.x;
+  const int c = blockIdx.x;
+  cx<double> lo[E], hi[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int j = t + e * T;
+    lo[e] = S[(int64_t)j * M + c];
+    hi[e] = S[(int64_t)(j + N) * M + c];
+  }
+  const roots_t<double> wn{r2n, 2};
+  for (int half = 0; half < 2; ++half) {
+    cx<double> f[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) f[e] = half ? cmul(lo[e] - hi[e], r2n[t + e * T]) : lo[e] + hi[e];
+    fft<false, N, T>(f, lds, wn, t);
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = f[e];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int qq = t + e * T;
+      cx<double> vals[2];
+      int rows[2];
+      int nv = 1;
+      if (c == 0) {
+        const int qm = half == 0 ? ((N - qq) & (N - 1)) : (N - 1 - qq);
+        const cx<double> u = f[e], um = conj(lds[pad(qm)]);
+        vals[0] = cx<double>{0.5 * (u.x + um.x), 0.5 * (u.y + um.y)};
+        vals[1] = cx<double>{0.5 * (u.y - um.y), -0.5 * (u.x - um.x)};
+        rows[0] = 0;
+        rows[1] = M;
+        nv = 2;
+      } else {
+        vals[0] = f[e];
+        rows[0] = c;
+      }
+      for (int h = 0; h < nv; ++h) {
+        const cx<double> w = vals[h] * scale;
+        if (kind == 0) {
+          if (half == 0 && qq <= N / 2) put_odd(tab, fp32, (int64_t)rows[h] * (N + 1) + qq, w.y);
+          if (half == 1 && qq < N / 2) put_odd(tab, fp32, (int64_t)rows[h] * (N + 1) + N / 2 + 1 + qq, w.y);
+        } else {
+          put_cplx(tab, fp32, (int64_t)rows[h] * (2 * N) + half * N + qq, w);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------ finite check --
+template <typename In>
+__global__ void k_check_finite(const In* __restrict__ x, int64_t n, int* __restrict__ flag) {
+  int bad = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite((double)x[i]);
+  if (bad) atomicOr(flag, 1);
+}
+
+// ------------------------------------------------- coefficients (C out) --
+// sigma -> C for k = 3 written out (sg_bspline_coeffs): the x-solve along
+// rows (Eq. (C_system)) then the y-solve along columns (Eq. (z_system));
+// the two commute.  The per-step force path fuses them into passes A and B.
+template <int M>
+struct coeff_cfg {
+  static constexpr int CH = M < 16 ? M : 16;
+  static constexpr int T = M / CH;
+  static constexpr int G = T >= 256 ? 1 : 256 / T;
+  static constexpr int SLOT = (int)sizeof(tri_smem<double, T>) / 8 + 1;
+};
+
+template <typename R, int M>
+__global__ void __launch_bounds__((coeff_cfg<M>::G * coeff_cfg<M>::T))
+    k_coeff_rows(const R* __restrict__ src, R* __restrict__ dst, int nrows) {
+  using C = coeff_cfg<M>;
+  constexpr int CH = C::CH, T = C::T;
+  __shared__ double smem[C::G * C::SLOT];
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int row = blockIdx.x * C::G + g;
+  const bool active = row < nrows;
+  double d[CH];
+#pragma unroll
+  for (int e = 0; e < CH; ++e) d[e] = active ? 8.0 * (double)src[(int64_t)row * M + t * CH + e] : 0.0;
+  tri_solve<CH, T, double>(d, t, *reinterpret_cast<tri_smem<double, T>*>(smem + g * C::SLOT));
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < CH; ++e) dst[(int64_t)row * M + t * CH + e] = (R)d[e];
+  }
+}
+
+template <int N>
+struct coeffc_cfg {
+  static constexpr int CH = N < 16 ? N : 16;
+  static constexpr int T = N / CH;
+  static constexpr int P = T >= 64 ? 1 : 64 / T;
+  static constexpr int TRI = (int)sizeof(tri_smem<double, T>) / 8 + 1;
+  static constexpr int SLOT = (N + 1) > TRI ? (N + 1) : TRI;
+};
+
+template <typename R, int N>
+__global__ void __launch_bounds__((coeffc_cfg<N>::P * coeffc_cfg<N>::T))
+    k_coeff_cols(R* __restrict__ data, int M) {
+  using C = coeffc_cfg<N>;
+  constexpr int CH = C::CH, T = C::T, SLOT = C::SLOT;
+  __shared__ double smem[C::P * SLOT];
+  const int P = blockDim.x / T;
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int c0 = blockIdx.x * P;
+  for (int s = 0; s < CH; ++s) {
+    const int l = threadIdx.x + s * P * T;
+    smem[(l % P) * SLOT + l / P] = (double)data[(int64_t)(l / P) * M + c0 + l % P];
+  }
+  __syncthreads();
+  double d[CH];
+#pragma unroll
+  for (int e = 0; e < CH; ++e) d[e] = 8.0 * smem[g * SLOT + t * CH + e];
+  __syncthreads();
+  tri_solve<CH, T, double>(d, t, *reinterpret_cast<tri_smem<double, T>*>(smem + g * SLOT));
+#pragma unroll
+  for (int e = 0; e < CH; ++e) smem[g * SLOT + t * CH + e] = d[e];
+  __syncthreads();
+  for (int s = 0; s < CH; ++s) {
+    const int l = threadIdx.x + s * P * T;
+    data[(int64_t)(l / P) * M + c0 + l % P] = (R)smem[(l % P) * SLOT + l / P];
+  }
+}
+
+// ------------------------------------------------------------ launches --
+template <typename R>
+struct tabs {
+  using odd = typename std::conditional<sizeof(R) == 4, float2, double>::type;
+  using cplx = typename std::conditional<sizeof(R) == 4, float4, double2>::type;
+};
+
+#define SG_SIZES(X) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
+
+template <typename R, typename In, int M>
+static hipError_t launch_row_fwd_t(const In* src, int64_t src_ld, cx<R>* X, int nrows, const cx<R>* r2m,
+                                   int solve, int full, hipStream_t st) {
+  using C = rowfwd_cfg<R, In, M>;
+  const int blocks = (nrows + C::G - 1) / C::G;
+  hipLaunchKernelGGL((k_row_fwd<R, In, M>), dim3(blocks), dim3(C::G * C::T), 0, st, src, src_ld, X, nrows,
+                     r2m, solve, full);
+  return hipGetLastError();
+}
+
+template <typename R, int N>
+static hipError_t launch_col_t(const cx<R>* X, cx<R>* V, int M, const void* tx, const void* ty, int kind,
+                               const cx<R>* r2n, int solve, hipStream_t st) {
+  using C = col_cfg<R, N>;
+  using TO = typename tabs<R>::odd;
+  using TC = typename tabs<R>::cplx;
+  const int P = C::P < M ? C::P : M;
+  const TO* tox = kind == 0 ? (const TO*)tx : nullptr;
+  const TO* toy = kind == 0 ? (const TO*)ty : nullptr;
+  const TC* tcx = kind == 1 ? (const TC*)tx : nullptr;
+  const TC* tcy = kind == 1 ? (const TC*)ty : nullptr;
+  hipLaunchKernelGGL((k_col<R, TO, TC, N>), dim3(M / P), dim3(P * C::T), 0, st, X, V, M, tox, toy, tcx, tcy,
+                     r2n, solve, kind);
+  return hipGetLastError();
+}
+
+template <typename R, typename Out, int M>
+static hipError_t launch_row_inv_t(const cx<R>* V, Out* fx, Out* fy, int nrows, const cx<R>* r2m,
+                                   hipStream_t st) {
+  using C = rowinv_cfg<R, M>;
+  const int blocks = (nrows + C::G - 1) / C::G;
+  hipLaunchKernelGGL((k_row_inv<R, Out, M>), dim3(blocks), dim3(C::G * C::T), 0, st, V, fx, fy, nrows, r2m);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_spec_col_t(const cx<double>* S, int M, void* tab, int kind, int fp32, double scale,
+                                    const cx<double>* r2n, hipStream_t st) {
+  using C = spec_cfg<N>;
+  hipLaunchKernelGGL((k_spec_col<N>), dim3(M), dim3(C::T), 0, st, S, M, tab, kind, fp32, scale, r2n);
+  return hipGetLastError();
+}
+
+}  // namespace sg
+
+// ------------------------------------------------- dispatch (host side) --
+using namespace sg;
+
+hipError_t sg_launch_weights(int k, double hx, double hy, int M, int N, double* wx, double* wy, int layout,
+                             hipStream_t st) {
+  const int64_t total = (int64_t)(layout == 0 ? 2 * M : 2 * M - 1) * (layout == 0 ? 2 * N : 2 * N - 1);
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_weights, dim3((unsigned)blocks), dim3(256), 0, st, k, hx, hy, M, N, wx, wy, layout);
+  return hipGetLastError();
+}
+
+hipError_t sg_set_gl_tables(const double* x, const double* w) {
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_glx), x, sizeof(double) * 64);
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_glw), w, sizeof(double) * 64);
+}
+
+template <typename R, typename In>
+static hipError_t row_fwd_dispatch(int M, const In* src, int64_t ld, cx<R>* X, int nrows, const cx<R>* r2m,
+                                   int solve, int full, hipStream_t st) {
+  switch (M) {
+#define CASE(SZ) \
+  case SZ:       \
+    return launch_row_fwd_t<R, In, SZ>(src, ld, X, nrows, r2m, solve, full, st);
+    SG_SIZES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename R>
+static hipError_t col_dispatch(int N, const cx<R>* X, cx<R>* V, int M, const void* tx, const void* ty, int kind,
+                               const cx<R>* r2n, int solve, hipStream_t st) {
+  switch (N) {
+#define CASE(SZ) \
+  case SZ:       \
+    return launch_col_t<R, SZ>(X, V, M, tx, ty, kind, r2n, solve, st);
+    SG_SIZES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename R, typename Out>
+static hipError_t row_inv_dispatch(int M, const cx<R>* V, Out* fx, Out* fy, int nrows, const cx<R>* r2m,
+                                   hipStream_t st) {
+  switch (M) {
+#define CASE(SZ) \
+  case SZ:       \
+    return launch_row_inv_t<R, Out, SZ>(V, fx, fy, nrows, r2m, st);
+    SG_SIZES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t sg_launch_row_fwd(int prec, int M, const void* src, int64_t ld, void* X, int nrows, const void* r2m,
+                             int solve, int full, hipStream_t st) {
+  if (prec == 0)
+    return row_fwd_dispatch<double, double>(M, (const double*)src, ld, (cx<double>*)X, nrows,
+                                            (const cx<double>*)r2m, solve, full, st);
+  return row_fwd_dispatch<float, float>(M, (const float*)src, ld, (cx<float>*)X, nrows, (const cx<float>*)r2m,
+                                        solve, full, st);
+}
+
+hipError_t sg_launch_col(int prec, int N, const void* X, void* V, int M, const void* tx, const void* ty, int kind,
+                         const void* r2n, int solve, hipStream_t st) {
+  if (prec == 0)
+    return col_dispatch<double>(N, (const cx<double>*)X, (cx<double>*)V, M, tx, ty, kind, (const cx<double>*)r2n,
+                                solve, st);
+  return col_dispatch<float>(N, (const cx<float>*)X, (cx<float>*)V, M, tx, ty, kind, (const cx<float>*)r2n, solve,
+                             st);
+}
+
+hipError_t sg_launch_row_inv(int prec, int M, const void* V, void* fx, void* fy, int nrows, const void* r2m,
+                             hipStream_t st) {
+  if (prec == 0)
+    return row_inv_dispatch<double, double>(M, (const cx<double>*)V, (double*)fx, (double*)fy, nrows,
+                                            (const cx<double>*)r2m, st);
+  return row_inv_dispatch<float, float>(M, (const cx<float>*)V, (float*)fx, (float*)fy, nrows,
+                                        (const cx<float>*)r2m, st);
+}
+
+hipError_t sg_launch_spec_col(int N, const void* rowspec, int M, void* tab, int kind, int fp32, double scale,
+                              const void* r2n, hipStream_t st) {
+  switch (N) {
+#define CASE(SZ) \
+  case SZ:       \
+    return launch_spec_col_t<SZ>((const cx<double>*)rowspec, M, tab, kind, fp32, scale, (const cx<double>*)r2n, st);
+    SG_SIZES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t sg_launch_check_finite(int prec, const void* x, int64_t n, int* flag, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_check_finite<double>, dim3((unsigned)blocks), dim3(256), 0, st, (const double*)x, n, flag);
+  else
+    hipLaunchKernelGGL(k_check_finite<float>, dim3((unsigned)blocks), dim3(256), 0, st, (const float*)x, n, flag);
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t coeff_rows_dispatch(int M, const R* src, R* dst, int nrows, hipStream_t st) {
+  switch (M) {
+#define CASE(SZ)                                                                                     \
+  case SZ: {                                                                                         \
+    using C = coeff_cfg<SZ>;                                                                         \
+    hipLaunchKernelGGL((k_coeff_rows<R, SZ>), dim3((nrows + C::G - 1) / C::G), dim3(C::G * C::T), 0, st, src, \
+                       dst, nrows);                                                                 \
+    return hipGetLastError();                                                                       \
+  }
+    SG_SIZES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename R>
+static hipError_t coeff_cols_dispatch(int N, R* data, int M, hipStream_t st) {
+  switch (N) {
+#define CASE(SZ)                                                                                      \
+  case SZ: {                                                                                          \
+    using C = coeffc_cfg<SZ>;                                                                         \
+    const int P = C::P < M ? C::P : M;                                                               \
+    hipLaunchKernelGGL((k_coeff_cols<R, SZ>), dim3(M / P), dim3(P * C::T), 0, st, data, M);           \
+    return hipGetLastError();                                                                        \
+  }
+    SG_SIZES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t sg_launch_coeff_rows(int prec, int M, const void* src, void* dst, int nrows, hipStream_t st) {
+  if (prec == 0) return coeff_rows_dispatch<double>(M, (const double*)src, (double*)dst, nrows, st);
+  return coeff_rows_dispatch<float>(M, (const float*)src, (float*)dst, nrows, st);
+}
+
+hipError_t sg_launch_coeff_cols(int prec, int N, void* data, int M, hipStream_t st) {
+  if (prec == 0) return coeff_cols_dispatch<double>(N, (double*)data, M, st);
+  return coeff_cols_dispatch<float>(N, (float*)data, M, st);
+}

@@ -144,82 +144,90 @@ def test_weights_k1_closed_form():
     assert np.allclose(wy2, wx, rtol=1e-15, atol=0)
 
 
-def _piece_poly_1d(k, m, shift):
-    """Knots (cell units) and the explicit cardinal spline as a function."""
+def _piece_poly_1d(k, m, shift, h=1.0):
+    """Knots (in length units, cell size h) and the explicit cardinal spline."""
     t0 = -m - 0.5 - shift
-    return [t0 + r for r in range(k + 1)], (lambda x: cardinal(k, [x - t0])[0])
+    return [(t0 + r) * h for r in range(k + 1)], (lambda x: cardinal(k, [x / h - t0])[0])
 
 
-@pytest.mark.parametrize("k,m,n", [(2, 1, 2), (2, -3, 0), (2, 0, 3), (3, 2, 1), (3, -1, 3), (3, 4, -2),
-                                   (3, 0, 2)])
-def test_weights_library_quadrature(k, m, n):
-    """Every spline piece integrated by scipy's adaptive quadrature."""
+def _pieces_by_dblquad(k, m, n, hx, hy, skip_origin):
     shift = (k - 1) // 2
-    tx, bx = _piece_poly_1d(k, m, shift)
-    ty, by = _piece_poly_1d(k, n, shift)
+    tx, bx = _piece_poly_1d(k, m, shift, hx)
+    ty, by = _piece_poly_1d(k, n, shift, hy)
     tot_x = tot_y = 0.0
     for r in range(k):
         for s in range(k):
             xa, xb, ya, yb = tx[r], tx[r + 1], ty[s], ty[s + 1]
-            assert not (xa < 0 < xb and ya < 0 < yb)
+            if xa < 0 < xb and ya < 0 < yb:
+                assert skip_origin
+                continue
             fx = lambda y, x: x / (x * x + y * y) ** 1.5 * bx(x) * by(y)
             fy = lambda y, x: y / (x * x + y * y) ** 1.5 * bx(x) * by(y)
             tot_x += integrate.dblquad(fx, xa, xb, ya, yb, epsabs=1e-15, epsrel=1e-13)[0]
             tot_y += integrate.dblquad(fy, xa, xb, ya, yb, epsabs=1e-15, epsrel=1e-13)[0]
-    wx, wy = oracle.weights_at(k, 1.0, 1.0, [m], [n])
+    return tot_x, tot_y
+
+
+@pytest.mark.parametrize("k,m,n,hx,hy", [(2, 1, 2, 1, 1), (2, -3, 0, 1, 1), (2, 0, 3, 1, 1), (3, 2, 1, 1, 1),
+                                         (3, -1, 3, 1, 1), (3, 4, -2, 1, 1), (3, 0, 2, 1, 1),
+                                         (3, 0, 2, 3, 1), (3, 2, 0, 1, 3), (1, 0, 1, 3, 1), (2, 2, 1, 2, 1),
+                                         (2, 0, 2, 1, 2.5)])
+def test_weights_library_quadrature(k, m, n, hx, hy):
+    """Every spline piece integrated by scipy's adaptive quadrature (also
+    for cells with dx != dy, which the grid of Sec. 2 allows)."""
+    tot_x, tot_y = _pieces_by_dblquad(k, m, n, hx, hy, skip_origin=False)
+    wx, wy = oracle.weights_at(k, hx, hy, [m], [n])
     assert abs(wx[0] - tot_x) < 1e-12 * max(abs(tot_x), 1e-3), (wx[0], tot_x)
     assert abs(wy[0] - tot_y) < 1e-12 * max(abs(tot_y), 1e-3), (wy[0], tot_y)
 
 
-def _origin_piece_closed(k, m, n):
-    """Principal value over the piece [-1/2,1/2]^2 that holds the singularity:
-    only monomials even in both x~ and y~ survive the symmetric integration
-    (the odd ones cancel in the principal value), each being 4 times the
-    integral over [0,1/2]^2, taken by corner differences of the Appendix A
-    antiderivatives (limits at the axes by a tiny offset at 50 digits)."""
+def _origin_piece_closed(k, m, n, hx=1.0, hy=1.0):
+    """Principal value over the piece [-dx/2,dx/2]x[-dy/2,dy/2] that holds the
+    singularity: only monomials even in both x~ and y~ survive the symmetric
+    integration (the odd ones cancel in the principal value), each being 4
+    times the integral over [0,dx/2]x[0,dy/2], taken by corner differences of
+    the Appendix A antiderivatives (limits at the axes by a tiny offset at 50
+    digits).  Returns (w^x part, w^y part)."""
     mp.mp.dps = 50
     shift = (k - 1) // 2
-    tx, bx = _piece_poly_1d(k, m, shift)
-    ty, by = _piece_poly_1d(k, n, shift)
-    # polynomial coefficients of the spline pieces on [-1/2, 1/2]
-    nodes = np.array([-0.25, 0.0, 0.25])
-    px = np.polyfit(nodes, [bx(x) for x in nodes], 2)[::-1]   # p0 + p1 x + p2 x^2
-    py = np.polyfit(nodes, [by(y) for y in nodes], 2)[::-1]
+    tx, bx = _piece_poly_1d(k, m, shift, hx)
+    ty, by = _piece_poly_1d(k, n, shift, hy)
+    # polynomial coefficients of the spline pieces on the centred square
+    nx_ = np.array([-0.25, 0.0, 0.25]) * hx
+    ny_ = np.array([-0.25, 0.0, 0.25]) * hy
+    px = np.polyfit(nx_, [bx(x) for x in nx_], 2)[::-1]   # p0 + p1 x + p2 x^2
+    py = np.polyfit(ny_, [by(y) for y in ny_], 2)[::-1]
     eps = mp.mpf("1e-40")
-    H = mp.mpf(1) / 2
+    X, Y = mp.mpf(hx) / 2, mp.mpf(hy) / 2
 
     def quad_pos(al, be):
         F = lambda x, y: oracle.antiderivative(x, y, al, be)
-        return F(H, H) - F(eps, H) - F(H, eps) + F(eps, eps)
+        return F(X, Y) - F(eps, Y) - F(X, eps) + F(eps, eps)
 
-    wx = mp.mpf(0)
+    wx = wy = mp.mpf(0)
     for a in range(3):
         for b in range(3):
-            al, be = a + 1, b          # kernel x~ times x~^a y~^b
-            if al % 2 == 0 and be % 2 == 0 and px[a] != 0 and py[b] != 0:
-                wx += 4 * mp.mpf(px[a]) * mp.mpf(py[b]) * quad_pos(al, be)
-    return float(wx)
+            if px[a] == 0 or py[b] == 0:
+                continue
+            if (a + 1) % 2 == 0 and b % 2 == 0:      # kernel x~ times x~^a y~^b
+                wx += 4 * mp.mpf(px[a]) * mp.mpf(py[b]) * quad_pos(a + 1, b)
+            if a % 2 == 0 and (b + 1) % 2 == 0:      # kernel y~ times x~^a y~^b
+                wy += 4 * mp.mpf(px[a]) * mp.mpf(py[b]) * quad_pos(a, b + 1)
+    return float(wx), float(wy)
 
 
-@pytest.mark.parametrize("k,m,n", [(1, 0, 0), (2, 0, 0), (2, 1, 0), (2, 0, 1), (2, 1, 1), (3, 0, 0),
-                                   (3, 1, 0), (3, -1, 1), (3, 1, 1), (3, 0, 1)])
-def test_weights_origin_piece(k, m, n):
+@pytest.mark.parametrize("k,m,n,hx,hy", [(1, 0, 0, 1, 1), (2, 0, 0, 1, 1), (2, 1, 0, 1, 1), (2, 0, 1, 1, 1),
+                                         (2, 1, 1, 1, 1), (3, 0, 0, 1, 1), (3, 1, 0, 1, 1), (3, -1, 1, 1, 1),
+                                         (3, 1, 1, 1, 1), (3, 0, 1, 1, 1), (3, 1, 0, 3, 1), (3, 1, -1, 1, 2.5),
+                                         (2, 1, 0, 2, 1)])
+def test_weights_origin_piece(k, m, n, hx, hy):
     """Offsets whose spline has a piece on the singularity: that piece by the
     closed forms, the other pieces by scipy's adaptive quadrature."""
-    shift = (k - 1) // 2
-    tx, bx = _piece_poly_1d(k, m, shift)
-    ty, by = _piece_poly_1d(k, n, shift)
-    tot = 0.0
-    for r in range(k):
-        for s in range(k):
-            xa, xb, ya, yb = tx[r], tx[r + 1], ty[s], ty[s + 1]
-            if xa < 0 < xb and ya < 0 < yb:
-                continue
-            f = lambda y, x: x / (x * x + y * y) ** 1.5 * bx(x) * by(y)
-            tot += integrate.dblquad(f, xa, xb, ya, yb, epsabs=1e-15, epsrel=1e-13)[0]
-    tot += _origin_piece_closed(k, m, n)
-    wx, _ = oracle.weights_at(k, 1.0, 1.0, [m], [n])
-    assert abs(wx[0] - tot) < 1e-12, (wx[0], tot)
+    ox, oy = _origin_piece_closed(k, m, n, hx, hy)
+    px, py = _pieces_by_dblquad(k, m, n, hx, hy, skip_origin=True)
+    wx, wy = oracle.weights_at(k, hx, hy, [m], [n])
+    assert abs(wx[0] - (ox + px)) < 1e-12 * max(1.0, abs(wx[0])), (wx[0], ox + px)
+    assert abs(wy[0] - (oy + py)) < 1e-12 * max(1.0, abs(wy[0])), (wy[0], oy + py)
 
 
 def test_weight_symmetries_and_scale():
