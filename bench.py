@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Benchmark: thin-disk self-gravity forces (Fx + Fy), order k = 3, on one MI355X.
+
+One step = the whole per-step path of the method for one surface density
+sigma already resident in HBM: coefficient solve (Sec. 2.3), one forward and
+two inverse zero-padded FFT convolutions with the kernel-weight spectra
+(Sec. 4.2), Fx and Fy written at every cell centre.  Plan time (weights and
+their spectra, done once per the end of Sec. 2.2) is outside the timed region
+and reported separately.
+
+Workload (default): 4096 x 4096 cells on [-1,1]^2, k = 3, sigma = 32 seeded
+Gaussian clumps times a taper (``workloads``).  ``value`` is the FP32-split
+path's cells/s; the FP64 path is timed on the same input and the FP32-split
+error against it (max over cells and components, scaled by max|F|) is
+reported.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+
+
+def bytes_per_cell(prec_fp64: bool):
+    """Algorithmic HBM bytes per output cell, per pass (A, B, C).
+
+    A: read sigma, write the row spectra X (one complex per cell).
+    B: read X, read the two weight spectra (one real per (p, q) bin each,
+       a float hi+lo pair or a double), write V (two complex per cell).
+    C: read V, write Fx and Fy."""
+    r = 8 if prec_fp64 else 4          # real
+    c = 2 * r                          # complex
+    t = 8                              # spectrum entry: double, or float hi + lo
+    return {"A": r + c, "B": c + 2 * t + 2 * c, "C": 2 * c + 2 * r}
+
+
+def time_plan(sg, torch, grid, prec, sigma_np, steps, warmup):
+    plan_t0 = time.perf_counter()
+    plan = sg.Plan([grid], prec)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - plan_t0
+    sigma = torch.as_tensor(sigma_np.ravel(), dtype=plan.dtype, device="cuda")
+    fx, fy = plan.empty(), plan.empty()
+    for _ in range(warmup):
+        plan.forces(sigma, fx, fy)
+    torch.cuda.synchronize()
+    sg.sg_plan_set_timing(plan.handle, True)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(steps):
+        plan.forces(sigma, fx, fy)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    pass_ms, calls = sg.sg_plan_pass_times(plan.handle)
+    sg.sg_plan_set_timing(plan.handle, False)
+    out = (fx.double().cpu().numpy(), fy.double().cpu().numpy())
+    plan.close()
+    return ms, [p / calls for p in pass_ms], plan_s, out
+
+
+def cpu_baseline(n, k, sigma_np, sample):
+    """The oracle (direct O(N^4) FP64 sum, OpenMP) on a bounded sample of cells."""
+    import numpy as np
+    import oracle
+    import workloads
+    h = 2.0 / n
+    t0 = time.perf_counter()
+    C = oracle.bspline_coeffs(sigma_np, k)
+    t_solve = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    wx, wy = oracle.weights(k, n, n, h, h)
+    t_tab = time.perf_counter() - t0
+    cells = workloads.sample_cells(7, n, n, sample)
+    t0 = time.perf_counter()
+    oracle.forces_from_coeffs(C, wx, wy, cells)
+    t_sum = time.perf_counter() - t0
+    # per-cell cost of a step: the full coefficient solve spread over all cells
+    per_cell = t_sum / cells.size + t_solve / (n * n)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / per_cell, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": (f"{cells.size} of {n}x{n} cells (seeded), direct FP64 sum with the full weight table; "
+                       f"coefficient solve on the full grid {t_solve:.2f} s (apportioned per cell); "
+                       f"weight-table build {t_tab:.1f} s excluded, like GPU plan time"),
+            "host_cpu": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--k", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design, not a build (see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1904_07400_amd as sg
+    import workloads
+
+    n, k = args.n, args.k
+    grid = (n, n, -1.0, 1.0, -1.0, 1.0, k)
+    # sample lattice of the plan (cell centres for odd k)
+    probe = sg.Plan([(8, 8, -1.0, 1.0, -1.0, 1.0, k)], sg.SG_FP64)
+    xs0, ys0, _, _ = sg.sg_sample_points(probe.handle, 0)
+    probe.close()
+    h = 2.0 / n
+    off = (xs0 + 1.0) / (2.0 / 8)  # 0.5 (centres) or 1.0 (vertices) in cell units
+    xs = -1.0 + h * (off + np.arange(n))
+    sigma = workloads.clump_sigma(workloads.clump_params(2, 32), xs, xs)
+
+    ms64, pass64, plan64, (gx, gy) = time_plan(sg, torch, grid, sg.SG_FP64, sigma, args.steps, args.warmup)
+    ms32, pass32, plan32, (fx, fy) = time_plan(sg, torch, grid, sg.SG_FP32_SPLIT, sigma, args.steps, args.warmup)
+    scale = max(np.abs(gx).max(), np.abs(gy).max())
+    err32 = max(np.abs(fx - gx).max(), np.abs(fy - gy).max()) / scale
+
+    cells = n * n
+    bpc = bytes_per_cell(False)
+    dom = max(range(3), key=lambda i: pass32[i])
+    name = "ABC"[dom]
+    achieved = bpc[name] * cells / (pass32[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": {"A": "k_row_fwd", "B": "k_col", "C": "k_row_inv"}[name],
+                "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "bytes_per_cell": bpc[name], "kernel_ms": round(pass32[dom], 4)}
+    total_bytes = sum(bpc.values()) * cells
+    line = {
+        "metric": "force cells/s (Fx+Fy, 3rd order, 4096²): FP32-split vs FP64 at ≤1e-6 rel",
+        "value": cells / (ms32 * 1e-3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32-split (fp64 solve, fp32 FFT, hi+lo spectra)",
+        "data": "synthetic",
+        "config": {"workload": f"{n}x{n} cells on [-1,1]^2, k={k}, sigma = 32 seeded Gaussian clumps x taper "
+                               f"(clump recipe of the 1024^2 precision case, at {n}^2)",
+                   "grid": n, "order": k, "parallelism": "single GPU"},
+        "fp64": {"value": cells / (ms64 * 1e-3), "ms_per_step": round(ms64, 4),
+                 "pass_ms": [round(x, 4) for x in pass64], "plan_s": round(plan64, 3)},
+        "fp32_split": {"pass_ms": [round(x, 4) for x in pass32], "plan_s": round(plan32, 3),
+                       "rel_err_vs_fp64": err32, "meets_1e-6": bool(err32 <= 1e-6),
+                       "step_gbs_algorithmic": round(total_bytes / (ms32 * 1e-3) / 1e9, 1)},
+        "speedup_fp32split_vs_fp64": round(ms64 / ms32, 3),
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(n, k, sigma, args.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -123,6 +123,16 @@ sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy);
  * inputs. */
 sg_status sg_forces_adjoint(sg_plan p, const void* gfx, const void* gfy, void* gsigma);
 
+/* Per-pass timing, a profiling aid.  While enabled, sg_forces records HIP
+ * events on the plan's stream around each of its three kernel passes (row
+ * transform, column transform with the spectral products, inverse row
+ * transform).  sg_plan_pass_times synchronises the stream, returns the
+ * milliseconds spent in each pass summed over all grids and calls since
+ * timing was enabled (ms: HOST array of 3) and the number of calls, and
+ * starts a new accumulation.  Enabling or disabling also resets it. */
+sg_status sg_plan_set_timing(sg_plan p, int32_t enable);
+sg_status sg_plan_pass_times(sg_plan p, double* ms, int64_t* calls);
+
 /* Static string for a status code. */
 const char* sg_status_string(sg_status s);
 

@@ -21,7 +21,7 @@ __all__ = [
     "SG_FP64", "SG_FP32_SPLIT", "SG_FLAG_CHECK_FINITE", "SGError", "sg_grid", "lib",
     "sg_plan_create", "sg_plan_destroy", "sg_plan_layout", "sg_plan_info", "sg_sample_points",
     "sg_weights", "sg_bspline_coeffs", "sg_forces", "sg_forces_adjoint", "sg_status_string",
-    "sg_last_error_message", "Plan", "ThinDiskForces",
+    "sg_last_error_message", "sg_plan_set_timing", "sg_plan_pass_times", "Plan", "ThinDiskForces",
 ]
 
 SG_FP64 = 0
@@ -69,13 +69,15 @@ def lib() -> ctypes.CDLL:
             L.sg_bspline_coeffs.argtypes = [vp, vp, vp]
             L.sg_forces.argtypes = [vp, vp, vp, vp]
             L.sg_forces_adjoint.argtypes = [vp, vp, vp, vp]
+            L.sg_plan_set_timing.argtypes = [vp, i32]
+            L.sg_plan_pass_times.argtypes = [vp, dp, ctypes.POINTER(i64)]
             L.sg_status_string.argtypes = [ctypes.c_int]
             L.sg_status_string.restype = ctypes.c_char_p
             L.sg_last_error_message.argtypes = []
             L.sg_last_error_message.restype = ctypes.c_char_p
             for f in ("sg_plan_create", "sg_plan_destroy", "sg_plan_layout", "sg_plan_info",
                       "sg_sample_points", "sg_weights", "sg_bspline_coeffs", "sg_forces",
-                      "sg_forces_adjoint"):
+                      "sg_forces_adjoint", "sg_plan_set_timing", "sg_plan_pass_times"):
                 getattr(L, f).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -137,6 +139,18 @@ def sg_plan_info(plan: int):
     n, p, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
     _check(lib().sg_plan_info(plan, ctypes.byref(n), ctypes.byref(p), ctypes.byref(b)))
     return n.value, p.value, b.value
+
+
+def sg_plan_set_timing(plan: int, enable: bool) -> None:
+    _check(lib().sg_plan_set_timing(plan, 1 if enable else 0))
+
+
+def sg_plan_pass_times(plan: int):
+    """(ms per pass summed since enabled [A, B, C], number of sg_forces calls)."""
+    ms = (ctypes.c_double * 3)()
+    calls = ctypes.c_int64()
+    _check(lib().sg_plan_pass_times(plan, ms, ctypes.byref(calls)))
+    return list(ms), calls.value
 
 
 def sg_sample_points(plan: int, g: int):

@@ -116,6 +116,9 @@ struct sg_plan_s {
   std::vector<void*> allocs;
   std::map<int, void*> roots;  // plan-precision tables keyed by B
   int* flag = nullptr;         // device word for the finite check
+  bool timing = false;         // per-pass event timing (sg_plan_set_timing)
+  std::vector<hipEvent_t> ev;  // 4 events per grid and call while timing
+  int64_t timed_calls = 0;
 };
 
 namespace {
@@ -148,9 +151,26 @@ sg_status upload_roots(sg_plan p, int B, void** out) {
   return hip_check(p, hipMemcpy(*out, h.data(), h.size() * sizeof(R), hipMemcpyHostToDevice), "hipMemcpy roots");
 }
 
+void drop_events(sg_plan p) {
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  p->ev.clear();
+  p->timed_calls = 0;
+}
+
 void release(sg_plan p) {
+  drop_events(p);
   for (void* a : p->allocs) (void)hipFree(a);
   p->allocs.clear();
+}
+
+// record one timing event on the plan's stream (no-op unless timing)
+hipError_t mark(sg_plan p) {
+  if (!p->timing) return hipSuccess;
+  hipEvent_t e;
+  hipError_t r = hipEventCreate(&e);
+  if (r != hipSuccess) return r;
+  p->ev.push_back(e);
+  return hipEventRecord(e, p->st);
 }
 
 sg_status check_plan(sg_plan p) {
@@ -397,11 +417,47 @@ sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy) {
     char* ox = (char*)fx + el * G.off;
     char* oy = (char*)fy + el * G.off;
     const int solve = G.k == 3 ? 1 : 0;
-    hipError_t e = sg_launch_row_fwd(prec, G.M, src, G.M, G.X, G.N, G.r2m, solve, 0, p->st);
+    hipError_t e = mark(p);
+    if (e == hipSuccess) e = sg_launch_row_fwd(prec, G.M, src, G.M, G.X, G.N, G.r2m, solve, 0, p->st);
+    if (e == hipSuccess) e = mark(p);
     if (e == hipSuccess) e = sg_launch_col(prec, G.N, G.X, G.V, G.M, G.tabx, G.taby, G.kind, G.r2n, solve, p->st);
+    if (e == hipSuccess) e = mark(p);
     if (e == hipSuccess) e = sg_launch_row_inv(prec, G.M, G.V, ox, oy, G.N, G.r2m, p->st);
+    if (e == hipSuccess) e = mark(p);
     if (e != hipSuccess) return hip_check(p, e, "force launch");
   }
+  if (p->timing) ++p->timed_calls;
+  return SG_OK;
+}
+
+sg_status sg_plan_set_timing(sg_plan p, int32_t enable) {
+  g_msg.clear();
+  sg_status s = check_plan(p);
+  if (s != SG_OK) return s;
+  hipError_t e = hipStreamSynchronize(p->st);
+  if (e != hipSuccess) return hip_check(p, e, "timing sync");
+  drop_events(p);
+  p->timing = enable != 0;
+  return SG_OK;
+}
+
+sg_status sg_plan_pass_times(sg_plan p, double* ms, int64_t* calls) {
+  g_msg.clear();
+  sg_status s = check_plan(p);
+  if (s != SG_OK) return s;
+  if (!ms) return fail(SG_ERR_ARG, "ms is NULL");
+  hipError_t e = hipStreamSynchronize(p->st);
+  if (e != hipSuccess) return hip_check(p, e, "timing sync");
+  ms[0] = ms[1] = ms[2] = 0.0;
+  for (size_t i = 0; i + 3 < p->ev.size(); i += 4)
+    for (int k = 0; k < 3; ++k) {
+      float t = 0.0f;
+      e = hipEventElapsedTime(&t, p->ev[i + k], p->ev[i + k + 1]);
+      if (e != hipSuccess) return hip_check(p, e, "hipEventElapsedTime");
+      ms[k] += (double)t;
+    }
+  if (calls) *calls = p->timed_calls;
+  drop_events(p);
   return SG_OK;
 }
 

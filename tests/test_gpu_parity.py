@@ -130,7 +130,11 @@ def test_forces_full_size_sparse_impulses(k, n):
     C = np.zeros((N, M))
     np.add.at(C, (sj, si), sc)
     sigma = oracle.bspline_apply(C, k)
-    cells = workloads.sample_cells(200 + k, M, N, 200, extra=[int(sj[0]) * M + int(si[0])])
+    # sampled cells plus every impulse's neighbourhood, where max|F| lies, so
+    # that the scale of the relative error is the field's max|F|
+    near = [int(min(max(b + db, 0), N - 1)) * M + int(min(max(a + da, 0), M - 1))
+            for a, b in zip(si, sj) for da in (-1, 0, 1) for db in (-1, 0, 1)]
+    cells = workloads.sample_cells(200 + k, M, N, 200, extra=near)
     rx, ry = oracle.forces_sparse(k, 2.0 / M, 2.0 / N, M, si, sj, sc, cells)
     scale = max(np.abs(rx).max(), np.abs(ry).max())
     for prec, tol in ((sg.SG_FP64, FP64_TOL), (sg.SG_FP32_SPLIT, FP32_TOL)):
