@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--k", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--prec", choices=["both", "fp32", "fp64"], default="both",
+                    help="both (default, the metric) or one path only (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -136,6 +138,11 @@ def main():
     xs = -1.0 + h * (off + np.arange(n))
     sigma = workloads.clump_sigma(workloads.clump_params(2, 32), xs, xs)
 
+    if args.prec != "both":
+        prec = sg.SG_FP32_SPLIT if args.prec == "fp32" else sg.SG_FP64
+        ms, passes, plan_s, _ = time_plan(sg, torch, grid, prec, sigma, args.steps, args.warmup)
+        print(json.dumps({"prec": args.prec, "ms_per_step": ms, "pass_ms": passes, "plan_s": plan_s}), flush=True)
+        return
     ms64, pass64, plan64, (gx, gy) = time_plan(sg, torch, grid, sg.SG_FP64, sigma, args.steps, args.warmup)
     ms32, pass32, plan32, (fx, fy) = time_plan(sg, torch, grid, sg.SG_FP32_SPLIT, sigma, args.steps, args.warmup)
     scale = max(np.abs(gx).max(), np.abs(gy).max())

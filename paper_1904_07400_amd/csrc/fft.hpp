@@ -144,16 +144,24 @@ __device__ __forceinline__ void dft(cx<R>* v) {
 }
 
 // ----------------------------------------------------------- radix plan --
-// Stages for length L with E elements per thread: radix E while it fits,
-// then the remainder (a power of two dividing E).
+// Stages for length L with E elements per thread: radix R0 = min(E, 16)
+// while it fits, then the remainder (a power of two dividing R0); each
+// thread runs E / radix butterflies per stage.
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 template <int L, int E>
 struct plan {
-  static constexpr int nfull = ilog2c(L) / ilog2c(E);
-  static constexpr int rem = L >> (nfull * ilog2c(E));  // 1 if exact
+  static constexpr int R0 = E < 16 ? E : 16;
+  static constexpr int nfull = ilog2c(L) / ilog2c(R0);
+  static constexpr int rem = L >> (nfull * ilog2c(R0));  // 1 if exact
   static constexpr int nstages = nfull + (rem > 1 ? 1 : 0);
-  static constexpr int radix(int s) { return s < nfull ? E : rem; }
+  static constexpr int radix(int s) { return s < nfull ? R0 : rem; }
   static constexpr int ns_before(int s) { return s == 0 ? 1 : ns_before(s - 1) * radix(s - 1); }
+  // per-stage twiddle tables, stage s >= 1: entry (q-1)*Ns + k holds
+  // w_{Ns r}^{k q}, q in [1, r), k in [0, Ns); tables laid end to end
+  static constexpr int tw_offset(int s) {
+    return s <= 1 ? 0 : tw_offset(s - 1) + (radix(s - 1) - 1) * ns_before(s - 1);
+  }
+  static constexpr int tw_size = tw_offset(nstages);
 };
 
 // LDS padding against bank conflicts: one slot every 16 elements
@@ -174,9 +182,11 @@ struct roots_t {
 
 // One Stockham stage.  v: E registers (strided distribution).  Unless this
 // is the last stage, the result is exchanged through lds (L padded slots)
-// and v again holds the strided distribution of the stage output.
+// and v again holds the strided distribution of the stage output.  tw: the
+// stage's twiddle table (see plan::tw_offset): consecutive butterflies read
+// consecutive entries.
 template <bool INV, int L, int T, int r, int Ns, typename R>
-__device__ __forceinline__ void stockham_stage(cx<R>* v, cx<R>* lds, roots_t<R> w, int t) {
+__device__ __forceinline__ void stockham_stage(cx<R>* v, cx<R>* lds, const cx<R>* __restrict__ tw, int t) {
   constexpr int E = L / T;
   constexpr int NB = E / r;
   constexpr bool last = (Ns * r == L);
@@ -187,12 +197,11 @@ __device__ __forceinline__ void stockham_stage(cx<R>* v, cx<R>* lds, roots_t<R> 
 #pragma unroll
     for (int q = 0; q < r; ++q) a[q] = v[u + q * NB];
     if constexpr (Ns > 1) {
-      const int k = b % Ns;
-      constexpr int step = L / (Ns * r);
+      const int k = b & (Ns - 1);
 #pragma unroll
       for (int q = 1; q < r; ++q) {
-        cx<R> tw = w(k * q * step);
-        a[q] = INV ? cmulc(a[q], tw) : cmul(a[q], tw);
+        const cx<R> w = tw[(q - 1) * Ns + k];
+        a[q] = INV ? cmulc(a[q], w) : cmul(a[q], w);
       }
     }
     dft<r, INV>(a);
@@ -201,7 +210,7 @@ __device__ __forceinline__ void stockham_stage(cx<R>* v, cx<R>* lds, roots_t<R> 
 #pragma unroll
       for (int q = 0; q < r; ++q) v[u + q * NB] = a[q];
     } else {
-      const int base = (b / Ns) * Ns * r + (b % Ns);
+      const int base = (b / Ns) * Ns * r + (b & (Ns - 1));
 #pragma unroll
       for (int q = 0; q < r; ++q) lds[pad(base + q * Ns)] = a[q];
     }
@@ -215,20 +224,36 @@ __device__ __forceinline__ void stockham_stage(cx<R>* v, cx<R>* lds, roots_t<R> 
 }
 
 template <bool INV, int L, int T, int S, typename R>
-__device__ __forceinline__ void fft_stages(cx<R>* v, cx<R>* lds, roots_t<R> w, int t) {
+__device__ __forceinline__ void fft_stages(cx<R>* v, cx<R>* lds, const cx<R>* __restrict__ tw, int t) {
   using P = plan<L, L / T>;
   if constexpr (S < P::nstages) {
-    stockham_stage<INV, L, T, P::radix(S), P::ns_before(S)>(v, lds, w, t);
-    fft_stages<INV, L, T, S + 1>(v, lds, w, t);
+    stockham_stage<INV, L, T, P::radix(S), P::ns_before(S)>(v, lds, tw + P::tw_offset(S), t);
+    fft_stages<INV, L, T, S + 1>(v, lds, tw, t);
   }
 }
 
-// Full length-L transform (unnormalised; INV uses the conjugate roots).
-// All threads of the workgroup must call it (it contains barriers).
+// Full length-L transform (unnormalised; INV uses the conjugate twiddles).
+// tw: the stage tables of plan<L, L/T>.  All threads of the workgroup must
+// call it (it contains barriers).
 template <bool INV, int L, int T, typename R>
-__device__ __forceinline__ void fft(cx<R>* v, cx<R>* lds, roots_t<R> w, int t) {
+__device__ __forceinline__ void fft(cx<R>* v, cx<R>* lds, const cx<R>* __restrict__ tw, int t) {
   static_assert(L % T == 0, "L must be a multiple of T");
-  fft_stages<INV, L, T, 0>(v, lds, w, t);
+  fft_stages<INV, L, T, 0>(v, lds, tw, t);
+}
+
+// Fill the stage tables of plan<L, E> from a table of roots of unity
+// (roots(i) = exp(-2 pi i * i / L)); one thread per entry.
+template <int L, int E, typename R>
+__device__ __forceinline__ void build_stage_twiddles(roots_t<R> roots, cx<R>* out, int idx) {
+  using P = plan<L, E>;
+#pragma unroll 1
+  for (int s = 1; s < P::nstages; ++s) {
+    const int r = P::radix(s), Ns = P::ns_before(s), off = P::tw_offset(s);
+    if (idx >= off && idx < off + (r - 1) * Ns) {
+      const int q = (idx - off) / Ns + 1, k = (idx - off) % Ns;
+      out[idx] = roots(k * q * (L / (Ns * r)));
+    }
+  }
 }
 
 }  // namespace sg

@@ -100,6 +100,9 @@ struct GridPlan {
   void* V = nullptr;
   const void* r2m = nullptr;
   const void* r2n = nullptr;
+  void* twA = nullptr;  // stage twiddles: forward rows, columns, inverse rows
+  void* twB = nullptr;
+  void* twC = nullptr;
 };
 
 }  // namespace
@@ -151,6 +154,16 @@ sg_status upload_roots(sg_plan p, int B, void** out) {
   return hip_check(p, hipMemcpy(*out, h.data(), h.size() * sizeof(R), hipMemcpyHostToDevice), "hipMemcpy roots");
 }
 
+// Stage twiddle table of one pass (see sg_twiddles), allocated in the plan.
+sg_status make_twiddles(sg_plan p, int prec, int pass, int len, const void* roots, void** out) {
+  const int n = sg_twiddles(prec, pass, len, nullptr, nullptr, p->st);
+  if (n < 0) return fail(SG_ERR_UNSUPPORTED, "no FFT kernel for length %d", len);
+  sg_status s = dev_alloc(p, out, (size_t)(prec == 0 ? 16 : 8) * (size_t)(n > 0 ? n : 1));
+  if (s != SG_OK) return s;
+  sg_twiddles(prec, pass, len, roots, *out, p->st);
+  return hip_check(p, hipGetLastError(), "twiddle table");
+}
+
 void drop_events(sg_plan p) {
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
   p->ev.clear();
@@ -182,6 +195,10 @@ sg_status check_plan(sg_plan p) {
 // Weight spectra of one grid (plan time, FP64 throughout).
 sg_status build_spectra(sg_plan p, GridPlan& G, const void* r2m64, const void* r2n64) {
   const int M = G.M, N = G.N;
+  void *twA64 = nullptr, *twS64 = nullptr;
+  sg_status ts = make_twiddles(p, 0, 0, M, r2m64, &twA64);
+  if (ts == SG_OK) ts = make_twiddles(p, 0, 3, N, r2n64, &twS64);
+  if (ts != SG_OK) return ts;
   double* wp = nullptr;
   void* S = nullptr;
   hipError_t e = hipMalloc((void**)&wp, sizeof(double) * 2 * (size_t)(2 * M) * (2 * N));
@@ -201,10 +218,10 @@ sg_status build_spectra(sg_plan p, GridPlan& G, const void* r2m64, const void* r
   const double scale = 1.0 / (4.0 * (double)M * (double)N);
   sg_status st = SG_OK;
   e = sg_launch_weights(G.k, G.hx, G.hy, M, N, wpx, wpy, 0, p->st);
-  if (e == hipSuccess) e = sg_launch_row_fwd(0, M, wpx, 2 * M, S, 2 * N, r2m64, 0, 1, p->st);
-  if (e == hipSuccess) e = sg_launch_spec_col(N, S, M, G.tabx, G.kind, fp32, scale, r2n64, p->st);
-  if (e == hipSuccess) e = sg_launch_row_fwd(0, M, wpy, 2 * M, S, 2 * N, r2m64, 0, 1, p->st);
-  if (e == hipSuccess) e = sg_launch_spec_col(N, S, M, G.taby, G.kind, fp32, scale, r2n64, p->st);
+  if (e == hipSuccess) e = sg_launch_row_fwd(0, M, wpx, 2 * M, S, 2 * N, r2m64, 0, 1, twA64, p->st);
+  if (e == hipSuccess) e = sg_launch_spec_col(N, S, M, G.tabx, G.kind, fp32, scale, r2n64, twS64, p->st);
+  if (e == hipSuccess) e = sg_launch_row_fwd(0, M, wpy, 2 * M, S, 2 * N, r2m64, 0, 1, twA64, p->st);
+  if (e == hipSuccess) e = sg_launch_spec_col(N, S, M, G.taby, G.kind, fp32, scale, r2n64, twS64, p->st);
   if (e == hipSuccess) e = hipStreamSynchronize(p->st);
   if (e != hipSuccess) st = hip_check(p, e, "plan-time spectrum");
   (void)hipFree(wp);
@@ -305,7 +322,11 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
     if (s == SG_OK) {
       G.r2m = p->roots[2 * G.M];
       G.r2n = p->roots[2 * G.N];
-      s = build_spectra(p, G, roots64[2 * G.M], roots64[2 * G.N]);
+      const int pc = prec == SG_FP64 ? 0 : 1;
+      s = make_twiddles(p, pc, 0, G.M, G.r2m, &G.twA);
+      if (s == SG_OK) s = make_twiddles(p, pc, 1, G.N, G.r2n, &G.twB);
+      if (s == SG_OK) s = make_twiddles(p, pc, 2, G.M, G.r2m, &G.twC);
+      if (s == SG_OK) s = build_spectra(p, G, roots64[2 * G.M], roots64[2 * G.N]);
     }
     p->grids.push_back(G);
   }
@@ -418,11 +439,14 @@ sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy) {
     char* oy = (char*)fy + el * G.off;
     const int solve = G.k == 3 ? 1 : 0;
     hipError_t e = mark(p);
-    if (e == hipSuccess) e = sg_launch_row_fwd(prec, G.M, src, G.M, G.X, G.N, G.r2m, solve, 0, p->st);
+    if (e == hipSuccess) e = sg_launch_row_fwd(prec, G.M, src, G.M, G.X, G.N, G.r2m, solve, 0, G.twA, p->st);
     if (e == hipSuccess) e = mark(p);
-    if (e == hipSuccess) e = sg_launch_col(prec, G.N, G.X, G.V, G.M, G.tabx, G.taby, G.kind, G.r2n, solve, p->st);
+    if (e == hipSuccess)
+      e = sg_launch_col(prec, G.N, G.X, G.V, G.M, sg_row_tile(prec, G.M, G.N), G.tabx, G.taby, G.kind, G.r2n, solve,
+                        G.twB, p->st);
     if (e == hipSuccess) e = mark(p);
-    if (e == hipSuccess) e = sg_launch_row_inv(prec, G.M, G.V, ox, oy, G.N, G.r2m, p->st);
+    if (e == hipSuccess)
+      e = sg_launch_row_inv(prec, G.M, G.V, ox, oy, G.N, sg_row_tile(prec, G.M, G.N), G.r2m, G.twC, p->st);
     if (e == hipSuccess) e = mark(p);
     if (e != hipSuccess) return hip_check(p, e, "force launch");
   }

@@ -7,14 +7,23 @@
 hipError_t sg_set_gl_tables(const double* x /*4x16*/, const double* w /*4x16*/);
 hipError_t sg_launch_weights(int k, double hx, double hy, int M, int N, double* wx, double* wy, int layout,
                              hipStream_t st);
+// tw: stage twiddle tables of the pass (sg_twiddles)
 hipError_t sg_launch_row_fwd(int prec, int M, const void* src, int64_t ld, void* X, int nrows, const void* r2m,
-                             int solve, int full, hipStream_t st);
-hipError_t sg_launch_col(int prec, int N, const void* X, void* V, int M, const void* tx, const void* ty, int kind,
-                         const void* r2n, int solve, hipStream_t st);
-hipError_t sg_launch_row_inv(int prec, int M, const void* V, void* fx, void* fy, int nrows, const void* r2m,
-                             hipStream_t st);
+                             int solve, int full, const void* tw, hipStream_t st);
+// X: column-major row spectra (bin p of row j at X[p*N + j]); V: tiles of
+// tj rows (sg_row_tile), the layout the inverse row pass reads
+hipError_t sg_launch_col(int prec, int N, const void* X, void* V, int M, int tj, const void* tx, const void* ty,
+                         int kind, const void* r2n, int solve, const void* tw, hipStream_t st);
+int sg_row_tile(int prec, int M, int N);
+hipError_t sg_launch_row_inv(int prec, int M, const void* V, void* fx, void* fy, int nrows, int tj, const void* r2m,
+                             const void* tw, hipStream_t st);
 hipError_t sg_launch_spec_col(int N, const void* S, int M, void* tab, int kind, int fp32, double scale,
-                              const void* r2n, hipStream_t st);
+                              const void* r2n, const void* tw, hipStream_t st);
+// Stage twiddle tables of a pass's FFT (pass 0: forward rows, 1: columns,
+// 2: inverse rows, 3: spectrum columns, FP64 only); len = M or N; roots =
+// the 2*len-th roots in the pass precision.  Returns the entry count (out ==
+// NULL) or fills out on st; -1 for an unsupported size.
+int sg_twiddles(int prec, int pass, int len, const void* roots, void* out, hipStream_t st);
 hipError_t sg_launch_check_finite(int prec, const void* x, int64_t n, int* flag, hipStream_t st);
 hipError_t sg_launch_coeff_rows(int prec, int M, const void* src, void* dst, int nrows, hipStream_t st);
 hipError_t sg_launch_coeff_cols(int prec, int N, void* data, int M, hipStream_t st);

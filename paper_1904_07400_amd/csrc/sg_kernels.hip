@@ -20,6 +20,35 @@
 #include "sg_internal.h"
 #include "tridiag.hpp"
 
+// Launch-shape knobs (compile-time; elements per thread E and threads per
+// workgroup of each pass).  Defaults are the measured best on MI355X.
+#ifndef SG_RF_THREADS
+#define SG_RF_THREADS 256
+#endif
+#ifndef SG_RI_THREADS
+#define SG_RI_THREADS 256
+#endif
+#ifndef SG_RI_E32
+#define SG_RI_E32 16
+#endif
+#ifndef SG_RI_E64
+#define SG_RI_E64 16
+#endif
+#ifndef SG_COL_E32
+#define SG_COL_E32 8
+#endif
+// rows per tile of the column pass's output (its store segments hold
+// SG_TJ consecutive rows of one column)
+#ifndef SG_TJ32
+#define SG_TJ32 4
+#endif
+#ifndef SG_TJ64
+#define SG_TJ64 2
+#endif
+#ifndef SG_COL_E64
+#define SG_COL_E64 8
+#endif
+
 namespace sg {
 
 // ------------------------------------------------------------- weights --
@@ -157,30 +186,40 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // Real FFT of length 2M of a row whose upper half is zero (or, with full,
 // of a row of 2M values), via the complex FFT of length M of
 // z[n] = x[2n] + i x[2n+1], itself split into its even and odd output bins
-// (two FFTs of length M/2).  Output: M packed bins, bin 0 = (X_0, X_M).
-// Row r of src starts at src + r*src_ld; row r of X at X + r*M.
+// (two FFTs of length M/2).  Output: M packed bins, bin 0 = (X_0, X_M),
+// stored column-major (bin p of row r at X[p*ldx + r]) so that the column
+// pass reads whole columns.  G rows per workgroup; the transposed store
+// goes through LDS so that each bin's G consecutive rows leave as one
+// contiguous segment.
+constexpr int kLdsBudget = 144 * 1024;
+
 template <typename R, typename In, int M>
 struct rowfwd_cfg {
   static constexpr int L = M / 2;
   static constexpr int E = (sizeof(R) == 4 ? 16 : 8) < L ? (sizeof(R) == 4 ? 16 : 8) : L;
   static constexpr int T = L / E;
-  static constexpr int G = T >= 256 ? 1 : 256 / T;
   static constexpr int LL = lds_len<L>::value;
   // per-row LDS slot (complex elements): FFT exchange buffer, also used
   // for the reduced system of the x-solve
   static constexpr int TRI = (int)(sizeof(tri_smem<double, T>) / sizeof(cx<R>)) + 1;
   static constexpr int SLOT = LL > TRI ? LL : TRI;
+  static constexpr int G0 = SG_RF_THREADS / T < 1 ? 1 : (SG_RF_THREADS / T < 16 ? SG_RF_THREADS / T : 16);
+  static constexpr int GL = kLdsBudget / (SLOT * (int)sizeof(cx<R>));
+  static constexpr int G = (G0 < GL ? G0 : GL) < 1 ? 1 : (G0 < GL ? G0 : GL);
+  // e-values per transposed-store chunk (2T bins per e, G rows)
+  static constexpr int EC = (SLOT / (2 * T)) < 1 ? 1 : ((SLOT / (2 * T)) > E ? E : SLOT / (2 * T));
 };
 
 template <typename R, typename In, int M>
 __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M>::T))
-    k_row_fwd(const In* __restrict__ src, int64_t src_ld, cx<R>* __restrict__ X, int nrows,
-              const cx<R>* __restrict__ r2m, int solve, int full) {
+    k_row_fwd(const In* __restrict__ src, int64_t src_ld, cx<R>* __restrict__ X, int ldx, int nrows,
+              const cx<R>* __restrict__ r2m, int solve, int full, const cx<R>* __restrict__ tw) {
   using C = rowfwd_cfg<R, In, M>;
-  constexpr int L = C::L, E = C::E, T = C::T, G = C::G, SLOT = C::SLOT;
-  __shared__ cx<R> smem[G * SLOT];
+  constexpr int L = C::L, E = C::E, T = C::T, SLOT = C::SLOT, EC = C::EC;
+  __shared__ cx<R> smem[C::G * SLOT];
+  const int G = blockDim.x / T;  // rows per workgroup (<= C::G)
   const int g = threadIdx.x / T, t = threadIdx.x % T;
-  const int row = blockIdx.x * G + g;
+  const int row0 = xcd_tile(blockIdx.x, gridDim.x) * G, row = row0 + g;
   const bool active = row < nrows;
   cx<R>* lds = smem + g * SLOT;
   const In* s = src + (int64_t)(active ? row : 0) * src_ld;
@@ -205,7 +244,6 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
       ze[e] = active ? cx<R>{(R)s[2 * n], (R)s[2 * n + 1]} : cx<R>{0, 0};
     }
   }
-  const roots_t<R> wl{r2m, 4};  // L-th roots
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int n = t + e * T;
@@ -218,7 +256,7 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
     zo[e] = cmul(lo, r2m[2 * n]);  // w_M^n
   }
   // even bins of Z
-  fft<false, L, T>(ze, lds, wl, t);
+  fft<false, L, T>(ze, lds, tw, t);
   cx<R> xe[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = ze[e];
@@ -233,28 +271,42 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
   }
   __syncthreads();
   // odd bins of Z
-  fft<false, L, T>(zo, lds, wl, t);
+  fft<false, L, T>(zo, lds, tw, t);
 #pragma unroll
   for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = zo[e];
   __syncthreads();
-  cx<R>* out = X + (int64_t)(active ? row : 0) * M;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int pp = t + e * T;                         // X bin p = 2 pp + 1
     const cx<R> zp = zo[e], zm = conj(lds[pad(L - 1 - pp)]);
     const cx<R> sum = zp + zm, dif = cmul(r2m[2 * pp + 1], zp - zm);
-    const cx<R> xo{(R)0.5 * (sum.x + dif.y), (R)0.5 * (sum.y - dif.x)};
-    if (active) {
-      out[2 * pp] = xe[e];
-      out[2 * pp + 1] = xo;
+    zo[e] = cx<R>{(R)0.5 * (sum.x + dif.y), (R)0.5 * (sum.y - dif.x)};
+  }
+  __syncthreads();
+  // transposed store: chunk of EC e-values = bins [2 e0 T, 2 (e0+EC) T) of all G rows
+#pragma unroll
+  for (int e0 = 0; e0 < E; e0 += EC) {
+#pragma unroll
+    for (int e = e0; e < e0 + EC && e < E; ++e) {
+      const int pl = 2 * (t + (e - e0) * T);
+      smem[pl * G + g] = xe[e];
+      smem[(pl + 1) * G + g] = zo[e];
     }
+    __syncthreads();
+    const int nchunk = 2 * T * (E - e0 < EC ? E - e0 : EC) * G;
+    for (int idx = threadIdx.x; idx < nchunk; idx += blockDim.x) {
+      const int pl = idx / G, gg = idx % G;
+      if (row0 + gg < nrows) X[(int64_t)(2 * e0 * T + pl) * ldx + row0 + gg] = smem[idx];
+    }
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------- pass B --
 template <typename R, int N>
 struct col_cfg {
-  static constexpr int E = sizeof(R) == 4 ? (N < 16 ? N : 16) : (N < 8 ? N : (N >= 8192 ? 16 : 8));
+  static constexpr int E0 = sizeof(R) == 4 ? SG_COL_E32 : (N >= 8192 ? 2 * SG_COL_E64 : SG_COL_E64);
+  static constexpr int E = N < E0 ? N : E0;
   static constexpr int T = N / E;
   static constexpr int LL = lds_len<N>::value;
   static constexpr int TRI = (int)(sizeof(tri_smem<double2, T>) / sizeof(cx<R>)) + 1;
@@ -348,9 +400,9 @@ __device__ __forceinline__ void col_products(const cx<R>* f, cx<R>* gx, cx<R>* g
 
 template <typename R, typename TO, typename TC, int N>
 __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
-    k_col(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, const TO* __restrict__ tox,
+    k_col(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
           const TO* __restrict__ toy, const TC* __restrict__ tcx, const TC* __restrict__ tcy,
-          const cx<R>* __restrict__ r2n, int solve, int kind) {
+          const cx<R>* __restrict__ r2n, int solve, int kind, const cx<R>* __restrict__ tw) {
   using C = col_cfg<R, N>;
   constexpr int E = C::E, T = C::T, LL = C::SLOT;
   __shared__ cx<R> smem[C::P * LL];
@@ -359,34 +411,28 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int c0 = tile * P, c = c0 + g;
   cx<R>* lds = smem + g * LL;
-  // coalesced tile load: P adjacent columns, row by row
-#pragma unroll
-  for (int s = 0; s < E; ++s) {
-    const int l = threadIdx.x + s * P * T;
-    const int j = l / P, cc = l % P;
-    smem[cc * LL + pad(j)] = X[(int64_t)j * M + c0 + cc];
-  }
-  __syncthreads();
+  const cx<R>* col = X + (int64_t)c * N;  // column c, contiguous (column-major X)
   cx<R> a[E];
   if (solve) {
-    // y-solve of Eq. (z_system) on the complex row spectra, FP64
+    // y-solve of Eq. (z_system) on the complex row spectra, FP64, chunk of E per thread
     double2 d[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const cx<R> v = lds[pad(t * E + e)];
+      const cx<R> v = col[t * E + e];
       d[e] = make_double2(8.0 * (double)v.x, 8.0 * (double)v.y);
     }
-    __syncthreads();
     tri_solve<E, T, double2>(d, t, *reinterpret_cast<tri_smem<double2, T>*>(lds));
 #pragma unroll
     for (int e = 0; e < E; ++e) lds[pad(t * E + e)] = cx<R>{(R)d[e].x, (R)d[e].y};
     __syncthreads();
-  }
 #pragma unroll
-  for (int e = 0; e < E; ++e) a[e] = lds[pad(t + e * T)];
-  __syncthreads();
+    for (int e = 0; e < E; ++e) a[e] = lds[pad(t + e * T)];
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) a[e] = col[t + e * T];
+  }
 
-  const roots_t<R> wn{r2n, 2};  // N-th roots
   const bool packed = (c == 0);
   // forward transform of the column zero-padded to 2N: even bins
   // fe = FFT_N(a), odd bins fo = FFT_N(a_j w_2N^j)
@@ -396,16 +442,16 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     fo[e] = cmul(a[e], r2n[t + e * T]);
     fe[e] = a[e];
   }
-  fft<false, N, T>(fe, lds, wn, t);
-  fft<false, N, T>(fo, lds, wn, t);
+  fft<false, N, T>(fe, lds, tw, t);
+  fft<false, N, T>(fo, lds, tw, t);
   cx<R> accx[E], accy[E];
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
     const cx<R>* f = half ? fo : fe;
     cx<R> gx[E], gy[E];
     col_products<R, TO, TC, N, E, T>(f, gx, gy, half, c0 == 0, packed, lds, kind, tox, toy, tcx, tcy, c, M, t);
-    fft<true, N, T>(gx, lds, wn, t);
-    fft<true, N, T>(gy, lds, wn, t);
+    fft<true, N, T>(gx, lds, tw, t);
+    fft<true, N, T>(gy, lds, tw, t);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       if (half == 0) {
@@ -420,63 +466,70 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
   }
   // V(c) = Yx + i Yy and V(2M - c) = conj(Yx) + i conj(Yy); the packed
   // column gives V(0) = Re Yx + i Re Yy and V(M) = Im Yx + i Im Yy.
+  // V is stored in tiles of tj rows: V(p, j) at ((jb*2 + (p&1))*M + p/2)*tj + jj,
+  // jb = j / tj, jj = j % tj, which the row pass reads contiguously.
+  const int pa = c, pb = packed ? M : 2 * M - c;
+  cx<R>* va = V + (int64_t)(pa & 1) * M * tj + (int64_t)(pa >> 1) * tj;
+  cx<R>* vb = V + (int64_t)(pb & 1) * M * tj + (int64_t)(pb >> 1) * tj;
+  const int64_t jstride = (int64_t)2 * M * tj;
 #pragma unroll
-  for (int pass = 0; pass < 2; ++pass) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const cx<R> yx = accx[e], yy = accy[e];
-      cx<R> v;
-      if (packed)
-        v = pass == 0 ? cx<R>{yx.x, yy.x} : cx<R>{yx.y, yy.y};
-      else
-        v = pass == 0 ? cx<R>{yx.x - yy.y, yx.y + yy.x} : cx<R>{yx.x + yy.y, yy.x - yx.y};
-      lds[pad(t + e * T)] = v;
+  for (int e = 0; e < E; ++e) {
+    const int j = t + e * T;
+    const cx<R> yx = accx[e], yy = accy[e];
+    cx<R> v1, v2;
+    if (packed) {
+      v1 = cx<R>{yx.x, yy.x};
+      v2 = cx<R>{yx.y, yy.y};
+    } else {
+      v1 = cx<R>{yx.x - yy.y, yx.y + yy.x};
+      v2 = cx<R>{yx.x + yy.y, yy.x - yx.y};
     }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < E; ++s) {
-      const int l = threadIdx.x + s * P * T;
-      const int j = l / P, cc = l % P;
-      const int cg = c0 + cc;
-      const int dst = pass == 0 ? cg : (cg == 0 ? M : 2 * M - cg);
-      V[(int64_t)j * (2 * M) + dst] = smem[cc * LL + pad(j)];
-    }
-    __syncthreads();
+    const int64_t o = (int64_t)(j / tj) * jstride + (j % tj);
+    va[o] = v1;
+    vb[o] = v2;
   }
 }
 
 // ---------------------------------------------------------------- pass C --
+// Rows j of the combined spectrum V: v = IFFT_2M(V) cropped to n < M via its
+// even and odd input bins (two inverse FFTs of length M); Fx = Re, Fy = Im.
+// V is stored in tiles of tj rows (element (p, j) at ((j/tj*2 + p%2)*M +
+// p/2)*tj + j%tj); each row loads its elements straight from the tile, and
+// the rows of one tile go to workgroups on the same XCD so that the tile's
+// cache lines are shared in its L2.
 template <typename R, int M>
 struct rowinv_cfg {
   static constexpr int L = M;
-  static constexpr int E = sizeof(R) == 4 ? (L < 16 ? L : 16) : (L < 8 ? L : (L >= 8192 ? 16 : 8));
+  static constexpr int E = sizeof(R) == 4 ? (L < SG_RI_E32 ? L : SG_RI_E32) : (L < SG_RI_E64 ? L : SG_RI_E64);
   static constexpr int T = L / E;
-  static constexpr int G = T >= 256 ? 1 : 256 / T;
   static constexpr int LL = lds_len<L>::value;
+  static constexpr int G0 = SG_RI_THREADS / T < 1 ? 1 : (SG_RI_THREADS / T < 16 ? SG_RI_THREADS / T : 16);
+  static constexpr int GL = kLdsBudget / (LL * (int)sizeof(cx<R>));
+  static constexpr int G = (G0 < GL ? G0 : GL) < 1 ? 1 : (G0 < GL ? G0 : GL);
 };
 
 template <typename R, typename Out, int M>
 __global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
-    k_row_inv(const cx<R>* __restrict__ V, Out* __restrict__ fx, Out* __restrict__ fy, int nrows,
-              const cx<R>* __restrict__ r2m) {
+    k_row_inv(const cx<R>* __restrict__ V, Out* __restrict__ fx, Out* __restrict__ fy, int nrows, int tj,
+              const cx<R>* __restrict__ r2m, const cx<R>* __restrict__ tw) {
   using C = rowinv_cfg<R, M>;
-  constexpr int E = C::E, T = C::T, G = C::G, LL = C::LL;
-  __shared__ cx<R> smem[G * LL];
+  constexpr int E = C::E, T = C::T, LL = C::LL;
+  __shared__ cx<R> smem[C::G * LL];
+  const int G = blockDim.x / T;  // rows per workgroup
   const int g = threadIdx.x / T, t = threadIdx.x % T;
-  const int row = blockIdx.x * G + g;
+  const int row = xcd_tile(blockIdx.x, gridDim.x) * G + g;
   const bool active = row < nrows;
   cx<R>* lds = smem + g * LL;
-  const cx<R>* v = V + (int64_t)(active ? row : 0) * (2 * M);
+  const int jb = (active ? row : 0) / tj, jj = (active ? row : 0) % tj;
   cx<R> ve[E], vo[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int p = t + e * T;
-    ve[e] = active ? v[2 * p] : cx<R>{0, 0};
-    vo[e] = active ? v[2 * p + 1] : cx<R>{0, 0};
+  for (int half = 0; half < 2; ++half) {
+    const cx<R>* base = V + ((int64_t)jb * 2 + half) * M * tj + jj;
+    cx<R>* v = half ? vo : ve;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = base[(int64_t)(t + e * T) * tj];
+    fft<true, M, T>(v, lds, tw, t);
   }
-  const roots_t<R> wm{r2m, 2};
-  fft<true, M, T>(ve, lds, wm, t);
-  fft<true, M, T>(vo, lds, wm, t);
   if (active) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -523,7 +576,7 @@ __device__ __forceinline__ void put_cplx(void* tab, int fp32, int64_t idx, cx<do
 template <int N>
 __global__ void __launch_bounds__((spec_cfg<N>::T))
     k_spec_col(const cx<double>* __restrict__ S, int M, void* __restrict__ tab, int kind, int fp32,
-               double scale, const cx<double>* __restrict__ r2n) {
+               double scale, const cx<double>* __restrict__ r2n, const cx<double>* __restrict__ tw) {
   using C = spec_cfg<N>;
   constexpr int E = C::E, T = C::T, LL = C::LL;
   __shared__ cx<double> lds[LL];
@@ -533,15 +586,14 @@ __global__ void __launch_bounds__((spec_cfg<N>::T))
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int j = t + e * T;
-    lo[e] = S[(int64_t)j * M + c];
-    hi[e] = S[(int64_t)(j + N) * M + c];
+    lo[e] = S[(int64_t)c * (2 * N) + j];
+    hi[e] = S[(int64_t)c * (2 * N) + j + N];
   }
-  const roots_t<double> wn{r2n, 2};
   for (int half = 0; half < 2; ++half) {
     cx<double> f[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) f[e] = half ? cmul(lo[e] - hi[e], r2n[t + e * T]) : lo[e] + hi[e];
-    fft<false, N, T>(f, lds, wn, t);
+    fft<false, N, T>(f, lds, tw, t);
 #pragma unroll
     for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = f[e];
     __syncthreads();
@@ -661,21 +713,24 @@ struct tabs {
   using cplx = typename std::conditional<sizeof(R) == 4, float4, double2>::type;
 };
 
+#ifndef SG_SIZES
 #define SG_SIZES(X) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
+#endif
 
 template <typename R, typename In, int M>
 static hipError_t launch_row_fwd_t(const In* src, int64_t src_ld, cx<R>* X, int nrows, const cx<R>* r2m,
-                                   int solve, int full, hipStream_t st) {
+                                   int solve, int full, const cx<R>* tw, hipStream_t st) {
   using C = rowfwd_cfg<R, In, M>;
-  const int blocks = (nrows + C::G - 1) / C::G;
-  hipLaunchKernelGGL((k_row_fwd<R, In, M>), dim3(blocks), dim3(C::G * C::T), 0, st, src, src_ld, X, nrows,
-                     r2m, solve, full);
+  const int G = C::G < nrows ? C::G : nrows;
+  const int blocks = (nrows + G - 1) / G;
+  hipLaunchKernelGGL((k_row_fwd<R, In, M>), dim3(blocks), dim3(G * C::T), 0, st, src, src_ld, X, nrows, nrows,
+                     r2m, solve, full, tw);
   return hipGetLastError();
 }
 
 template <typename R, int N>
-static hipError_t launch_col_t(const cx<R>* X, cx<R>* V, int M, const void* tx, const void* ty, int kind,
-                               const cx<R>* r2n, int solve, hipStream_t st) {
+static hipError_t launch_col_t(const cx<R>* X, cx<R>* V, int M, int tj, const void* tx, const void* ty, int kind,
+                               const cx<R>* r2n, int solve, const cx<R>* tw, hipStream_t st) {
   using C = col_cfg<R, N>;
   using TO = typename tabs<R>::odd;
   using TC = typename tabs<R>::cplx;
@@ -684,25 +739,26 @@ static hipError_t launch_col_t(const cx<R>* X, cx<R>* V, int M, const void* tx, 
   const TO* toy = kind == 0 ? (const TO*)ty : nullptr;
   const TC* tcx = kind == 1 ? (const TC*)tx : nullptr;
   const TC* tcy = kind == 1 ? (const TC*)ty : nullptr;
-  hipLaunchKernelGGL((k_col<R, TO, TC, N>), dim3(M / P), dim3(P * C::T), 0, st, X, V, M, tox, toy, tcx, tcy,
-                     r2n, solve, kind);
+  hipLaunchKernelGGL((k_col<R, TO, TC, N>), dim3(M / P), dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy,
+                     r2n, solve, kind, tw);
   return hipGetLastError();
 }
 
 template <typename R, typename Out, int M>
-static hipError_t launch_row_inv_t(const cx<R>* V, Out* fx, Out* fy, int nrows, const cx<R>* r2m,
-                                   hipStream_t st) {
+static hipError_t launch_row_inv_t(const cx<R>* V, Out* fx, Out* fy, int nrows, int tj, const cx<R>* r2m,
+                                   const cx<R>* tw, hipStream_t st) {
   using C = rowinv_cfg<R, M>;
-  const int blocks = (nrows + C::G - 1) / C::G;
-  hipLaunchKernelGGL((k_row_inv<R, Out, M>), dim3(blocks), dim3(C::G * C::T), 0, st, V, fx, fy, nrows, r2m);
+  const int G = C::G < nrows ? C::G : nrows;
+  const int blocks = (nrows + G - 1) / G;
+  hipLaunchKernelGGL((k_row_inv<R, Out, M>), dim3(blocks), dim3(G * C::T), 0, st, V, fx, fy, nrows, tj, r2m, tw);
   return hipGetLastError();
 }
 
 template <int N>
 static hipError_t launch_spec_col_t(const cx<double>* S, int M, void* tab, int kind, int fp32, double scale,
-                                    const cx<double>* r2n, hipStream_t st) {
+                                    const cx<double>* r2n, const cx<double>* tw, hipStream_t st) {
   using C = spec_cfg<N>;
-  hipLaunchKernelGGL((k_spec_col<N>), dim3(M), dim3(C::T), 0, st, S, M, tab, kind, fp32, scale, r2n);
+  hipLaunchKernelGGL((k_spec_col<N>), dim3(M), dim3(C::T), 0, st, S, M, tab, kind, fp32, scale, r2n, tw);
   return hipGetLastError();
 }
 
@@ -728,11 +784,11 @@ hipError_t sg_set_gl_tables(const double* x, const double* w) {
 
 template <typename R, typename In>
 static hipError_t row_fwd_dispatch(int M, const In* src, int64_t ld, cx<R>* X, int nrows, const cx<R>* r2m,
-                                   int solve, int full, hipStream_t st) {
+                                   int solve, int full, const cx<R>* tw, hipStream_t st) {
   switch (M) {
 #define CASE(SZ) \
   case SZ:       \
-    return launch_row_fwd_t<R, In, SZ>(src, ld, X, nrows, r2m, solve, full, st);
+    return launch_row_fwd_t<R, In, SZ>(src, ld, X, nrows, r2m, solve, full, tw, st);
     SG_SIZES(CASE)
 #undef CASE
     default:
@@ -741,12 +797,12 @@ static hipError_t row_fwd_dispatch(int M, const In* src, int64_t ld, cx<R>* X, i
 }
 
 template <typename R>
-static hipError_t col_dispatch(int N, const cx<R>* X, cx<R>* V, int M, const void* tx, const void* ty, int kind,
-                               const cx<R>* r2n, int solve, hipStream_t st) {
+static hipError_t col_dispatch(int N, const cx<R>* X, cx<R>* V, int M, int tj, const void* tx, const void* ty,
+                               int kind, const cx<R>* r2n, int solve, const cx<R>* tw, hipStream_t st) {
   switch (N) {
 #define CASE(SZ) \
   case SZ:       \
-    return launch_col_t<R, SZ>(X, V, M, tx, ty, kind, r2n, solve, st);
+    return launch_col_t<R, SZ>(X, V, M, tj, tx, ty, kind, r2n, solve, tw, st);
     SG_SIZES(CASE)
 #undef CASE
     default:
@@ -755,12 +811,12 @@ static hipError_t col_dispatch(int N, const cx<R>* X, cx<R>* V, int M, const voi
 }
 
 template <typename R, typename Out>
-static hipError_t row_inv_dispatch(int M, const cx<R>* V, Out* fx, Out* fy, int nrows, const cx<R>* r2m,
-                                   hipStream_t st) {
+static hipError_t row_inv_dispatch(int M, const cx<R>* V, Out* fx, Out* fy, int nrows, int tj, const cx<R>* r2m,
+                                   const cx<R>* tw, hipStream_t st) {
   switch (M) {
 #define CASE(SZ) \
   case SZ:       \
-    return launch_row_inv_t<R, Out, SZ>(V, fx, fy, nrows, r2m, st);
+    return launch_row_inv_t<R, Out, SZ>(V, fx, fy, nrows, tj, r2m, tw, st);
     SG_SIZES(CASE)
 #undef CASE
     default:
@@ -769,38 +825,45 @@ static hipError_t row_inv_dispatch(int M, const cx<R>* V, Out* fx, Out* fy, int 
 }
 
 hipError_t sg_launch_row_fwd(int prec, int M, const void* src, int64_t ld, void* X, int nrows, const void* r2m,
-                             int solve, int full, hipStream_t st) {
+                             int solve, int full, const void* tw, hipStream_t st) {
   if (prec == 0)
     return row_fwd_dispatch<double, double>(M, (const double*)src, ld, (cx<double>*)X, nrows,
-                                            (const cx<double>*)r2m, solve, full, st);
+                                            (const cx<double>*)r2m, solve, full, (const cx<double>*)tw, st);
   return row_fwd_dispatch<float, float>(M, (const float*)src, ld, (cx<float>*)X, nrows, (const cx<float>*)r2m,
-                                        solve, full, st);
+                                        solve, full, (const cx<float>*)tw, st);
 }
 
-hipError_t sg_launch_col(int prec, int N, const void* X, void* V, int M, const void* tx, const void* ty, int kind,
-                         const void* r2n, int solve, hipStream_t st) {
+hipError_t sg_launch_col(int prec, int N, const void* X, void* V, int M, int tj, const void* tx, const void* ty,
+                         int kind, const void* r2n, int solve, const void* tw, hipStream_t st) {
   if (prec == 0)
-    return col_dispatch<double>(N, (const cx<double>*)X, (cx<double>*)V, M, tx, ty, kind, (const cx<double>*)r2n,
-                                solve, st);
-  return col_dispatch<float>(N, (const cx<float>*)X, (cx<float>*)V, M, tx, ty, kind, (const cx<float>*)r2n, solve,
-                             st);
+    return col_dispatch<double>(N, (const cx<double>*)X, (cx<double>*)V, M, tj, tx, ty, kind,
+                                (const cx<double>*)r2n, solve, (const cx<double>*)tw, st);
+  return col_dispatch<float>(N, (const cx<float>*)X, (cx<float>*)V, M, tj, tx, ty, kind, (const cx<float>*)r2n,
+                             solve, (const cx<float>*)tw, st);
 }
 
-hipError_t sg_launch_row_inv(int prec, int M, const void* V, void* fx, void* fy, int nrows, const void* r2m,
-                             hipStream_t st) {
+int sg_row_tile(int prec, int M, int N) {
+  (void)M;
+  const int tj = prec == 0 ? SG_TJ64 : SG_TJ32;
+  return tj < N ? tj : N;
+}
+
+hipError_t sg_launch_row_inv(int prec, int M, const void* V, void* fx, void* fy, int nrows, int tj, const void* r2m,
+                             const void* tw, hipStream_t st) {
   if (prec == 0)
-    return row_inv_dispatch<double, double>(M, (const cx<double>*)V, (double*)fx, (double*)fy, nrows,
-                                            (const cx<double>*)r2m, st);
-  return row_inv_dispatch<float, float>(M, (const cx<float>*)V, (float*)fx, (float*)fy, nrows,
-                                        (const cx<float>*)r2m, st);
+    return row_inv_dispatch<double, double>(M, (const cx<double>*)V, (double*)fx, (double*)fy, nrows, tj,
+                                            (const cx<double>*)r2m, (const cx<double>*)tw, st);
+  return row_inv_dispatch<float, float>(M, (const cx<float>*)V, (float*)fx, (float*)fy, nrows, tj,
+                                        (const cx<float>*)r2m, (const cx<float>*)tw, st);
 }
 
 hipError_t sg_launch_spec_col(int N, const void* rowspec, int M, void* tab, int kind, int fp32, double scale,
-                              const void* r2n, hipStream_t st) {
+                              const void* r2n, const void* tw, hipStream_t st) {
   switch (N) {
 #define CASE(SZ) \
   case SZ:       \
-    return launch_spec_col_t<SZ>((const cx<double>*)rowspec, M, tab, kind, fp32, scale, (const cx<double>*)r2n, st);
+    return launch_spec_col_t<SZ>((const cx<double>*)rowspec, M, tab, kind, fp32, scale, (const cx<double>*)r2n, \
+                                (const cx<double>*)tw, st);
     SG_SIZES(CASE)
 #undef CASE
     default:
@@ -861,4 +924,46 @@ hipError_t sg_launch_coeff_rows(int prec, int M, const void* src, void* dst, int
 hipError_t sg_launch_coeff_cols(int prec, int N, void* data, int M, hipStream_t st) {
   if (prec == 0) return coeff_cols_dispatch<double>(N, (double*)data, M, st);
   return coeff_cols_dispatch<float>(N, (float*)data, M, st);
+}
+
+// ------------------------------------------------- stage twiddle tables --
+template <typename R, int L, int E>
+__global__ void k_build_tw(const cx<R>* __restrict__ roots, int stride, cx<R>* __restrict__ out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < plan<L, E>::tw_size) build_stage_twiddles<L, E>(roots_t<R>{roots, stride}, out, idx);
+}
+
+template <typename R, int L, int E>
+static int tw_build(const void* roots, int stride, void* out, hipStream_t st) {
+  constexpr int n = plan<L, E>::tw_size;
+  if (out && n > 0)
+    hipLaunchKernelGGL((k_build_tw<R, L, E>), dim3((n + 255) / 256), dim3(256), 0, st, (const cx<R>*)roots, stride,
+                       (cx<R>*)out);
+  return n;
+}
+
+// pass: 0 = forward rows (length M/2), 1 = columns (N), 2 = inverse rows (M),
+// 3 = plan-time spectrum columns (N, FP64).  len = M or N.  roots: the
+// table of the 2*len-th roots in the pass precision.  With out == NULL only
+// the entry count is returned; otherwise the table is filled on st.
+template <typename R>
+static int tw_dispatch(int pass, int len, const void* roots, void* out, hipStream_t st) {
+  switch (len) {
+#define CASE(SZ)                                                                                         \
+  case SZ:                                                                                               \
+    if (pass == 0) return tw_build<R, SZ / 2, rowfwd_cfg<R, R, SZ>::E>(roots, 4, out, st);               \
+    if (pass == 1) return tw_build<R, SZ, col_cfg<R, SZ>::E>(roots, 2, out, st);                         \
+    if (pass == 2) return tw_build<R, SZ, rowinv_cfg<R, SZ>::E>(roots, 2, out, st);                      \
+    if (pass == 3) return tw_build<R, SZ, spec_cfg<SZ>::E>(roots, 2, out, st);                           \
+    return -1;
+    SG_SIZES(CASE)
+#undef CASE
+    default:
+      return -1;
+  }
+}
+
+int sg_twiddles(int prec, int pass, int len, const void* roots, void* out, hipStream_t st) {
+  if (pass == 3 && prec != 0) return -1;
+  return prec == 0 ? tw_dispatch<double>(pass, len, roots, out, st) : tw_dispatch<float>(pass, len, roots, out, st);
 }
