@@ -24,10 +24,12 @@
  *  - Element type: double for SG_FP64 plans; float for SG_FP32_SPLIT plans
  *    (sigma, forces and gradients), except sg_weights, always double.
  *  - Per-step calls (sg_bspline_coeffs, sg_forces, sg_forces_adjoint) are
- *    asynchronous on the plan's HIP stream, allocate nothing and do not
- *    synchronise; buffers must stay alive until the stream has passed the
- *    call.  Two calls on one plan must not overlap in time (they share the
- *    plan's workspace): issue them on the plan's stream.
+ *    asynchronous on the plan's HIP stream, allocate no device memory and do
+ *    not synchronise (except sg_forces on a plan created with
+ *    SG_FLAG_CHECK_FINITE, which waits for the check's result); buffers must
+ *    stay alive until the stream has passed the call.  Two calls on one
+ *    plan must not overlap in time (they share the plan's workspace): issue
+ *    them on the plan's stream.
  *  - Every call returns an sg_status; a non-OK status leaves a thread-local
  *    message for sg_last_error_message().  After a device error
  *    (SG_ERR_DEVICE) the plan is sticky: every later call on it returns
@@ -60,8 +62,8 @@ typedef enum {
 } sg_precision;
 
 /* One grid.  Cell sizes are dx = (x1-x0)/nx, dy = (y1-y0)/ny (Sec. 2, grid
- * points x_{i+1/2} = x0 + i dx).  nx, ny: >= 2, each a power of two from 4
- * to 8192, or three times a power of two from 12 to 6144. */
+ * points x_{i+1/2} = x0 + i dx).  nx, ny: each a power of two from 4 to
+ * 4096 (other sizes: SG_ERR_UNSUPPORTED). */
 typedef struct {
   int32_t nx, ny;
   double x0, x1, y0, y1;

@@ -262,8 +262,8 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
         !(g.y1 > g.y0))
       return fail(SG_ERR_ARG, "grid %d: empty or non-finite domain", i);
     if (g.order < 1 || g.order > 3) return fail(SG_ERR_UNSUPPORTED, "grid %d: order %d (supported: 1..3)", i, g.order);
-    if (!pow2_in(g.nx, 4, 8192) || !pow2_in(g.ny, 4, 8192))
-      return fail(SG_ERR_UNSUPPORTED, "grid %d: %dx%d (supported: powers of two 4..8192)", i, g.nx, g.ny);
+    if (!pow2_in(g.nx, 4, 4096) || !pow2_in(g.ny, 4, 4096))
+      return fail(SG_ERR_UNSUPPORTED, "grid %d: %dx%d (supported: powers of two 4..4096)", i, g.nx, g.ny);
   }
   sg_plan p = new (std::nothrow) sg_plan_s();
   if (!p) return fail(SG_ERR_NOMEM, "host allocation failed");
@@ -490,7 +490,25 @@ sg_status sg_forces_adjoint(sg_plan p, const void* gfx, const void* gfy, void* g
   sg_status s = check_plan(p);
   if (s != SG_OK) return s;
   if (!gfx || !gfy || !gsigma) return fail(SG_ERR_ARG, "gfx, gfy or gsigma is NULL");
-  return fail(SG_ERR_UNSUPPORTED, "adjoint not built yet");
+  if (gsigma == gfx || gsigma == gfy) return fail(SG_ERR_ARG, "gsigma must not alias gfx or gfy");
+  const int prec = p->prec == SG_FP64 ? 0 : 1;
+  const size_t el = prec == 0 ? 8 : 4, cb = 2 * el;
+  for (const GridPlan& G : p->grids) {
+    const char* gx = (const char*)gfx + el * G.off;
+    const char* gy = (const char*)gfy + el * G.off;
+    char* out = (char*)gsigma + el * G.off;
+    const int solve = G.k == 3 ? 1 : 0;
+    // workspace: row spectra of gx in X, of gy in the first half of V, gC spectra in its second half
+    void* Xy = G.V;
+    void* Y = (char*)G.V + cb * (size_t)G.M * G.N;
+    hipError_t e = sg_launch_row_fwd(prec, G.M, gx, G.M, G.X, G.N, G.r2m, 0, 0, G.twA, p->st);
+    if (e == hipSuccess) e = sg_launch_row_fwd(prec, G.M, gy, G.M, Xy, G.N, G.r2m, 0, 0, G.twA, p->st);
+    if (e == hipSuccess)
+      e = sg_launch_adjoint_tail(prec, G.M, G.N, G.X, Xy, Y, out, sg_row_tile(prec, G.M, G.N), G.tabx, G.taby, G.kind,
+                                 G.r2m, G.r2n, solve, G.twB, G.twA, p->st);
+    if (e != hipSuccess) return hip_check(p, e, "adjoint launch");
+  }
+  return SG_OK;
 }
 
 }  // extern "C"

@@ -27,3 +27,9 @@ int sg_twiddles(int prec, int pass, int len, const void* roots, void* out, hipSt
 hipError_t sg_launch_check_finite(int prec, const void* x, int64_t n, int* flag, hipStream_t st);
 hipError_t sg_launch_coeff_rows(int prec, int M, const void* src, void* dst, int nrows, hipStream_t st);
 hipError_t sg_launch_coeff_cols(int prec, int N, void* data, int M, hipStream_t st);
+// Adjoint after the two forward row transforms of gx, gy (Xx, Xy
+// column-major like X): conjugate-spectrum column pass into Y (tiles of tj
+// rows), then the inverse real row pass with the x-solve into gsigma.
+hipError_t sg_launch_adjoint_tail(int prec, int M, int N, const void* Xx, const void* Xy, void* Y, void* gsigma,
+                                  int tj, const void* tx, const void* ty, int kind, const void* r2m, const void* r2n,
+                                  int solve, const void* twB, const void* twA, hipStream_t st);

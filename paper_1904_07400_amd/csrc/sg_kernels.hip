@@ -305,7 +305,7 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
 // ---------------------------------------------------------------- pass B --
 template <typename R, int N>
 struct col_cfg {
-  static constexpr int E0 = sizeof(R) == 4 ? SG_COL_E32 : (N >= 8192 ? 2 * SG_COL_E64 : SG_COL_E64);
+  static constexpr int E0 = sizeof(R) == 4 ? SG_COL_E32 : SG_COL_E64;
   static constexpr int E = N < E0 ? N : E0;
   static constexpr int T = N / E;
   static constexpr int LL = lds_len<N>::value;
@@ -332,34 +332,39 @@ __device__ __forceinline__ cx<float> mul_iA(cx<float> z, const float2* tab, int 
   return {-(z.y * h + z.y * l), z.x * h + z.x * l};
 }
 template <typename R, typename TC>
-__device__ __forceinline__ cx<R> mul_W(cx<R> z, const TC* tab, int idx);
+__device__ __forceinline__ cx<R> mul_W(cx<R> z, const TC* tab, int idx, bool cj);
 template <>
-__device__ __forceinline__ cx<double> mul_W(cx<double> z, const double2* tab, int idx) {
+__device__ __forceinline__ cx<double> mul_W(cx<double> z, const double2* tab, int idx, bool cj) {
   const double2 w = tab[idx];
-  return cmul(z, cx<double>{w.x, w.y});
+  return cmul(z, cx<double>{w.x, cj ? -w.y : w.y});
 }
 template <>
-__device__ __forceinline__ cx<float> mul_W(cx<float> z, const float4* tab, int idx) {
-  const float4 w = tab[idx];  // (re_hi, re_lo, im_hi, im_lo)
+__device__ __forceinline__ cx<float> mul_W(cx<float> z, const float4* tab, int idx, bool cj) {
+  float4 w = tab[idx];  // (re_hi, re_lo, im_hi, im_lo)
+  if (cj) {
+    w.z = -w.z;
+    w.w = -w.w;
+  }
   return {(z.x * w.x - z.y * w.z) + (z.x * w.y - z.y * w.w), (z.x * w.z + z.y * w.x) + (z.x * w.w + z.y * w.y)};
 }
 
-// Product of the column spectrum with W^d at column bin p.  half 0: bins
-// q = 2q', half 1: q = 2q'+1.  eps: symmetry of the stored table across
-// q -> 2N - q (+1 for x, -1 for y) for odd k.
-template <typename R, typename TO, typename TC, int N>
+// Product of the column spectrum with W^d (or conj W^d, CJ) at column bin p.
+// half 0: bins q = 2q', half 1: q = 2q'+1.  eps: symmetry of the stored
+// table across q -> 2N - q (+1 for x, -1 for y) for odd k.
+template <typename R, typename TO, typename TC, int N, bool CJ = false>
 __device__ __forceinline__ cx<R> spec_mul(cx<R> z, int kind, const TO* to, const TC* tc, int p, int qq,
                                           int half, R eps) {
   if (kind == 0) {
     const TO* row = to + (int64_t)p * (N + 1);
+    const R c = CJ ? (R)-1 : (R)1;  // conj(i A) = -i A
     if (half == 0) {
       const bool lo = qq <= N / 2;
-      return mul_iA(z, row, lo ? qq : N - qq, lo ? (R)1 : eps);
+      return mul_iA(z, row, lo ? qq : N - qq, lo ? c : c * eps);
     }
     const bool lo = qq < N / 2;
-    return mul_iA(z, row + N / 2 + 1, lo ? qq : N - 1 - qq, lo ? (R)1 : eps);
+    return mul_iA(z, row + N / 2 + 1, lo ? qq : N - 1 - qq, lo ? c : c * eps);
   }
-  return mul_W(z, tc + (int64_t)p * (2 * N), half * N + qq);
+  return mul_W(z, tc + (int64_t)p * (2 * N), half * N + qq, CJ);
 }
 
 // Products of one half of the column spectrum with W^x and W^y.  exch:
@@ -541,6 +546,206 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
   }
 }
 
+// -------------------------------------------------------------- adjoint --
+// Transposed convolution: gC = crop(IFFT(FFT(pad gx) conj Wx + FFT(pad gy)
+// conj Wy)) with the forward pass's spectra and scaling, then the
+// transposed coefficient solve (the same symmetric systems).  Row
+// transforms of gx, gy reuse k_row_fwd; the column pass below multiplies by
+// the conjugate spectra, sums the two components, inverts cropped to N rows,
+// applies the y-solve and writes the packed row spectra of gC in tiles of
+// tj rows: bin p of row j at ((j/tj*2 + p%2)*(M/2) + p/2)*tj + j%tj.
+template <typename R, typename TO, typename TC, int N, int E, int T>
+__device__ __forceinline__ void col_products_adj(const cx<R>* fx, const cx<R>* fy, cx<R>* h, int half, bool exch,
+                                                 bool packed, cx<R>* lds, int kind, const TO* tox, const TO* toy,
+                                                 const TC* tcx, const TC* tcy, int c, int M, int t) {
+  // packed column: each spectrum U carries bins p = 0 and p = M; split both
+  cx<R> umx[E], umy[E];
+  if (exch) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = fx[e];
+    __syncthreads();
+    if (packed) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int qq = t + e * T;
+        umx[e] = conj(lds[pad(half == 0 ? ((N - qq) & (N - 1)) : (N - 1 - qq))]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = fy[e];
+    __syncthreads();
+    if (packed) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int qq = t + e * T;
+        umy[e] = conj(lds[pad(half == 0 ? ((N - qq) & (N - 1)) : (N - 1 - qq))]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int qq = t + e * T;
+    if (packed) {
+      const cx<R> ux = fx[e], uy = fy[e];
+      const cx<R> x0v{(R)0.5 * (ux.x + umx[e].x), (R)0.5 * (ux.y + umx[e].y)};
+      const cx<R> xmv{(R)0.5 * (ux.y - umx[e].y), (R)-0.5 * (ux.x - umx[e].x)};
+      const cx<R> y0v{(R)0.5 * (uy.x + umy[e].x), (R)0.5 * (uy.y + umy[e].y)};
+      const cx<R> ymv{(R)0.5 * (uy.y - umy[e].y), (R)-0.5 * (uy.x - umy[e].x)};
+      const cx<R> h0 = spec_mul<R, TO, TC, N, true>(x0v, kind, tox, tcx, 0, qq, half, (R)1) +
+                       spec_mul<R, TO, TC, N, true>(y0v, kind, toy, tcy, 0, qq, half, (R)-1);
+      const cx<R> hm = spec_mul<R, TO, TC, N, true>(xmv, kind, tox, tcx, M, qq, half, (R)1) +
+                       spec_mul<R, TO, TC, N, true>(ymv, kind, toy, tcy, M, qq, half, (R)-1);
+      h[e] = cx<R>{h0.x - hm.y, h0.y + hm.x};
+    } else {
+      h[e] = spec_mul<R, TO, TC, N, true>(fx[e], kind, tox, tcx, c, qq, half, (R)1) +
+             spec_mul<R, TO, TC, N, true>(fy[e], kind, toy, tcy, c, qq, half, (R)-1);
+    }
+  }
+}
+
+template <typename R, typename TO, typename TC, int N>
+__global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
+    k_col_adj(const cx<R>* __restrict__ Xx, const cx<R>* __restrict__ Xy, cx<R>* __restrict__ Y, int M, int tj,
+              const TO* __restrict__ tox, const TO* __restrict__ toy, const TC* __restrict__ tcx,
+              const TC* __restrict__ tcy, const cx<R>* __restrict__ r2n, int solve, int kind,
+              const cx<R>* __restrict__ tw) {
+  using C = col_cfg<R, N>;
+  constexpr int E = C::E, T = C::T, LL = C::SLOT;
+  __shared__ cx<R> smem[C::P * LL];
+  const int P = blockDim.x / T;
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int c0 = xcd_tile(blockIdx.x, gridDim.x) * P, c = c0 + g;
+  cx<R>* lds = smem + g * LL;
+  const bool packed = (c == 0);
+  cx<R> ax[E], ay[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    ax[e] = Xx[(int64_t)c * N + t + e * T];
+    ay[e] = Xy[(int64_t)c * N + t + e * T];
+  }
+  cx<R> acc[E];
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    cx<R> fx[E], fy[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const cx<R> w = r2n[t + e * T];
+      fx[e] = half ? cmul(ax[e], w) : ax[e];
+      fy[e] = half ? cmul(ay[e], w) : ay[e];
+    }
+    fft<false, N, T>(fx, lds, tw, t);
+    fft<false, N, T>(fy, lds, tw, t);
+    cx<R> h[E];
+    col_products_adj<R, TO, TC, N, E, T>(fx, fy, h, half, c0 == 0, packed, lds, kind, tox, toy, tcx, tcy, c, M, t);
+    fft<true, N, T>(h, lds, tw, t);
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = half ? acc[e] + cmulc(h[e], r2n[t + e * T]) : h[e];
+  }
+  if (solve) {
+    // transposed y-solve (Eq. (z_system) is symmetric): chunk of E per thread
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = acc[e];
+    __syncthreads();
+    double2 d[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const cx<R> v = lds[pad(t * E + e)];
+      d[e] = make_double2(8.0 * (double)v.x, 8.0 * (double)v.y);
+    }
+    __syncthreads();
+    tri_solve<E, T, double2>(d, t, *reinterpret_cast<tri_smem<double2, T>*>(lds));
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[pad(t * E + e)] = cx<R>{(R)d[e].x, (R)d[e].y};
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = lds[pad(t + e * T)];
+  }
+  cx<R>* out = Y + (int64_t)(c & 1) * (M / 2) * tj + (int64_t)(c >> 1) * tj;
+  const int64_t jstride = (int64_t)M * tj;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int j = t + e * T;
+    out[(int64_t)(j / tj) * jstride + (j % tj)] = acc[e];
+  }
+}
+
+// Rows of the packed gC spectra -> real row of length 2M cropped to M via
+// the half-length complex inverse FFT (z = x_even + i x_odd, its first M/2
+// outputs from the even and odd input bins: two inverse FFTs of length M/2),
+// then the transposed x-solve (Eq. (C_system) is symmetric).
+template <typename R, typename Out, int M>
+__global__ void __launch_bounds__((rowfwd_cfg<R, R, M>::G * rowfwd_cfg<R, R, M>::T))
+    k_row_c2r(const cx<R>* __restrict__ Y, Out* __restrict__ out, int nrows, int tj, const cx<R>* __restrict__ r2m,
+              int solve, const cx<R>* __restrict__ tw) {
+  using C = rowfwd_cfg<R, R, M>;
+  constexpr int L = C::L, E = C::E, T = C::T, SLOT = C::SLOT;
+  __shared__ cx<R> smem[C::G * SLOT];
+  const int G = blockDim.x / T;
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int row = xcd_tile(blockIdx.x, gridDim.x) * G + g;
+  const bool active = row < nrows;
+  cx<R>* lds = smem + g * SLOT;
+  const int jb = (active ? row : 0) / tj, jj = (active ? row : 0) % tj;
+  // bin p of this row: tile half p&1, index p>>1
+  const cx<R>* b0 = Y + ((int64_t)jb * 2) * L * tj + jj;
+  const cx<R>* b1 = Y + ((int64_t)jb * 2 + 1) * L * tj + jj;
+  cx<R> ze[E], zo[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int pp = t + e * T;
+    // Z'[p] = (X[p] + conj X[M-p]) + i conj(w_2M^p) (X[p] - conj X[M-p]), X[M] packed in slot 0
+    const cx<R> xe = b0[(int64_t)pp * tj];                       // X[2pp]
+    const cx<R> xo = b1[(int64_t)pp * tj];                       // X[2pp+1]
+    cx<R> me = conj(b0[(int64_t)((L - pp) & (L - 1)) * tj]);     // conj X[M - 2pp]
+    const cx<R> mo = conj(b1[(int64_t)(L - 1 - pp) * tj]);       // conj X[M - 2pp - 1]
+    if (pp == 0) {
+      const cx<R> x0 = xe;  // (X_0, X_M)
+      ze[e] = cx<R>{x0.x + x0.y, x0.x - x0.y};
+    } else {
+      const cx<R> sum = xe + me, dif = cmulc(xe - me, r2m[2 * pp]);
+      ze[e] = cx<R>{sum.x - dif.y, sum.y + dif.x};
+    }
+    const cx<R> sum = xo + mo, dif = cmulc(xo - mo, r2m[2 * pp + 1]);
+    zo[e] = cx<R>{sum.x - dif.y, sum.y + dif.x};
+  }
+  fft<true, L, T>(ze, lds, tw, t);
+  fft<true, L, T>(zo, lds, tw, t);
+  // z[n'] = ze + exp(2 pi i n'/M) zo, n' < M/2: x[2n'] = Re z, x[2n'+1] = Im z
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int n = t + e * T;
+    ze[e] = ze[e] + cmulc(zo[e], r2m[2 * n]);
+  }
+  if (solve) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = ze[e];
+    __syncthreads();
+    constexpr int CH = 2 * E;
+    double d[CH];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const cx<R> v = lds[pad(t * E + e)];
+      d[2 * e] = 8.0 * (double)v.x;
+      d[2 * e + 1] = 8.0 * (double)v.y;
+    }
+    __syncthreads();
+    tri_solve<CH, T, double>(d, t, *reinterpret_cast<tri_smem<double, T>*>(lds));
+    if (active) {
+#pragma unroll
+      for (int e = 0; e < CH; ++e) out[(int64_t)row * M + t * CH + e] = (Out)d[e];
+    }
+  } else if (active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int n = t + e * T;
+      out[(int64_t)row * M + 2 * n] = (Out)ze[e].x;
+      out[(int64_t)row * M + 2 * n + 1] = (Out)ze[e].y;
+    }
+  }
+}
+
 // ------------------------------------------------------ spectrum (plan) --
 // Column FFT (FP64, full length 2N: the even/odd output split preceded by
 // the first radix-2 butterfly) of the row spectra of the padded weight
@@ -714,7 +919,7 @@ struct tabs {
 };
 
 #ifndef SG_SIZES
-#define SG_SIZES(X) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
+#define SG_SIZES(X) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 #endif
 
 template <typename R, typename In, int M>
@@ -966,4 +1171,71 @@ static int tw_dispatch(int pass, int len, const void* roots, void* out, hipStrea
 int sg_twiddles(int prec, int pass, int len, const void* roots, void* out, hipStream_t st) {
   if (pass == 3 && prec != 0) return -1;
   return prec == 0 ? tw_dispatch<double>(pass, len, roots, out, st) : tw_dispatch<float>(pass, len, roots, out, st);
+}
+
+// ------------------------------------------------------ adjoint launches --
+template <typename R, int N>
+static hipError_t launch_col_adj_t(const cx<R>* Xx, const cx<R>* Xy, cx<R>* Y, int M, int tj, const void* tx,
+                                   const void* ty, int kind, const cx<R>* r2n, int solve, const cx<R>* tw,
+                                   hipStream_t st) {
+  using C = col_cfg<R, N>;
+  using TO = typename tabs<R>::odd;
+  using TC = typename tabs<R>::cplx;
+  const int P = C::P < M ? C::P : M;
+  const TO* tox = kind == 0 ? (const TO*)tx : nullptr;
+  const TO* toy = kind == 0 ? (const TO*)ty : nullptr;
+  const TC* tcx = kind == 1 ? (const TC*)tx : nullptr;
+  const TC* tcy = kind == 1 ? (const TC*)ty : nullptr;
+  hipLaunchKernelGGL((k_col_adj<R, TO, TC, N>), dim3(M / P), dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy, tcx,
+                     tcy, r2n, solve, kind, tw);
+  return hipGetLastError();
+}
+
+template <typename R, int M>
+static hipError_t launch_row_c2r_t(const cx<R>* Y, R* out, int nrows, int tj, const cx<R>* r2m, int solve,
+                                   const cx<R>* tw, hipStream_t st) {
+  using C = rowfwd_cfg<R, R, M>;
+  const int G = C::G < nrows ? C::G : nrows;
+  hipLaunchKernelGGL((k_row_c2r<R, R, M>), dim3((nrows + G - 1) / G), dim3(G * C::T), 0, st, Y, out, nrows, tj, r2m,
+                     solve, tw);
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t adj_dispatch(int M, int N, const cx<R>* Xx, const cx<R>* Xy, cx<R>* Y, R* out, int tj,
+                               const void* tx, const void* ty, int kind, const cx<R>* r2m, const cx<R>* r2n,
+                               int solve, const cx<R>* twB, const cx<R>* twA, hipStream_t st) {
+  hipError_t e = hipErrorInvalidValue;
+  switch (N) {
+#define CASE(SZ)                                                                          \
+  case SZ:                                                                                \
+    e = launch_col_adj_t<R, SZ>(Xx, Xy, Y, M, tj, tx, ty, kind, r2n, solve, twB, st);     \
+    break;
+    SG_SIZES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  switch (M) {
+#define CASE(SZ) \
+  case SZ:       \
+    return launch_row_c2r_t<R, SZ>(Y, out, N, tj, r2m, solve, twA, st);
+    SG_SIZES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t sg_launch_adjoint_tail(int prec, int M, int N, const void* Xx, const void* Xy, void* Y, void* gsigma,
+                                  int tj, const void* tx, const void* ty, int kind, const void* r2m, const void* r2n,
+                                  int solve, const void* twB, const void* twA, hipStream_t st) {
+  if (prec == 0)
+    return adj_dispatch<double>(M, N, (const cx<double>*)Xx, (const cx<double>*)Xy, (cx<double>*)Y, (double*)gsigma,
+                                tj, tx, ty, kind, (const cx<double>*)r2m, (const cx<double>*)r2n, solve,
+                                (const cx<double>*)twB, (const cx<double>*)twA, st);
+  return adj_dispatch<float>(M, N, (const cx<float>*)Xx, (const cx<float>*)Xy, (cx<float>*)Y, (float*)gsigma, tj, tx,
+                             ty, kind, (const cx<float>*)r2m, (const cx<float>*)r2n, solve, (const cx<float>*)twB,
+                             (const cx<float>*)twA, st);
 }

@@ -56,6 +56,17 @@ def clump_sigma(params, xs: np.ndarray, ys: np.ndarray) -> np.ndarray:
     return out * taper
 
 
+def perturb_clumps(params, seed, amp_frac: float = 0.1, shift: float = 0.01):
+    """Seeded perturbation of clump parameters (target densities for a
+    fitting loss): a_c (1 + amp_frac xi), x_c + shift eta, xi, eta ~ N(0, 1)."""
+    a, s, cx, cy = params
+    rng = np.random.default_rng(seed)
+    xi = rng.standard_normal(len(a))
+    ex = rng.standard_normal(len(a))
+    ey = rng.standard_normal(len(a))
+    return a * (1.0 + amp_frac * xi), s, cx + shift * ex, cy + shift * ey
+
+
 def sparse_coeffs(seed, M: int, N: int, count: int, margin: int = 0):
     """``count`` seeded impulse positions (i, j) and values in [-1, 1]."""
     rng = np.random.default_rng(seed)
