@@ -118,8 +118,8 @@ def main():
                     help="both (default, the metric) or one path only (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "decomposition is a design, not a build (see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the multi-GPU "
+              "decomposition of this method is designed but not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -20,8 +20,12 @@ Everything here is plain FP64 on the CPU and uses no FFT:
 * ``error_norms``        - L1 / L2 / Linf of Eqs. (oneNormErr)-(inftyNormErr)
 * ``antiderivative``     - the closed forms of Appendix A and Eq. (intF) (mpmath)
 
-Readings of the paper that this oracle takes where the text is silent or
-ambiguous are listed in DESIGN.md ("Readings").
+Where the paper is silent or ambiguous the oracle takes these readings: the
+k = 2 splines are centred on the vertices x0 + i dx and sampled there; the
+k = 3 labels are shifted so that C_i is centred on cell i; the weight
+integral over the piece holding the singular point is a principal value;
+the error norms are weighted by the cell area; G = 1 and the force is
+attractive.
 """
 from .core import (  # noqa: F401
     sample_lattice, cell_centres, thomas, bspline_coeffs, bspline_apply, bspline_value,

@@ -228,8 +228,9 @@ def disk_force_radial(n: int, R, alpha: float, sigma0: float = 1.0, G: float = 1
 # ---------------------------------------------------------------- norms ---
 def error_norms(num: np.ndarray, ana: np.ndarray, dx: float, dy: float):
     """(L1, L2, Linf) of Eqs. (oneNormErr)-(inftyNormErr) as the tables use
-    them: the sums are weighted by the cell area dx*dy (reading of the printed
-    1/N^2 on the [-1,1]^2 domain)."""
+    them: the sums are weighted by the cell area dx*dy (the printed 1/N^2
+    read as the cell area of the [-1,1]^2 domain up to its constant factor:
+    only this weighting reproduces the tabulated L1 and L2 values)."""
     e = np.abs(np.asarray(num) - np.asarray(ana))
     return float(e.sum() * dx * dy), float(math.sqrt((e * e).sum() * dx * dy)), float(e.max())
 

@@ -34,11 +34,65 @@ def _compile(src: str, obj_dir: str) -> str:
     return obj
 
 
+# Largest per-lane private (scratch) segment a kernel may have.  Every
+# dispatch on MI355X gets a 1024 B/lane scratch allocation up front; the two
+# builds whose kernels needed more (register spills of 1.6 and 2.2 KB/lane)
+# faulted the device, while every kernel at or below 656 B/lane has run
+# cleanly, so the build refuses anything above that.
+SCRATCH_LIMIT = 656
+
+
+def kernel_resources(obj: str):
+    """(name, scratch B/lane, LDS B, max workgroup size, VGPRs, AGPRs) of every
+    gfx950 kernel in a compiled object, read from its code-object metadata."""
+    llvm = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "llvm", "bin")
+    if not os.path.isdir(llvm):
+        llvm = "/opt/rocm/llvm/bin"
+    tmp = obj + ".meta"
+    fat, elf = tmp + ".fatbin", tmp + ".elf"
+    subprocess.run(["objcopy", "-O", "binary", "--only-section=.hip_fatbin", obj, fat], check=True)
+    subprocess.run([os.path.join(llvm, "clang-offload-bundler"), "--type=o",
+                    "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", "--input=" + fat, "--output=" + elf,
+                    "--unbundle"], check=True)
+    notes = subprocess.run([os.path.join(llvm, "llvm-readelf"), "--notes", elf], check=True,
+                           capture_output=True, text=True).stdout
+    for f in (fat, elf):
+        os.remove(f)
+    out, cur = [], {}
+    keys = ("agpr_count", "group_segment_fixed_size", "max_flat_workgroup_size", "name",
+            "private_segment_fixed_size", "vgpr_count")
+    for line in notes.splitlines():
+        t = line.strip()
+        if not t.startswith(".") or ":" not in t:
+            continue
+        k, v = t[1:].split(":", 1)
+        if k in keys:
+            cur[k] = v.strip()
+            if k == "vgpr_count":  # last key of each kernel record
+                out.append((cur.get("name", "?"), int(cur.get("private_segment_fixed_size", 0)),
+                            int(cur.get("group_segment_fixed_size", 0)),
+                            int(cur.get("max_flat_workgroup_size", 0)), int(cur["vgpr_count"]),
+                            int(cur.get("agpr_count", 0))))
+                cur = {}
+    return out
+
+
+def check_resources(obj: str) -> None:
+    res = kernel_resources(obj)
+    if not res:
+        raise RuntimeError("no kernel metadata found in " + obj)
+    bad = [r for r in res if r[1] > SCRATCH_LIMIT]
+    if bad:
+        lines = "\n".join(f"  {r[0]}: {r[1]} B/lane" for r in bad)
+        raise RuntimeError(f"kernels above the {SCRATCH_LIMIT} B/lane scratch limit:\n{lines}")
+
+
 def build(verbose: bool = False) -> str:
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(lambda s: _compile(s, obj_dir), SOURCES))
+    check_resources(objs[0])
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -48,6 +48,22 @@
 #ifndef SG_COL_E64
 #define SG_COL_E64 8
 #endif
+#ifndef SG_RF_E32
+#define SG_RF_E32 16
+#endif
+#ifndef SG_RF_E64
+#define SG_RF_E64 8
+#endif
+// minimum waves per SIMD the register allocation must allow (1 = no cap)
+#ifndef SG_RF_WPE
+#define SG_RF_WPE 1
+#endif
+#ifndef SG_COL_WPE
+#define SG_COL_WPE 1
+#endif
+#ifndef SG_RI_WPE
+#define SG_RI_WPE 1
+#endif
 
 namespace sg {
 
@@ -196,7 +212,8 @@ constexpr int kLdsBudget = 144 * 1024;
 template <typename R, typename In, int M>
 struct rowfwd_cfg {
   static constexpr int L = M / 2;
-  static constexpr int E = (sizeof(R) == 4 ? 16 : 8) < L ? (sizeof(R) == 4 ? 16 : 8) : L;
+  static constexpr int E0 = sizeof(R) == 4 ? SG_RF_E32 : SG_RF_E64;
+  static constexpr int E = E0 < L ? E0 : L;
   static constexpr int T = L / E;
   static constexpr int LL = lds_len<L>::value;
   // per-row LDS slot (complex elements): FFT exchange buffer, also used
@@ -212,6 +229,7 @@ struct rowfwd_cfg {
 
 template <typename R, typename In, int M>
 __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M>::T))
+    __attribute__((amdgpu_waves_per_eu(SG_RF_WPE)))
     k_row_fwd(const In* __restrict__ src, int64_t src_ld, cx<R>* __restrict__ X, int ldx, int nrows,
               const cx<R>* __restrict__ r2m, int solve, int full, const cx<R>* __restrict__ tw) {
   using C = rowfwd_cfg<R, In, M>;
@@ -405,7 +423,7 @@ __device__ __forceinline__ void col_products(const cx<R>* f, cx<R>* gx, cx<R>* g
 
 template <typename R, typename TO, typename TC, int N>
 __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
-    k_col(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
+    __attribute__((amdgpu_waves_per_eu(SG_COL_WPE))) k_col(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
           const TO* __restrict__ toy, const TC* __restrict__ tcx, const TC* __restrict__ tcy,
           const cx<R>* __restrict__ r2n, int solve, int kind, const cx<R>* __restrict__ tw) {
   using C = col_cfg<R, N>;
@@ -515,6 +533,7 @@ struct rowinv_cfg {
 
 template <typename R, typename Out, int M>
 __global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
+    __attribute__((amdgpu_waves_per_eu(SG_RI_WPE)))
     k_row_inv(const cx<R>* __restrict__ V, Out* __restrict__ fx, Out* __restrict__ fy, int nrows, int tj,
               const cx<R>* __restrict__ r2m, const cx<R>* __restrict__ tw) {
   using C = rowinv_cfg<R, M>;

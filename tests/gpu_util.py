@@ -28,7 +28,7 @@ def run_forces(grid, prec, sigma):
 
 
 def rel_max_err(got_x, got_y, ref_x, ref_y):
-    """max_{cells, d} |F_d - F_d^ref| / max |F^ref| (the benchmark spec's metric)."""
+    """max_{cells, d} |F_d - F_d^ref| / max |F^ref| (the accuracy metric of the FP32-split path)."""
     scale = max(np.max(np.abs(ref_x)), np.max(np.abs(ref_y)))
     err = max(np.max(np.abs(got_x - ref_x)), np.max(np.abs(got_y - ref_y)))
     return err / scale

@@ -1,6 +1,6 @@
 """GPU parity: the HIP library (through its C ABI) against the CPU oracle.
 
-Bars (written here, derived in the design doc): FP64 path <= 1e-12 relative
+Bars: FP64 path <= 1e-12 relative
 (max-norm over cells and components, scaled by max|F|); FP32-split path
 <= 1e-6 relative; weights <= 1e-14 of max|w|; coefficients <= 1e-13 (FP64)
 relative to max|C|.
