@@ -197,10 +197,11 @@ __device__ __forceinline__ void stockham_stage(cx<R>* v, cx<R>* lds, const cx<R>
 #pragma unroll
     for (int q = 0; q < r; ++q) a[q] = v[u + q * NB];
     if constexpr (Ns > 1) {
-      const int k = b & (Ns - 1);
+      // unsigned 32-bit offsets from the uniform table base (scalar-base loads)
+      const unsigned k = (unsigned)b & (Ns - 1);
 #pragma unroll
       for (int q = 1; q < r; ++q) {
-        const cx<R> w = tw[(q - 1) * Ns + k];
+        const cx<R> w = tw[(unsigned)((q - 1) * Ns) + k];
         a[q] = INV ? cmulc(a[q], w) : cmul(a[q], w);
       }
     }
@@ -238,6 +239,10 @@ __device__ __forceinline__ void fft_stages(cx<R>* v, cx<R>* lds, const cx<R>* __
 template <bool INV, int L, int T, typename R>
 __device__ __forceinline__ void fft(cx<R>* v, cx<R>* lds, const cx<R>* __restrict__ tw, int t) {
   static_assert(L % T == 0, "L must be a multiple of T");
+#ifdef SG_FFT_FENCE
+  // keep the twiddle loads inside this transform (no hoisting across calls)
+  __asm__ volatile("" ::: "memory");
+#endif
   fft_stages<INV, L, T, 0>(v, lds, tw, t);
 }
 

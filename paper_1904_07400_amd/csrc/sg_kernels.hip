@@ -54,16 +54,27 @@
 #ifndef SG_RF_E64
 #define SG_RF_E64 8
 #endif
-// minimum waves per SIMD the register allocation must allow (1 = no cap)
-#ifndef SG_RF_WPE
-#define SG_RF_WPE 1
+// minimum waves per SIMD the register allocation must allow (1 = no cap),
+// per pass and precision
+#ifndef SG_RF_WPE32
+#define SG_RF_WPE32 1
 #endif
-#ifndef SG_COL_WPE
-#define SG_COL_WPE 1
+#ifndef SG_RF_WPE64
+#define SG_RF_WPE64 1
 #endif
-#ifndef SG_RI_WPE
-#define SG_RI_WPE 1
+#ifndef SG_COL_WPE32
+#define SG_COL_WPE32 1
 #endif
+#ifndef SG_COL_WPE64
+#define SG_COL_WPE64 1
+#endif
+#ifndef SG_RI_WPE32
+#define SG_RI_WPE32 1
+#endif
+#ifndef SG_RI_WPE64
+#define SG_RI_WPE64 1
+#endif
+#define SG_WPE(R, P) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? SG_##P##_WPE32 : SG_##P##_WPE64)))
 
 namespace sg {
 
@@ -229,7 +240,7 @@ struct rowfwd_cfg {
 
 template <typename R, typename In, int M>
 __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M>::T))
-    __attribute__((amdgpu_waves_per_eu(SG_RF_WPE)))
+    SG_WPE(R, RF)
     k_row_fwd(const In* __restrict__ src, int64_t src_ld, cx<R>* __restrict__ X, int ldx, int nrows,
               const cx<R>* __restrict__ r2m, int solve, int full, const cx<R>* __restrict__ tw) {
   using C = rowfwd_cfg<R, In, M>;
@@ -340,12 +351,12 @@ template <typename R, typename TO>
 __device__ __forceinline__ cx<R> mul_iA(cx<R> z, const TO* tab, int idx, R sgn);
 template <>
 __device__ __forceinline__ cx<double> mul_iA(cx<double> z, const double* tab, int idx, double sgn) {
-  const double a = tab[idx] * sgn;
+  const double a = tab[(unsigned)idx] * sgn;
   return {-z.y * a, z.x * a};
 }
 template <>
 __device__ __forceinline__ cx<float> mul_iA(cx<float> z, const float2* tab, int idx, float sgn) {
-  const float2 a = tab[idx];
+  const float2 a = tab[(unsigned)idx];
   const float h = a.x * sgn, l = a.y * sgn;
   return {-(z.y * h + z.y * l), z.x * h + z.x * l};
 }
@@ -353,12 +364,12 @@ template <typename R, typename TC>
 __device__ __forceinline__ cx<R> mul_W(cx<R> z, const TC* tab, int idx, bool cj);
 template <>
 __device__ __forceinline__ cx<double> mul_W(cx<double> z, const double2* tab, int idx, bool cj) {
-  const double2 w = tab[idx];
+  const double2 w = tab[(unsigned)idx];
   return cmul(z, cx<double>{w.x, cj ? -w.y : w.y});
 }
 template <>
 __device__ __forceinline__ cx<float> mul_W(cx<float> z, const float4* tab, int idx, bool cj) {
-  float4 w = tab[idx];  // (re_hi, re_lo, im_hi, im_lo)
+  float4 w = tab[(unsigned)idx];  // (re_hi, re_lo, im_hi, im_lo)
   if (cj) {
     w.z = -w.z;
     w.w = -w.w;
@@ -385,15 +396,15 @@ __device__ __forceinline__ cx<R> spec_mul(cx<R> z, int kind, const TO* to, const
   return mul_W(z, tc + (int64_t)p * (2 * N), half * N + qq, CJ);
 }
 
-// Products of one half of the column spectrum with W^x and W^y.  exch:
-// the workgroup holds the packed column 0 (uniform over the workgroup);
-// packed: this slice is column 0, whose spectrum U carries bins p = 0 and
-// p = M: C_0 = (U(q) + conj U(-q))/2, C_M = (U(q) - conj U(-q))/(2i), and
-// the products are re-packed as G_0 + i G_M.
+// Product of one half of the column spectrum with W^d of one component
+// (to/tc: that component's table, eps: its reflection sign).  exch: the
+// workgroup holds the packed column 0 (uniform over the workgroup); packed:
+// this slice is column 0, whose spectrum U carries bins p = 0 and p = M:
+// C_0 = (U(q) + conj U(-q))/2, C_M = (U(q) - conj U(-q))/(2i), and the
+// products are re-packed as G_0 + i G_M.
 template <typename R, typename TO, typename TC, int N, int E, int T>
-__device__ __forceinline__ void col_products(const cx<R>* f, cx<R>* gx, cx<R>* gy, int half, bool exch,
-                                             bool packed, cx<R>* lds, int kind, const TO* tox, const TO* toy,
-                                             const TC* tcx, const TC* tcy, int c, int M, int t) {
+__device__ __forceinline__ void col_product(const cx<R>* f, cx<R>* g, int half, bool exch, bool packed, cx<R>* lds,
+                                            int kind, const TO* to, const TC* tc, R eps, int c, int M, int t) {
   if (exch) {
 #pragma unroll
     for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = f[e];
@@ -407,25 +418,25 @@ __device__ __forceinline__ void col_products(const cx<R>* f, cx<R>* gx, cx<R>* g
       const cx<R> u = f[e], um = conj(lds[pad(qm)]);
       const cx<R> c0v{(R)0.5 * (u.x + um.x), (R)0.5 * (u.y + um.y)};
       const cx<R> cmv{(R)0.5 * (u.y - um.y), (R)-0.5 * (u.x - um.x)};
-      const cx<R> x0 = spec_mul<R, TO, TC, N>(c0v, kind, tox, tcx, 0, qq, half, (R)1);
-      const cx<R> xm = spec_mul<R, TO, TC, N>(cmv, kind, tox, tcx, M, qq, half, (R)1);
-      const cx<R> y0 = spec_mul<R, TO, TC, N>(c0v, kind, toy, tcy, 0, qq, half, (R)-1);
-      const cx<R> ym = spec_mul<R, TO, TC, N>(cmv, kind, toy, tcy, M, qq, half, (R)-1);
-      gx[e] = cx<R>{x0.x - xm.y, x0.y + xm.x};
-      gy[e] = cx<R>{y0.x - ym.y, y0.y + ym.x};
+      const cx<R> w0 = spec_mul<R, TO, TC, N>(c0v, kind, to, tc, 0, qq, half, eps);
+      const cx<R> wm = spec_mul<R, TO, TC, N>(cmv, kind, to, tc, M, qq, half, eps);
+      g[e] = cx<R>{w0.x - wm.y, w0.y + wm.x};
     } else {
-      gx[e] = spec_mul<R, TO, TC, N>(f[e], kind, tox, tcx, c, qq, half, (R)1);
-      gy[e] = spec_mul<R, TO, TC, N>(f[e], kind, toy, tcy, c, qq, half, (R)-1);
+      g[e] = spec_mul<R, TO, TC, N>(f[e], kind, to, tc, c, qq, half, eps);
     }
   }
   if (exch) __syncthreads();
 }
 
-template <typename R, typename TO, typename TC, int N>
+// MODE: 0 = k 1 (real tables, no solve), 1 = k 2 (complex tables), 2 = k 3
+// (real tables, y-solve)
+template <typename R, typename TO, typename TC, int N, int MODE>
 __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
-    __attribute__((amdgpu_waves_per_eu(SG_COL_WPE))) k_col(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
+    SG_WPE(R, COL) k_col(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
           const TO* __restrict__ toy, const TC* __restrict__ tcx, const TC* __restrict__ tcy,
-          const cx<R>* __restrict__ r2n, int solve, int kind, const cx<R>* __restrict__ tw) {
+          const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ tw) {
+  constexpr int kind = MODE == 1 ? 1 : 0;
+  constexpr bool solve = MODE == 2;
   using C = col_cfg<R, N>;
   constexpr int E = C::E, T = C::T, LL = C::SLOT;
   __shared__ cx<R> smem[C::P * LL];
@@ -441,7 +452,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     double2 d[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const cx<R> v = col[t * E + e];
+      const cx<R> v = col[(unsigned)(t * E + e)];
       d[e] = make_double2(8.0 * (double)v.x, 8.0 * (double)v.y);
     }
     tri_solve<E, T, double2>(d, t, *reinterpret_cast<tri_smem<double2, T>*>(lds));
@@ -453,7 +464,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     __syncthreads();
   } else {
 #pragma unroll
-    for (int e = 0; e < E; ++e) a[e] = col[t + e * T];
+    for (int e = 0; e < E; ++e) a[e] = col[(unsigned)(t + e * T)];
   }
 
   const bool packed = (c == 0);
@@ -462,28 +473,32 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
   cx<R> fe[E], fo[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    fo[e] = cmul(a[e], r2n[t + e * T]);
+    fo[e] = cmul(a[e], r2n[(unsigned)(t + e * T)]);
     fe[e] = a[e];
   }
   fft<false, N, T>(fe, lds, tw, t);
   fft<false, N, T>(fo, lds, tw, t);
+  // one half and one component at a time: g = f W^d, inverse, accumulate
+  // (the odd half with the phase exp(+i pi j / N))
   cx<R> accx[E], accy[E];
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
     const cx<R>* f = half ? fo : fe;
-    cx<R> gx[E], gy[E];
-    col_products<R, TO, TC, N, E, T>(f, gx, gy, half, c0 == 0, packed, lds, kind, tox, toy, tcx, tcy, c, M, t);
-    fft<true, N, T>(gx, lds, tw, t);
-    fft<true, N, T>(gy, lds, tw, t);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      if (half == 0) {
-        accx[e] = gx[e];
-        accy[e] = gy[e];
-      } else {
-        const cx<R> w = r2n[t + e * T];  // conj -> exp(+i pi j / N)
-        accx[e] = accx[e] + cmulc(gx[e], w);
-        accy[e] = accy[e] + cmulc(gy[e], w);
+    for (int comp = 0; comp < 2; ++comp) {
+      cx<R> g[E];
+      col_product<R, TO, TC, N, E, T>(f, g, half, c0 == 0, packed, lds, kind, comp ? toy : tox, comp ? tcy : tcx,
+                                      comp ? (R)-1 : (R)1, c, M, t);
+      fft<true, N, T>(g, lds, tw, t);
+      cx<R>* acc = comp ? accy : accx;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (half == 0) {
+          acc[e] = g[e];
+        } else {
+          const cx<R> w = r2n[(unsigned)(t + e * T)];  // conj -> exp(+i pi j / N)
+          acc[e] = acc[e] + cmulc(g[e], w);
+        }
       }
     }
   }
@@ -533,7 +548,7 @@ struct rowinv_cfg {
 
 template <typename R, typename Out, int M>
 __global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
-    __attribute__((amdgpu_waves_per_eu(SG_RI_WPE)))
+    SG_WPE(R, RI)
     k_row_inv(const cx<R>* __restrict__ V, Out* __restrict__ fx, Out* __restrict__ fy, int nrows, int tj,
               const cx<R>* __restrict__ r2m, const cx<R>* __restrict__ tw) {
   using C = rowinv_cfg<R, M>;
@@ -624,12 +639,13 @@ __device__ __forceinline__ void col_products_adj(const cx<R>* fx, const cx<R>* f
   }
 }
 
-template <typename R, typename TO, typename TC, int N>
+template <typename R, typename TO, typename TC, int N, int MODE>
 __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     k_col_adj(const cx<R>* __restrict__ Xx, const cx<R>* __restrict__ Xy, cx<R>* __restrict__ Y, int M, int tj,
               const TO* __restrict__ tox, const TO* __restrict__ toy, const TC* __restrict__ tcx,
-              const TC* __restrict__ tcy, const cx<R>* __restrict__ r2n, int solve, int kind,
-              const cx<R>* __restrict__ tw) {
+              const TC* __restrict__ tcy, const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ tw) {
+  constexpr int kind = MODE == 1 ? 1 : 0;
+  constexpr bool solve = MODE == 2;
   using C = col_cfg<R, N>;
   constexpr int E = C::E, T = C::T, LL = C::SLOT;
   __shared__ cx<R> smem[C::P * LL];
@@ -650,7 +666,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     cx<R> fx[E], fy[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const cx<R> w = r2n[t + e * T];
+      const cx<R> w = r2n[(unsigned)(t + e * T)];
       fx[e] = half ? cmul(ax[e], w) : ax[e];
       fy[e] = half ? cmul(ay[e], w) : ay[e];
     }
@@ -660,7 +676,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     col_products_adj<R, TO, TC, N, E, T>(fx, fy, h, half, c0 == 0, packed, lds, kind, tox, toy, tcx, tcy, c, M, t);
     fft<true, N, T>(h, lds, tw, t);
 #pragma unroll
-    for (int e = 0; e < E; ++e) acc[e] = half ? acc[e] + cmulc(h[e], r2n[t + e * T]) : h[e];
+    for (int e = 0; e < E; ++e) acc[e] = half ? acc[e] + cmulc(h[e], r2n[(unsigned)(t + e * T)]) : h[e];
   }
   if (solve) {
     // transposed y-solve (Eq. (z_system) is symmetric): chunk of E per thread
@@ -816,7 +832,7 @@ __global__ void __launch_bounds__((spec_cfg<N>::T))
   for (int half = 0; half < 2; ++half) {
     cx<double> f[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) f[e] = half ? cmul(lo[e] - hi[e], r2n[t + e * T]) : lo[e] + hi[e];
+    for (int e = 0; e < E; ++e) f[e] = half ? cmul(lo[e] - hi[e], r2n[(unsigned)(t + e * T)]) : lo[e] + hi[e];
     fft<false, N, T>(f, lds, tw, t);
 #pragma unroll
     for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = f[e];
@@ -963,8 +979,15 @@ static hipError_t launch_col_t(const cx<R>* X, cx<R>* V, int M, int tj, const vo
   const TO* toy = kind == 0 ? (const TO*)ty : nullptr;
   const TC* tcx = kind == 1 ? (const TC*)tx : nullptr;
   const TC* tcy = kind == 1 ? (const TC*)ty : nullptr;
-  hipLaunchKernelGGL((k_col<R, TO, TC, N>), dim3(M / P), dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy,
-                     r2n, solve, kind, tw);
+  if (kind == 1)
+    hipLaunchKernelGGL((k_col<R, TO, TC, N, 1>), dim3(M / P), dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy,
+                       r2n, tw);
+  else if (solve)
+    hipLaunchKernelGGL((k_col<R, TO, TC, N, 2>), dim3(M / P), dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy,
+                       r2n, tw);
+  else
+    hipLaunchKernelGGL((k_col<R, TO, TC, N, 0>), dim3(M / P), dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy,
+                       r2n, tw);
   return hipGetLastError();
 }
 
@@ -1205,8 +1228,15 @@ static hipError_t launch_col_adj_t(const cx<R>* Xx, const cx<R>* Xy, cx<R>* Y, i
   const TO* toy = kind == 0 ? (const TO*)ty : nullptr;
   const TC* tcx = kind == 1 ? (const TC*)tx : nullptr;
   const TC* tcy = kind == 1 ? (const TC*)ty : nullptr;
-  hipLaunchKernelGGL((k_col_adj<R, TO, TC, N>), dim3(M / P), dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy, tcx,
-                     tcy, r2n, solve, kind, tw);
+  if (kind == 1)
+    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 1>), dim3(M / P), dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy,
+                       tcx, tcy, r2n, tw);
+  else if (solve)
+    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 2>), dim3(M / P), dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy,
+                       tcx, tcy, r2n, tw);
+  else
+    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 0>), dim3(M / P), dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy,
+                       tcx, tcy, r2n, tw);
   return hipGetLastError();
 }
 
