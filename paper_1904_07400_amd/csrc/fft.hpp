@@ -246,6 +246,78 @@ __device__ __forceinline__ void fft(cx<R>* v, cx<R>* lds, const cx<R>* __restric
   fft_stages<INV, L, T, 0>(v, lds, tw, t);
 }
 
+// Two independent transforms of the same length through the same stages,
+// sharing each exchange's barriers (lds0, lds1: separate padded buffers).
+template <bool INV, int L, int T, int r, int Ns, typename R>
+__device__ __forceinline__ void stockham_stage2(cx<R>* v0, cx<R>* v1, cx<R>* lds0, cx<R>* lds1,
+                                                const cx<R>* __restrict__ tw, int t) {
+  constexpr int E = L / T;
+  constexpr int NB = E / r;
+  constexpr bool last = (Ns * r == L);
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int b = t + u * T;
+    cx<R> a0[r], a1[r];
+#pragma unroll
+    for (int q = 0; q < r; ++q) {
+      a0[q] = v0[u + q * NB];
+      a1[q] = v1[u + q * NB];
+    }
+    if constexpr (Ns > 1) {
+      const unsigned k = (unsigned)b & (Ns - 1);
+#pragma unroll
+      for (int q = 1; q < r; ++q) {
+        const cx<R> w = tw[(unsigned)((q - 1) * Ns) + k];
+        a0[q] = INV ? cmulc(a0[q], w) : cmul(a0[q], w);
+        a1[q] = INV ? cmulc(a1[q], w) : cmul(a1[q], w);
+      }
+    }
+    dft<r, INV>(a0);
+    dft<r, INV>(a1);
+    if constexpr (last) {
+#pragma unroll
+      for (int q = 0; q < r; ++q) {
+        v0[u + q * NB] = a0[q];
+        v1[u + q * NB] = a1[q];
+      }
+    } else {
+      const int base = (b / Ns) * Ns * r + (b & (Ns - 1));
+#pragma unroll
+      for (int q = 0; q < r; ++q) {
+        lds0[pad(base + q * Ns)] = a0[q];
+        lds1[pad(base + q * Ns)] = a1[q];
+      }
+    }
+  }
+  if constexpr (!last) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      v0[e] = lds0[pad(t + e * T)];
+      v1[e] = lds1[pad(t + e * T)];
+    }
+    __syncthreads();
+  }
+}
+
+template <bool INV, int L, int T, int S, typename R>
+__device__ __forceinline__ void fft2_stages(cx<R>* v0, cx<R>* v1, cx<R>* lds0, cx<R>* lds1,
+                                            const cx<R>* __restrict__ tw, int t) {
+  using P = plan<L, L / T>;
+  if constexpr (S < P::nstages) {
+    stockham_stage2<INV, L, T, P::radix(S), P::ns_before(S)>(v0, v1, lds0, lds1, tw + P::tw_offset(S), t);
+    fft2_stages<INV, L, T, S + 1>(v0, v1, lds0, lds1, tw, t);
+  }
+}
+
+// fft() on two arrays at once (half the barriers of two calls).
+template <bool INV, int L, int T, typename R>
+__device__ __forceinline__ void fft2(cx<R>* v0, cx<R>* v1, cx<R>* lds0, cx<R>* lds1, const cx<R>* __restrict__ tw,
+                                     int t) {
+  static_assert(L % T == 0, "L must be a multiple of T");
+  fft2_stages<INV, L, T, 0>(v0, v1, lds0, lds1, tw, t);
+}
+
 // Fill the stage tables of plan<L, E> from a table of roots of unity
 // (roots(i) = exp(-2 pi i * i / L)); one thread per entry.
 template <int L, int E, typename R>

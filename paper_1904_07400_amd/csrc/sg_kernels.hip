@@ -51,6 +51,9 @@
 #ifndef SG_RF_E32
 #define SG_RF_E32 16
 #endif
+#ifndef SG_COL_NBUF32
+#define SG_COL_NBUF32 2
+#endif
 #ifndef SG_RF_E64
 #define SG_RF_E64 8
 #endif
@@ -340,7 +343,9 @@ struct col_cfg {
   static constexpr int LL = lds_len<N>::value;
   static constexpr int TRI = (int)(sizeof(tri_smem<double2, T>) / sizeof(cx<R>)) + 1;
   static constexpr int SLOT = LL > TRI ? LL : TRI;  // per-column LDS slot (complex elements)
-  static constexpr int BYTES = SLOT * (int)sizeof(cx<R>);
+  // exchange buffers per column: 2 lets two transforms share their barriers
+  static constexpr int NBUF = sizeof(R) == 4 ? SG_COL_NBUF32 : 1;
+  static constexpr int BYTES = NBUF * SLOT * (int)sizeof(cx<R>);
   static constexpr int P0 = T >= 256 ? 1 : 256 / T;
   static constexpr int PL = (65536 / BYTES) < 1 ? 1 : (65536 / BYTES);
   static constexpr int P = P0 < PL ? P0 : PL;
@@ -438,13 +443,14 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
   constexpr int kind = MODE == 1 ? 1 : 0;
   constexpr bool solve = MODE == 2;
   using C = col_cfg<R, N>;
-  constexpr int E = C::E, T = C::T, LL = C::SLOT;
-  __shared__ cx<R> smem[C::P * LL];
+  constexpr int E = C::E, T = C::T, LL = C::SLOT, NBUF = C::NBUF;
+  __shared__ cx<R> smem[C::P * LL * NBUF];
   const int P = blockDim.x / T;  // columns per workgroup (<= C::P, divides M)
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int c0 = tile * P, c = c0 + g;
-  cx<R>* lds = smem + g * LL;
+  cx<R>* lds = smem + g * LL * NBUF;
+  cx<R>* lds2 = lds + (NBUF - 1) * LL;
   const cx<R>* col = X + (int64_t)c * N;  // column c, contiguous (column-major X)
   cx<R> a[E];
   if (solve) {
@@ -476,28 +482,53 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     fo[e] = cmul(a[e], r2n[(unsigned)(t + e * T)]);
     fe[e] = a[e];
   }
-  fft<false, N, T>(fe, lds, tw, t);
-  fft<false, N, T>(fo, lds, tw, t);
-  // one half and one component at a time: g = f W^d, inverse, accumulate
-  // (the odd half with the phase exp(+i pi j / N))
   cx<R> accx[E], accy[E];
+  if constexpr (NBUF == 2) {
+    // both forward transforms, then per half both components' inverses,
+    // two at a time through the two exchange buffers
+    fft2<false, N, T>(fe, fo, lds, lds2, tw, t);
 #pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    const cx<R>* f = half ? fo : fe;
-#pragma unroll
-    for (int comp = 0; comp < 2; ++comp) {
-      cx<R> g[E];
-      col_product<R, TO, TC, N, E, T>(f, g, half, c0 == 0, packed, lds, kind, comp ? toy : tox, comp ? tcy : tcx,
-                                      comp ? (R)-1 : (R)1, c, M, t);
-      fft<true, N, T>(g, lds, tw, t);
-      cx<R>* acc = comp ? accy : accx;
+    for (int half = 0; half < 2; ++half) {
+      const cx<R>* f = half ? fo : fe;
+      cx<R> gx[E], gy[E];
+      col_product<R, TO, TC, N, E, T>(f, gx, half, c0 == 0, packed, lds, kind, tox, tcx, (R)1, c, M, t);
+      col_product<R, TO, TC, N, E, T>(f, gy, half, c0 == 0, packed, lds, kind, toy, tcy, (R)-1, c, M, t);
+      fft2<true, N, T>(gx, gy, lds, lds2, tw, t);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         if (half == 0) {
-          acc[e] = g[e];
+          accx[e] = gx[e];
+          accy[e] = gy[e];
         } else {
           const cx<R> w = r2n[(unsigned)(t + e * T)];  // conj -> exp(+i pi j / N)
-          acc[e] = acc[e] + cmulc(g[e], w);
+          accx[e] = accx[e] + cmulc(gx[e], w);
+          accy[e] = accy[e] + cmulc(gy[e], w);
+        }
+      }
+    }
+  } else {
+    fft<false, N, T>(fe, lds, tw, t);
+    fft<false, N, T>(fo, lds, tw, t);
+    // one half and one component at a time: g = f W^d, inverse, accumulate
+    // (the odd half with the phase exp(+i pi j / N))
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const cx<R>* f = half ? fo : fe;
+#pragma unroll
+      for (int comp = 0; comp < 2; ++comp) {
+        cx<R> g[E];
+        col_product<R, TO, TC, N, E, T>(f, g, half, c0 == 0, packed, lds, kind, comp ? toy : tox, comp ? tcy : tcx,
+                                        comp ? (R)-1 : (R)1, c, M, t);
+        fft<true, N, T>(g, lds, tw, t);
+        cx<R>* acc = comp ? accy : accx;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if (half == 0) {
+            acc[e] = g[e];
+          } else {
+            const cx<R> w = r2n[(unsigned)(t + e * T)];  // conj -> exp(+i pi j / N)
+            acc[e] = acc[e] + cmulc(g[e], w);
+          }
         }
       }
     }
