@@ -69,6 +69,108 @@ def time_plan(sg, torch, grid, prec, sigma_np, steps, warmup):
     return ms, [p / calls for p in pass_ms], plan_s, out
 
 
+KERNEL_SOURCES = ["paper_1904_07400_amd/csrc/sg_kernels.hip", "paper_1904_07400_amd/csrc/fft.hpp",
+                  "paper_1904_07400_amd/csrc/tridiag.hpp", "paper_1904_07400_amd/csrc/sg_internal.h",
+                  "paper_1904_07400_amd/build.py"]
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "forces_4096_k3_fp32_traffic.md")
+
+
+def kernel_source_hash():
+    """SHA-256 of the kernel sources and build flags (ties a counter profile to a build)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def calibration_copy(torch, mib):
+    """A plain device copy of known size (torch.neg: reads and writes mib MiB),
+    the reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def pmc_summary(fetch_csv, write_csv, mib, cells):
+    """Per-kernel HBM bytes from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE; KiB per dispatch), each scaled so that the calibration copy
+    (the torch.neg kernel of ``mib`` MiB) reads and writes exactly its size."""
+    import csv
+    import re
+    known = mib * (1 << 20)
+
+    def load(path, counter):
+        per = {}
+        for row in csv.DictReader(open(path)):
+            if row["Counter_Name"] != counter:
+                continue
+            name = row["Kernel_Name"]
+            per.setdefault(name, []).append(float(row["Counter_Value"]) * 1024.0)
+        return per
+
+    fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    cal = [k for k in fetch if "neg" in k.lower()]
+    if not cal:
+        raise SystemExit("calibration copy (torch.neg) not found in " + fetch_csv)
+    f_scale = known / max(fetch[cal[0]])
+    w_scale = known / max(write[cal[0]])
+    rows = []
+    for name in fetch:
+        if not re.search(r"k_(row_fwd|col|row_inv)<", name) or name not in write:
+            continue
+        f = sum(fetch[name]) / len(fetch[name]) * f_scale
+        w = sum(write[name]) / len(write[name]) * w_scale
+        short = re.sub(r"\(.*", "", name).replace("sg::", "").replace("void ", "")
+        rows.append((short, len(fetch[name]), f, w, (f + w) / cells))
+    return f_scale, w_scale, rows
+
+
+def trace_summary(stats_csv, trace_csv):
+    """Markdown table of a rocprofv3 kernel-trace run: durations from the
+    stats file, launch shape and LDS from the trace file."""
+    import csv
+    import re
+    shape = {r["Kernel_Name"]: r for r in csv.DictReader(open(trace_csv))}
+    out = ["| kernel | calls | avg us | min us | max us | % of GPU time | workgroup | grid (threads) | LDS B |",
+           "|---|---|---|---|---|---|---|---|---|"]
+    for r in csv.DictReader(open(stats_csv)):
+        if float(r["Percentage"]) < 0.05:
+            continue
+        m = shape.get(r["Name"], {})
+        nm = re.sub(r"HIP_vector_type<(\w+), (\d)u>", r"\1\2", r["Name"]).replace("sg::", "").replace("void ", "")
+        nm = re.sub(r"\(.*", "", nm)
+        if nm.startswith("at::native"):
+            nm = "at::native (PyTorch)"
+        out.append(f"| `{nm}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                   f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} | {m.get('Workgroup_Size_X', '')} | "
+                   f"{m.get('Grid_Size_X', '')} | {m.get('LDS_Block_Size', '')} |")
+    return "\n".join(out)
+
+
+def measured_traffic(kname, n):
+    """HBM bytes per launch of the FP32 kernel from the committed counter
+    profile, or None if there is none for this size or the kernels changed
+    since it was taken."""
+    import re
+    if n != 4096 or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    text = open(TRAFFIC_PROFILE).read()
+    m = re.search(r"source hash: (\w+)", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    for line in text.splitlines():
+        if line.startswith("| `" + kname + "<float"):
+            cols = [c.strip() for c in line.strip("|").split("|")]
+            return round((float(cols[2]) + float(cols[3])) * 1e6)
+    return None
+
+
 def cpu_baseline(n, k, sigma_np, sample):
     """The oracle (direct O(N^4) FP64 sum, OpenMP) on a bounded sample of cells."""
     import numpy as np
@@ -116,7 +218,26 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--prec", choices=["both", "fp32", "fp64"], default="both",
                     help="both (default, the metric) or one path only (profiling)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print per-kernel HBM traffic from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("STATS_CSV", "TRACE_CSV"),
+                    help="print a table of a rocprofv3 --kernel-trace --stats run and exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(trace_summary(*args.trace_summary))
+        return
+    if args.pmc_summary:
+        mib = args.copy_calibration_mib or 256
+        fs, ws, rows = pmc_summary(*args.pmc_summary, mib, args.n * args.n)
+        print(f"source hash: {kernel_source_hash()}")
+        print(f"calibration: torch.neg copy of {mib} MiB; FETCH scale {fs:.4f}, WRITE scale {ws:.4f}")
+        print("| kernel | dispatches | read MB/launch | written MB/launch | bytes/cell |")
+        print("|---|---|---|---|---|")
+        for name, nd, f, w, bpc in rows:
+            print(f"| `{name}` | {nd} | {f / 1e6:.1f} | {w / 1e6:.1f} | {bpc:.1f} |")
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the multi-GPU "
               "decomposition of this method is designed but not built", file=sys.stderr)
@@ -138,6 +259,8 @@ def main():
     xs = -1.0 + h * (off + np.arange(n))
     sigma = workloads.clump_sigma(workloads.clump_params(2, 32), xs, xs)
 
+    if args.copy_calibration_mib:
+        calibration_copy(torch, args.copy_calibration_mib)
     if args.prec != "both":
         prec = sg.SG_FP32_SPLIT if args.prec == "fp32" else sg.SG_FP64
         ms, passes, plan_s, _ = time_plan(sg, torch, grid, prec, sigma, args.steps, args.warmup)
@@ -153,9 +276,10 @@ def main():
     dom = max(range(3), key=lambda i: pass32[i])
     name = "ABC"[dom]
     achieved = bpc[name] * cells / (pass32[dom] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": {"A": "k_row_fwd", "B": "k_col", "C": "k_row_inv"}[name],
+    kname = {"A": "k_row_fwd", "B": "k_col", "C": "k_row_inv"}[name]
+    roofline = {"bound": "hbm", "kernel": kname,
                 "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(kname, n),
                 "bytes_per_cell": bpc[name], "kernel_ms": round(pass32[dom], 4)}
     total_bytes = sum(bpc.values()) * cells
     line = {
