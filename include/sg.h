@@ -62,8 +62,8 @@ typedef enum {
 } sg_precision;
 
 /* One grid.  Cell sizes are dx = (x1-x0)/nx, dy = (y1-y0)/ny (Sec. 2, grid
- * points x_{i+1/2} = x0 + i dx).  nx, ny: each a power of two from 4 to
- * 4096 (other sizes: SG_ERR_UNSUPPORTED). */
+ * points x_{i+1/2} = x0 + i dx).  nx, ny: each 2^a from 4 to 4096 or
+ * 3 * 2^a from 12 to 1536 (other sizes: SG_ERR_UNSUPPORTED). */
 typedef struct {
   int32_t nx, ny;
   double x0, x1, y0, y1;

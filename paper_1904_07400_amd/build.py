@@ -1,7 +1,8 @@
 """Compile the HIP library (libsg.so) for gfx950, in-tree.
 
-Sources: csrc/sg_kernels.hip (device kernels + launch dispatch) and
-csrc/sg_api.cpp (the C ABI of include/sg.h).  Every call recompiles.
+Sources: csrc/sg_kernels.hip (device kernels + launch dispatch, compiled as
+four objects in parallel) and csrc/sg_api.cpp (the C ABI of include/sg.h).
+Every call recompiles.
 """
 from __future__ import annotations
 
@@ -21,12 +22,16 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC, "--offload-
           # no packed FP32 instructions in device code
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]
-SOURCES = ["sg_kernels.hip", "sg_api.cpp"]
+# (source, extra flags, object name): the kernel file is compiled in four
+# parts (SG_PART) in parallel
+UNITS = [("sg_kernels.hip", ["-DSG_PART=%d" % i], "sg_kernels_p%d.o" % i) for i in range(4)] + \
+        [("sg_api.cpp", [], "sg_api.o")]
 
 
-def _compile(src: str, obj_dir: str) -> str:
-    obj = os.path.join(obj_dir, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit, obj_dir: str) -> str:
+    src, extra, name = unit
+    obj = os.path.join(obj_dir, name)
+    cmd = [HIPCC, *COMMON, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
@@ -90,9 +95,11 @@ def check_resources(obj: str) -> None:
 def build(verbose: bool = False) -> str:
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, obj_dir), SOURCES))
-    check_resources(objs[0])
+    with ThreadPoolExecutor(max_workers=len(UNITS)) as ex:
+        objs = list(ex.map(lambda u: _compile(u, obj_dir), UNITS))
+    for o, u in zip(objs, UNITS):
+        if u[0].endswith(".hip"):
+            check_resources(o)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

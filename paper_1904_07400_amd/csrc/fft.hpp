@@ -133,10 +133,25 @@ __device__ __forceinline__ void dft16(cx<R>* v) {
   }
 }
 
+// length 3: X_1,2 = a - (b + c)/2 -/+ i (sqrt(3)/2)(b - c) (forward; the
+// inverse swaps the sign of the imaginary term)
+template <bool INV, typename R>
+__device__ __forceinline__ void dft3(cx<R>* v) {
+  constexpr double S3 = 0.86602540378443864676;  // sqrt(3) / 2
+  const cx<R> a = v[0], b = v[1], c = v[2];
+  const cx<R> s = b + c, d = b - c;
+  const cx<R> m{a.x - (R)0.5 * s.x, a.y - (R)0.5 * s.y};
+  const cx<R> j = rot<INV>(cx<R>{d.x * (R)S3, d.y * (R)S3});  // -i (sqrt(3)/2) d forward
+  v[0] = a + s;
+  v[1] = m + j;
+  v[2] = m - j;
+}
+
 template <int r, bool INV, typename R>
 __device__ __forceinline__ void dft(cx<R>* v) {
   if constexpr (r == 1) {
   } else if constexpr (r == 2) dft2<INV>(v);
+  else if constexpr (r == 3) dft3<INV>(v);
   else if constexpr (r == 4) dft4<INV>(v);
   else if constexpr (r == 8) dft8<INV>(v);
   else if constexpr (r == 16) dft16<INV>(v);
@@ -144,17 +159,22 @@ __device__ __forceinline__ void dft(cx<R>* v) {
 }
 
 // ----------------------------------------------------------- radix plan --
-// Stages for length L with E elements per thread: radix R0 = min(E, 16)
-// while it fits, then the remainder (a power of two dividing R0); each
-// thread runs E / radix butterflies per stage.
+// Stages for length L = 2^a or 3 * 2^a with E elements per thread: for
+// L = 3 * 2^a a radix-3 stage first (E must then be a multiple of 3); then
+// radix R0 = the largest power of two dividing E (at most 16) while it fits,
+// then the power-of-two remainder.  Each stage of radix r runs E / r
+// butterflies per thread.
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+__host__ __device__ constexpr int pow2_part(int v) { return (v & 1) ? 1 : 2 * pow2_part(v / 2); }
 template <int L, int E>
 struct plan {
-  static constexpr int R0 = E < 16 ? E : 16;
-  static constexpr int nfull = ilog2c(L) / ilog2c(R0);
-  static constexpr int rem = L >> (nfull * ilog2c(R0));  // 1 if exact
-  static constexpr int nstages = nfull + (rem > 1 ? 1 : 0);
-  static constexpr int radix(int s) { return s < nfull ? R0 : rem; }
+  static constexpr int R3 = (L % 3 == 0) ? 1 : 0;  // leading radix-3 stage
+  static constexpr int L2 = R3 ? L / 3 : L;        // power-of-two part of L
+  static constexpr int R0 = pow2_part(E) < 16 ? pow2_part(E) : 16;
+  static constexpr int nfull = R0 > 1 ? ilog2c(L2) / ilog2c(R0) : 0;
+  static constexpr int rem = L2 >> (nfull * ilog2c(R0));  // 1 if exact
+  static constexpr int nstages = R3 + nfull + (rem > 1 ? 1 : 0);
+  static constexpr int radix(int s) { return s < R3 ? 3 : (s < R3 + nfull ? R0 : rem); }
   static constexpr int ns_before(int s) { return s == 0 ? 1 : ns_before(s - 1) * radix(s - 1); }
   // per-stage twiddle tables, stage s >= 1: entry (q-1)*Ns + k holds
   // w_{Ns r}^{k q}, q in [1, r), k in [0, Ns); tables laid end to end
@@ -162,6 +182,8 @@ struct plan {
     return s <= 1 ? 0 : tw_offset(s - 1) + (radix(s - 1) - 1) * ns_before(s - 1);
   }
   static constexpr int tw_size = tw_offset(nstages);
+  static_assert(L2 == (1 << ilog2c(L2)), "length must be 2^a or 3 * 2^a");
+  static_assert(E % (R3 ? 3 : 1) == 0 && (R0 == 1 ? L2 == 1 : true), "elements per thread do not fit the radices");
 };
 
 // LDS padding against bank conflicts: one slot every 16 elements
@@ -198,7 +220,7 @@ __device__ __forceinline__ void stockham_stage(cx<R>* v, cx<R>* lds, const cx<R>
     for (int q = 0; q < r; ++q) a[q] = v[u + q * NB];
     if constexpr (Ns > 1) {
       // unsigned 32-bit offsets from the uniform table base (scalar-base loads)
-      const unsigned k = (unsigned)b & (Ns - 1);
+      const unsigned k = (unsigned)b % (unsigned)Ns;
 #pragma unroll
       for (int q = 1; q < r; ++q) {
         const cx<R> w = tw[(unsigned)((q - 1) * Ns) + k];
@@ -211,7 +233,7 @@ __device__ __forceinline__ void stockham_stage(cx<R>* v, cx<R>* lds, const cx<R>
 #pragma unroll
       for (int q = 0; q < r; ++q) v[u + q * NB] = a[q];
     } else {
-      const int base = (b / Ns) * Ns * r + (b & (Ns - 1));
+      const int base = (b / Ns) * Ns * r + b % Ns;
 #pragma unroll
       for (int q = 0; q < r; ++q) lds[pad(base + q * Ns)] = a[q];
     }
@@ -264,7 +286,7 @@ __device__ __forceinline__ void stockham_stage2(cx<R>* v0, cx<R>* v1, cx<R>* lds
       a1[q] = v1[u + q * NB];
     }
     if constexpr (Ns > 1) {
-      const unsigned k = (unsigned)b & (Ns - 1);
+      const unsigned k = (unsigned)b % (unsigned)Ns;
 #pragma unroll
       for (int q = 1; q < r; ++q) {
         const cx<R> w = tw[(unsigned)((q - 1) * Ns) + k];
@@ -281,7 +303,7 @@ __device__ __forceinline__ void stockham_stage2(cx<R>* v0, cx<R>* v1, cx<R>* lds
         v1[u + q * NB] = a1[q];
       }
     } else {
-      const int base = (b / Ns) * Ns * r + (b & (Ns - 1));
+      const int base = (b / Ns) * Ns * r + b % Ns;
 #pragma unroll
       for (int q = 0; q < r; ++q) {
         lds0[pad(base + q * Ns)] = a0[q];

@@ -29,6 +29,8 @@ sg_status fail(sg_status s, const char* fmt, ...) {
 }
 
 bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+// Grid sizes with kernels: 2^a from 4 to 4096 and 3 * 2^a from 12 to 1536.
+bool size_ok(int v) { return pow2_in(v, 4, 4096) || (v % 3 == 0 && pow2_in(v / 3, 4, 512)); }
 
 // Roots of unity exp(-2 pi i k / B), k = 0..B-1, from long double sin/cos of
 // the octant-reduced angle (one rounding to the stored precision).
@@ -262,8 +264,9 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
         !(g.y1 > g.y0))
       return fail(SG_ERR_ARG, "grid %d: empty or non-finite domain", i);
     if (g.order < 1 || g.order > 3) return fail(SG_ERR_UNSUPPORTED, "grid %d: order %d (supported: 1..3)", i, g.order);
-    if (!pow2_in(g.nx, 4, 4096) || !pow2_in(g.ny, 4, 4096))
-      return fail(SG_ERR_UNSUPPORTED, "grid %d: %dx%d (supported: powers of two 4..4096)", i, g.nx, g.ny);
+    if (!size_ok(g.nx) || !size_ok(g.ny))
+      return fail(SG_ERR_UNSUPPORTED, "grid %d: %dx%d (supported: 2^a from 4 to 4096, 3*2^a from 12 to 1536)", i,
+                  g.nx, g.ny);
   }
   sg_plan p = new (std::nothrow) sg_plan_s();
   if (!p) return fail(SG_ERR_NOMEM, "host allocation failed");

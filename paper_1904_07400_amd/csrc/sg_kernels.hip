@@ -57,6 +57,10 @@
 #ifndef SG_RF_E64
 #define SG_RF_E64 8
 #endif
+// elements per thread for transform lengths 3 * 2^a (a multiple of 3)
+#ifndef SG_E3
+#define SG_E3 12
+#endif
 // minimum waves per SIMD the register allocation must allow (1 = no cap),
 // per pass and precision
 #ifndef SG_RF_WPE32
@@ -79,9 +83,19 @@
 #endif
 #define SG_WPE(R, P) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? SG_##P##_WPE32 : SG_##P##_WPE64)))
 
+// The host dispatch is split into parts that can be compiled as separate
+// objects in parallel (SG_PART = 0: plan-time and helper kernels, 1: row
+// passes, 2: column pass, 3: adjoint column and row passes); without
+// SG_PART everything is compiled.
+#ifndef SG_PART
+#define SG_PART -1
+#endif
+#define SG_IN_PART(n) (SG_PART < 0 || SG_PART == (n))
+
 namespace sg {
 
 // ------------------------------------------------------------- weights --
+#if SG_IN_PART(0)
 __constant__ double c_glx[4][16];
 __constant__ double c_glw[4][16];
 __constant__ int c_glq[4] = {4, 6, 10, 16};
@@ -204,7 +218,19 @@ __global__ void k_weights(int k, double hx, double hy, int M, int N, double* __r
   }
 }
 
+#endif
+
 // --------------------------------------------------------- common bits --
+// Elements per thread for a transform of length L: E0 (a power of two) for
+// L = 2^a, E3 (a multiple of 3) for L = 3 * 2^a, never more than L.
+__host__ __device__ constexpr int elems_for(int L, int E0, int E3) {
+  return (L % 3 == 0) ? (E3 < L ? E3 : L) : (E0 < L ? E0 : L);
+}
+// Largest power of two that divides v, capped at cap (a power of two).
+__host__ __device__ constexpr int pow2_div(int v, int cap) {
+  return (v % 2 == 0 && cap > 1) ? 2 * pow2_div(v / 2, cap / 2) : 1;
+}
+
 // Map the launch index to a tile so that consecutive tiles land on the same
 // XCD (workgroups are dealt round-robin over the 8 XCDs).
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
@@ -227,7 +253,7 @@ template <typename R, typename In, int M>
 struct rowfwd_cfg {
   static constexpr int L = M / 2;
   static constexpr int E0 = sizeof(R) == 4 ? SG_RF_E32 : SG_RF_E64;
-  static constexpr int E = E0 < L ? E0 : L;
+  static constexpr int E = elems_for(L, E0, SG_E3);
   static constexpr int T = L / E;
   static constexpr int LL = lds_len<L>::value;
   // per-row LDS slot (complex elements): FFT exchange buffer, also used
@@ -296,7 +322,7 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int pp = t + e * T;                         // X bin p = 2 pp
-    const cx<R> zp = ze[e], zm = conj(lds[pad((L - pp) & (L - 1))]);
+    const cx<R> zp = ze[e], zm = conj(lds[pad(pp == 0 ? 0 : L - pp)]);
     const cx<R> sum = zp + zm, dif = cmul(r2m[2 * pp], zp - zm);
     xe[e] = cx<R>{(R)0.5 * (sum.x + dif.y), (R)0.5 * (sum.y - dif.x)};
     if (pp == 0) xe[e] = cx<R>{zp.x + zp.y, zp.x - zp.y};
@@ -338,7 +364,7 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
 template <typename R, int N>
 struct col_cfg {
   static constexpr int E0 = sizeof(R) == 4 ? SG_COL_E32 : SG_COL_E64;
-  static constexpr int E = N < E0 ? N : E0;
+  static constexpr int E = elems_for(N, E0, SG_E3);
   static constexpr int T = N / E;
   static constexpr int LL = lds_len<N>::value;
   static constexpr int TRI = (int)(sizeof(tri_smem<double2, T>) / sizeof(cx<R>)) + 1;
@@ -419,7 +445,7 @@ __device__ __forceinline__ void col_product(const cx<R>* f, cx<R>* g, int half, 
   for (int e = 0; e < E; ++e) {
     const int qq = t + e * T;
     if (packed) {
-      const int qm = half == 0 ? ((N - qq) & (N - 1)) : (N - 1 - qq);
+      const int qm = half == 0 ? (qq == 0 ? 0 : N - qq) : (N - 1 - qq);
       const cx<R> u = f[e], um = conj(lds[pad(qm)]);
       const cx<R> c0v{(R)0.5 * (u.x + um.x), (R)0.5 * (u.y + um.y)};
       const cx<R> cmv{(R)0.5 * (u.y - um.y), (R)-0.5 * (u.x - um.x)};
@@ -569,7 +595,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
 template <typename R, int M>
 struct rowinv_cfg {
   static constexpr int L = M;
-  static constexpr int E = sizeof(R) == 4 ? (L < SG_RI_E32 ? L : SG_RI_E32) : (L < SG_RI_E64 ? L : SG_RI_E64);
+  static constexpr int E = elems_for(L, sizeof(R) == 4 ? SG_RI_E32 : SG_RI_E64, SG_E3);
   static constexpr int T = L / E;
   static constexpr int LL = lds_len<L>::value;
   static constexpr int G0 = SG_RI_THREADS / T < 1 ? 1 : (SG_RI_THREADS / T < 16 ? SG_RI_THREADS / T : 16);
@@ -633,7 +659,7 @@ __device__ __forceinline__ void col_products_adj(const cx<R>* fx, const cx<R>* f
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int qq = t + e * T;
-        umx[e] = conj(lds[pad(half == 0 ? ((N - qq) & (N - 1)) : (N - 1 - qq))]);
+        umx[e] = conj(lds[pad(half == 0 ? (qq == 0 ? 0 : N - qq) : (N - 1 - qq))]);
       }
     }
     __syncthreads();
@@ -644,7 +670,7 @@ __device__ __forceinline__ void col_products_adj(const cx<R>* fx, const cx<R>* f
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int qq = t + e * T;
-        umy[e] = conj(lds[pad(half == 0 ? ((N - qq) & (N - 1)) : (N - 1 - qq))]);
+        umy[e] = conj(lds[pad(half == 0 ? (qq == 0 ? 0 : N - qq) : (N - 1 - qq))]);
       }
     }
     __syncthreads();
@@ -764,7 +790,7 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, R, M>::G * rowfwd_cfg<R, R, M>:
     // Z'[p] = (X[p] + conj X[M-p]) + i conj(w_2M^p) (X[p] - conj X[M-p]), X[M] packed in slot 0
     const cx<R> xe = b0[(int64_t)pp * tj];                       // X[2pp]
     const cx<R> xo = b1[(int64_t)pp * tj];                       // X[2pp+1]
-    cx<R> me = conj(b0[(int64_t)((L - pp) & (L - 1)) * tj]);     // conj X[M - 2pp]
+    cx<R> me = conj(b0[(int64_t)(pp == 0 ? 0 : L - pp) * tj]);   // conj X[M - 2pp]
     const cx<R> mo = conj(b1[(int64_t)(L - 1 - pp) * tj]);       // conj X[M - 2pp - 1]
     if (pp == 0) {
       const cx<R> x0 = xe;  // (X_0, X_M)
@@ -821,7 +847,7 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, R, M>::G * rowfwd_cfg<R, R, M>:
 // Output element type: double / double2 (FP64 plans) or hi+lo floats.
 template <int N>
 struct spec_cfg {
-  static constexpr int E = N < 8 ? N : 8;
+  static constexpr int E = elems_for(N, 8, SG_E3);
   static constexpr int T = N / E;
   static constexpr int LL = lds_len<N>::value;
 };
@@ -875,7 +901,7 @@ __global__ void __launch_bounds__((spec_cfg<N>::T))
       int rows[2];
       int nv = 1;
       if (c == 0) {
-        const int qm = half == 0 ? ((N - qq) & (N - 1)) : (N - 1 - qq);
+        const int qm = half == 0 ? (qq == 0 ? 0 : N - qq) : (N - 1 - qq);
         const cx<double> u = f[e], um = conj(lds[pad(qm)]);
         vals[0] = cx<double>{0.5 * (u.x + um.x), 0.5 * (u.y + um.y)};
         vals[1] = cx<double>{0.5 * (u.y - um.y), -0.5 * (u.x - um.x)};
@@ -915,7 +941,7 @@ __global__ void k_check_finite(const In* __restrict__ x, int64_t n, int* __restr
 // the two commute.  The per-step force path fuses them into passes A and B.
 template <int M>
 struct coeff_cfg {
-  static constexpr int CH = M < 16 ? M : 16;
+  static constexpr int CH = elems_for(M, 16, 12);
   static constexpr int T = M / CH;
   static constexpr int G = T >= 256 ? 1 : 256 / T;
   static constexpr int SLOT = (int)sizeof(tri_smem<double, T>) / 8 + 1;
@@ -942,7 +968,7 @@ __global__ void __launch_bounds__((coeff_cfg<M>::G * coeff_cfg<M>::T))
 
 template <int N>
 struct coeffc_cfg {
-  static constexpr int CH = N < 16 ? N : 16;
+  static constexpr int CH = elems_for(N, 16, 12);
   static constexpr int T = N / CH;
   static constexpr int P = T >= 64 ? 1 : 64 / T;
   static constexpr int TRI = (int)sizeof(tri_smem<double, T>) / 8 + 1;
@@ -985,7 +1011,9 @@ struct tabs {
 };
 
 #ifndef SG_SIZES
-#define SG_SIZES(X) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+#define SG_SIZES(X)                                                                                        \
+  X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(12) X(24) X(48) X(96) X(192) X(384) \
+      X(768) X(1536)
 #endif
 
 template <typename R, typename In, int M>
@@ -1005,7 +1033,7 @@ static hipError_t launch_col_t(const cx<R>* X, cx<R>* V, int M, int tj, const vo
   using C = col_cfg<R, N>;
   using TO = typename tabs<R>::odd;
   using TC = typename tabs<R>::cplx;
-  const int P = C::P < M ? C::P : M;
+  const int P = pow2_div(M, C::P);
   const TO* tox = kind == 0 ? (const TO*)tx : nullptr;
   const TO* toy = kind == 0 ? (const TO*)ty : nullptr;
   const TC* tcx = kind == 1 ? (const TC*)tx : nullptr;
@@ -1045,6 +1073,7 @@ static hipError_t launch_spec_col_t(const cx<double>* S, int M, void* tab, int k
 // ------------------------------------------------- dispatch (host side) --
 using namespace sg;
 
+#if SG_IN_PART(0)
 hipError_t sg_launch_weights(int k, double hx, double hy, int M, int N, double* wx, double* wy, int layout,
                              hipStream_t st) {
   const int64_t total = (int64_t)(layout == 0 ? 2 * M : 2 * M - 1) * (layout == 0 ? 2 * N : 2 * N - 1);
@@ -1060,6 +1089,9 @@ hipError_t sg_set_gl_tables(const double* x, const double* w) {
   return hipMemcpyToSymbol(HIP_SYMBOL(c_glw), w, sizeof(double) * 64);
 }
 
+#endif
+
+#if SG_IN_PART(1)
 template <typename R, typename In>
 static hipError_t row_fwd_dispatch(int M, const In* src, int64_t ld, cx<R>* X, int nrows, const cx<R>* r2m,
                                    int solve, int full, const cx<R>* tw, hipStream_t st) {
@@ -1074,6 +1106,9 @@ static hipError_t row_fwd_dispatch(int M, const In* src, int64_t ld, cx<R>* X, i
   }
 }
 
+#endif
+
+#if SG_IN_PART(2)
 template <typename R>
 static hipError_t col_dispatch(int N, const cx<R>* X, cx<R>* V, int M, int tj, const void* tx, const void* ty,
                                int kind, const cx<R>* r2n, int solve, const cx<R>* tw, hipStream_t st) {
@@ -1088,6 +1123,9 @@ static hipError_t col_dispatch(int N, const cx<R>* X, cx<R>* V, int M, int tj, c
   }
 }
 
+#endif
+
+#if SG_IN_PART(1)
 template <typename R, typename Out>
 static hipError_t row_inv_dispatch(int M, const cx<R>* V, Out* fx, Out* fy, int nrows, int tj, const cx<R>* r2m,
                                    const cx<R>* tw, hipStream_t st) {
@@ -1102,6 +1140,9 @@ static hipError_t row_inv_dispatch(int M, const cx<R>* V, Out* fx, Out* fy, int 
   }
 }
 
+#endif
+
+#if SG_IN_PART(1)
 hipError_t sg_launch_row_fwd(int prec, int M, const void* src, int64_t ld, void* X, int nrows, const void* r2m,
                              int solve, int full, const void* tw, hipStream_t st) {
   if (prec == 0)
@@ -1111,6 +1152,9 @@ hipError_t sg_launch_row_fwd(int prec, int M, const void* src, int64_t ld, void*
                                         solve, full, (const cx<float>*)tw, st);
 }
 
+#endif
+
+#if SG_IN_PART(2)
 hipError_t sg_launch_col(int prec, int N, const void* X, void* V, int M, int tj, const void* tx, const void* ty,
                          int kind, const void* r2n, int solve, const void* tw, hipStream_t st) {
   if (prec == 0)
@@ -1126,6 +1170,9 @@ int sg_row_tile(int prec, int M, int N) {
   return tj < N ? tj : N;
 }
 
+#endif
+
+#if SG_IN_PART(1)
 hipError_t sg_launch_row_inv(int prec, int M, const void* V, void* fx, void* fy, int nrows, int tj, const void* r2m,
                              const void* tw, hipStream_t st) {
   if (prec == 0)
@@ -1135,6 +1182,9 @@ hipError_t sg_launch_row_inv(int prec, int M, const void* V, void* fx, void* fy,
                                         (const cx<float>*)r2m, (const cx<float>*)tw, st);
 }
 
+#endif
+
+#if SG_IN_PART(0)
 hipError_t sg_launch_spec_col(int N, const void* rowspec, int M, void* tab, int kind, int fp32, double scale,
                               const void* r2n, const void* tw, hipStream_t st) {
   switch (N) {
@@ -1183,7 +1233,7 @@ static hipError_t coeff_cols_dispatch(int N, R* data, int M, hipStream_t st) {
 #define CASE(SZ)                                                                                      \
   case SZ: {                                                                                          \
     using C = coeffc_cfg<SZ>;                                                                         \
-    const int P = C::P < M ? C::P : M;                                                               \
+    const int P = pow2_div(M, C::P);                                                               \
     hipLaunchKernelGGL((k_coeff_cols<R, SZ>), dim3(M / P), dim3(P * C::T), 0, st, data, M);           \
     return hipGetLastError();                                                                        \
   }
@@ -1246,6 +1296,9 @@ int sg_twiddles(int prec, int pass, int len, const void* roots, void* out, hipSt
   return prec == 0 ? tw_dispatch<double>(pass, len, roots, out, st) : tw_dispatch<float>(pass, len, roots, out, st);
 }
 
+#endif
+
+#if SG_IN_PART(3)
 // ------------------------------------------------------ adjoint launches --
 template <typename R, int N>
 static hipError_t launch_col_adj_t(const cx<R>* Xx, const cx<R>* Xy, cx<R>* Y, int M, int tj, const void* tx,
@@ -1254,7 +1307,7 @@ static hipError_t launch_col_adj_t(const cx<R>* Xx, const cx<R>* Xy, cx<R>* Y, i
   using C = col_cfg<R, N>;
   using TO = typename tabs<R>::odd;
   using TC = typename tabs<R>::cplx;
-  const int P = C::P < M ? C::P : M;
+  const int P = pow2_div(M, C::P);
   const TO* tox = kind == 0 ? (const TO*)tx : nullptr;
   const TO* toy = kind == 0 ? (const TO*)ty : nullptr;
   const TC* tcx = kind == 1 ? (const TC*)tx : nullptr;
@@ -1319,3 +1372,4 @@ hipError_t sg_launch_adjoint_tail(int prec, int M, int N, const void* Xx, const 
                              ty, kind, (const cx<float>*)r2m, (const cx<float>*)r2n, solve, (const cx<float>*)twB,
                              (const cx<float>*)twA, st);
 }
+#endif

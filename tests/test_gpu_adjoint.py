@@ -31,7 +31,8 @@ def _sg():
 
 
 ADJ_CASES = [(1, 16, 16, (-1, 1, -1, 1)), (2, 32, 16, (-1, 1, -1, 1)), (3, 64, 64, (-1, 1, -1, 1)),
-             (3, 8, 128, (-1, 1, -0.5, 1.5)), (2, 4, 4, (-1, 1, -1, 1)), (3, 256, 128, (-1, 1, -1, 1))]
+             (3, 8, 128, (-1, 1, -0.5, 1.5)), (2, 4, 4, (-1, 1, -1, 1)), (3, 256, 128, (-1, 1, -1, 1)),
+             (3, 96, 48, (-1, 1, -1, 1)), (2, 24, 12, (-1, 1, -1, 1)), (1, 192, 96, (-1, 1, -1, 1))]
 
 
 @pytest.mark.parametrize("k,M,N,dom", ADJ_CASES, ids=[f"k{c[0]}-{c[1]}x{c[2]}" for c in ADJ_CASES])

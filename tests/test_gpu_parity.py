@@ -92,6 +92,12 @@ CASES = [
     (3, 4, 4, (-1, 1, -1, 1), "random"),
     (3, 8, 512, (-1, 1, -1, 1), "random"),
     (3, 256, 256, (-1, 1, -1, 1), "clumps"),
+    # sizes 3 * 2^a (a radix-3 stage in every transform)
+    (3, 96, 96, (-1, 1, -1, 1), "clumps"),
+    (2, 48, 192, (-1, 1, -1, 1), "random"),
+    (1, 12, 24, (-1, 1, -1, 1), "random"),
+    (3, 384, 96, (-1, 1, -0.5, 0.5), "clumps"),
+    (3, 12, 12, (-1, 1, -1, 1), "random"),
 ]
 
 
@@ -119,7 +125,7 @@ def test_forces_fp64_and_fp32_match_oracle(k, M, N, dom, kind):
 
 
 @pytest.mark.parametrize("k", [1, 2, 3])
-@pytest.mark.parametrize("n", [1024, 4096])
+@pytest.mark.parametrize("n", [1024, 4096, 1536])
 def test_forces_full_size_sparse_impulses(k, n):
     """Full-size grids: C = a few seeded impulses (sigma = S C, Eq. (sigmaW)),
     so the oracle's exact superposition gives F at sampled cells."""
