@@ -72,6 +72,8 @@ typedef struct {
 
 /* plan flags */
 #define SG_FLAG_CHECK_FINITE 0x1u /* sg_forces rejects non-finite sigma (SG_ERR_STATE); costs one extra read */
+#define SG_FLAG_GRAPH 0x2u        /* sg_forces replays a captured HIP graph of the whole step (see sg_forces) */
+#define SG_FLAG_AUTOTUNE 0x4u     /* sg_plan_create times the launch tiles of every class and keeps the best */
 
 /* Create a plan for ngrids grids (all of one precision) on the given HIP
  * stream (hipStream_t; NULL = the null stream).  Plan time does what the
@@ -115,8 +117,24 @@ sg_status sg_bspline_coeffs(sg_plan p, const void* sigma, void* coeffs);
 /* sigma -> (Fx, Fy) at the cell centres for every grid of the plan:
  * coefficient solve, then one forward and two inverse zero-padded FFT
  * convolutions (Sec. 4.2).  Packed buffers; fx and fy must not alias sigma
- * or each other. */
+ * or each other.
+ *
+ * Batching: the plan groups its grids into classes of equal (nx, ny, order);
+ * each of the three passes is one launch for all grids of a class.  With
+ * SG_FLAG_GRAPH the whole step (every class and pass, classes spread over
+ * up to four plan-owned streams so that they overlap) is captured as a HIP
+ * graph on the first call with a given (sigma, fx, fy) and replayed on
+ * later calls with the same pointers (the four most recent are kept); the
+ * replay is ordered after earlier work on the plan's stream and before
+ * later work on it.  Per-pass timing is not recorded for graph plans. */
 sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy);
+
+/* The plan's grid classes: *nclasses (HOST) and, for the first cap classes,
+ * 8 HOST int32 each in info: nx, ny, order, number of grids, then the rows
+ * per workgroup of the row passes and the columns per workgroup of the
+ * column pass in use (A, B, C; chosen by the autotuner with
+ * SG_FLAG_AUTOTUNE), then 0.  info may be NULL. */
+sg_status sg_plan_classes(sg_plan p, int32_t* nclasses, int32_t* info, int32_t cap);
 
 /* Adjoint of sg_forces: gsigma = d<gfx,Fx> + <gfy,Fy> / d sigma, i.e. the
  * transposed convolutions (correlation with the weights) followed by the

@@ -18,7 +18,8 @@ import os
 import threading
 
 __all__ = [
-    "SG_FP64", "SG_FP32_SPLIT", "SG_FLAG_CHECK_FINITE", "SGError", "sg_grid", "lib",
+    "SG_FP64", "SG_FP32_SPLIT", "SG_FLAG_CHECK_FINITE", "SG_FLAG_GRAPH", "SG_FLAG_AUTOTUNE", "SGError",
+    "sg_grid", "lib", "sg_plan_classes",
     "sg_plan_create", "sg_plan_destroy", "sg_plan_layout", "sg_plan_info", "sg_sample_points",
     "sg_weights", "sg_bspline_coeffs", "sg_forces", "sg_forces_adjoint", "sg_status_string",
     "sg_last_error_message", "sg_plan_set_timing", "sg_plan_pass_times", "Plan", "ThinDiskForces",
@@ -27,6 +28,8 @@ __all__ = [
 SG_FP64 = 0
 SG_FP32_SPLIT = 1
 SG_FLAG_CHECK_FINITE = 0x1
+SG_FLAG_GRAPH = 0x2
+SG_FLAG_AUTOTUNE = 0x4
 STATUS = {0: "SG_OK", 1: "SG_ERR_ARG", 2: "SG_ERR_UNSUPPORTED", 3: "SG_ERR_NOMEM",
           4: "SG_ERR_DEVICE", 5: "SG_ERR_STATE"}
 
@@ -70,6 +73,7 @@ def lib() -> ctypes.CDLL:
             L.sg_forces.argtypes = [vp, vp, vp, vp]
             L.sg_forces_adjoint.argtypes = [vp, vp, vp, vp]
             L.sg_plan_set_timing.argtypes = [vp, i32]
+            L.sg_plan_classes.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), i32]
             L.sg_plan_pass_times.argtypes = [vp, dp, ctypes.POINTER(i64)]
             L.sg_status_string.argtypes = [ctypes.c_int]
             L.sg_status_string.restype = ctypes.c_char_p
@@ -77,7 +81,7 @@ def lib() -> ctypes.CDLL:
             L.sg_last_error_message.restype = ctypes.c_char_p
             for f in ("sg_plan_create", "sg_plan_destroy", "sg_plan_layout", "sg_plan_info",
                       "sg_sample_points", "sg_weights", "sg_bspline_coeffs", "sg_forces",
-                      "sg_forces_adjoint", "sg_plan_set_timing", "sg_plan_pass_times"):
+                      "sg_forces_adjoint", "sg_plan_set_timing", "sg_plan_pass_times", "sg_plan_classes"):
                 getattr(L, f).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -151,6 +155,15 @@ def sg_plan_pass_times(plan: int):
     calls = ctypes.c_int64()
     _check(lib().sg_plan_pass_times(plan, ms, ctypes.byref(calls)))
     return list(ms), calls.value
+
+
+def sg_plan_classes(plan: int):
+    """[(nx, ny, order, ngrids, tile_A, tile_B, tile_C), ...] of the plan's grid classes."""
+    n = ctypes.c_int32()
+    _check(lib().sg_plan_classes(plan, ctypes.byref(n), None, 0))
+    info = (ctypes.c_int32 * (8 * max(n.value, 1)))()
+    _check(lib().sg_plan_classes(plan, ctypes.byref(n), info, n.value))
+    return [tuple(info[8 * i:8 * i + 7]) for i in range(n.value)]
 
 
 def sg_sample_points(plan: int, g: int):

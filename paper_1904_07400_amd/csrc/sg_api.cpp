@@ -7,8 +7,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "sg.h"
@@ -107,10 +109,33 @@ struct GridPlan {
   void* twC = nullptr;
 };
 
+// Grids of one size and order: one launch per pass runs all of them
+// (descriptor array desc on the device, blockIdx.y = member).
+struct GridClass {
+  int M, N, k;
+  std::vector<int> members;
+  sg_bgrid* desc = nullptr;
+  int tile[3] = {0, 0, 0};  // rows / columns per workgroup of passes A, B, C (0 = compiled maximum)
+};
+
+// One captured step: the graph of every class's three launches for a given
+// (sigma, fx, fy), classes spread over the plan's side streams.
+struct StepGraph {
+  const void* sigma;
+  void* fx;
+  void* fy;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 }  // namespace
 
 struct sg_plan_s {
   std::vector<GridPlan> grids;
+  std::vector<GridClass> classes;
+  std::vector<hipStream_t> side;    // streams of a captured step (default priority)
+  std::vector<hipEvent_t> sync_ev;  // fork / join events of the captured step
+  std::vector<StepGraph> graphs;    // most recent first, at most kMaxGraphs
   sg_precision prec;
   hipStream_t st;
   uint32_t flags;
@@ -172,8 +197,21 @@ void drop_events(sg_plan p) {
   p->timed_calls = 0;
 }
 
+void drop_graphs(sg_plan p) {
+  for (StepGraph& g : p->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  p->graphs.clear();
+}
+
 void release(sg_plan p) {
   drop_events(p);
+  drop_graphs(p);
+  for (hipEvent_t e : p->sync_ev) (void)hipEventDestroy(e);
+  p->sync_ev.clear();
+  for (hipStream_t q : p->side) (void)hipStreamDestroy(q);
+  p->side.clear();
   for (void* a : p->allocs) (void)hipFree(a);
   p->allocs.clear();
 }
@@ -220,15 +258,152 @@ sg_status build_spectra(sg_plan p, GridPlan& G, const void* r2m64, const void* r
   const double scale = 1.0 / (4.0 * (double)M * (double)N);
   sg_status st = SG_OK;
   e = sg_launch_weights(G.k, G.hx, G.hy, M, N, wpx, wpy, 0, p->st);
-  if (e == hipSuccess) e = sg_launch_row_fwd(0, M, wpx, 2 * M, S, 2 * N, r2m64, 0, 1, twA64, p->st);
+  if (e == hipSuccess) e = sg_launch_row_fwd(0, M, wpx, 2 * M, S, 2 * N, r2m64, 0, 1, twA64, nullptr, 1, 0, p->st);
   if (e == hipSuccess) e = sg_launch_spec_col(N, S, M, G.tabx, G.kind, fp32, scale, r2n64, twS64, p->st);
-  if (e == hipSuccess) e = sg_launch_row_fwd(0, M, wpy, 2 * M, S, 2 * N, r2m64, 0, 1, twA64, p->st);
+  if (e == hipSuccess) e = sg_launch_row_fwd(0, M, wpy, 2 * M, S, 2 * N, r2m64, 0, 1, twA64, nullptr, 1, 0, p->st);
   if (e == hipSuccess) e = sg_launch_spec_col(N, S, M, G.taby, G.kind, fp32, scale, r2n64, twS64, p->st);
   if (e == hipSuccess) e = hipStreamSynchronize(p->st);
   if (e != hipSuccess) st = hip_check(p, e, "plan-time spectrum");
   (void)hipFree(wp);
   (void)hipFree(S);
   return st;
+}
+
+constexpr size_t kMaxGraphs = 4;
+constexpr int kSideStreams = 4;
+
+// The three launches of every grid of one class on stream q.
+hipError_t issue_class(sg_plan p, const GridClass& c, const void* sigma, void* fx, void* fy, hipStream_t q,
+                       const int* tile) {
+  const int prec = p->prec == SG_FP64 ? 0 : 1;
+  const GridPlan& G = p->grids[c.members[0]];
+  const int solve = c.k == 3 ? 1 : 0;
+  const int ng = (int)c.members.size();
+  const int tj = sg_row_tile(prec, c.M, c.N);
+  hipError_t e = sg_launch_row_fwd(prec, c.M, sigma, c.M, nullptr, c.N, G.r2m, solve, 0, G.twA, c.desc, ng, tile[0], q);
+  if (e == hipSuccess)
+    e = sg_launch_col(prec, c.N, nullptr, nullptr, c.M, tj, nullptr, nullptr, G.kind, G.r2n, solve, G.twB, c.desc, ng,
+                      tile[1], q);
+  if (e == hipSuccess)
+    e = sg_launch_row_inv(prec, c.M, nullptr, fx, fy, c.N, tj, G.r2m, G.twC, c.desc, ng, tile[2], q);
+  return e;
+}
+
+// Capture the whole step (every class) for these buffers: classes spread
+// round-robin over the plan's side streams, forked from and joined to the
+// first one.
+sg_status capture_step(sg_plan p, const void* sigma, void* fx, void* fy, StepGraph* out) {
+  const int nside = (int)p->side.size();
+  hipStream_t q0 = p->side[0];
+  hipError_t e = hipStreamBeginCapture(q0, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_check(p, e, "hipStreamBeginCapture");
+  hipError_t ce = hipEventRecord(p->sync_ev[0], q0);
+  for (int i = 1; i < nside && ce == hipSuccess; ++i) ce = hipStreamWaitEvent(p->side[i], p->sync_ev[0], 0);
+  for (size_t ci = 0; ci < p->classes.size() && ce == hipSuccess; ++ci)
+    ce = issue_class(p, p->classes[ci], sigma, fx, fy, p->side[ci % nside], p->classes[ci].tile);
+  for (int i = 1; i < nside && ce == hipSuccess; ++i) {
+    ce = hipEventRecord(p->sync_ev[i], p->side[i]);
+    if (ce == hipSuccess) ce = hipStreamWaitEvent(q0, p->sync_ev[i], 0);
+  }
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(q0, &g);
+  if (ce != hipSuccess || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_check(p, ce != hipSuccess ? ce : e, "step capture");
+  }
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_check(p, e, "hipGraphInstantiate");
+  }
+  out->sigma = sigma;
+  out->fx = fx;
+  out->fy = fy;
+  out->graph = g;
+  out->exec = x;
+  return SG_OK;
+}
+
+// Time pass `pass` of class c with a candidate tile (ms per launch, median of
+// reps), on scratch buffers.
+sg_status time_tile(sg_plan p, GridClass& c, int pass, int tile, const void* sig, void* fx, void* fy, float* ms) {
+  int t3[3] = {c.tile[0], c.tile[1], c.tile[2]};
+  t3[pass] = tile;
+  const int prec = p->prec == SG_FP64 ? 0 : 1;
+  const GridPlan& G = p->grids[c.members[0]];
+  const int solve = c.k == 3 ? 1 : 0;
+  const int ng = (int)c.members.size();
+  const int tj = sg_row_tile(prec, c.M, c.N);
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return fail(SG_ERR_DEVICE, "hipEventCreate");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(SG_ERR_DEVICE, "hipEventCreate");
+  }
+  const int reps = 5;
+  float best = 1e30f;
+  hipError_t e = hipSuccess;
+  for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+    e = hipEventRecord(a, p->st);
+    if (e != hipSuccess) break;
+    if (pass == 0)
+      e = sg_launch_row_fwd(prec, c.M, sig, c.M, nullptr, c.N, G.r2m, solve, 0, G.twA, c.desc, ng, t3[0], p->st);
+    else if (pass == 1)
+      e = sg_launch_col(prec, c.N, nullptr, nullptr, c.M, tj, nullptr, nullptr, G.kind, G.r2n, solve, G.twB, c.desc,
+                        ng, t3[1], p->st);
+    else
+      e = sg_launch_row_inv(prec, c.M, nullptr, fx, fy, c.N, tj, G.r2m, G.twC, c.desc, ng, t3[2], p->st);
+    if (e == hipSuccess) e = hipEventRecord(b, p->st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    if (r > 0 && t < best) best = t;  // first run warms up
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return hip_check(p, e, "autotune timing");
+  *ms = best;
+  return SG_OK;
+}
+
+// Autotuner: per class and pass, the tile (rows or columns per workgroup,
+// powers of two up to the compiled maximum) with the shortest time, the
+// passes tuned in order A, B, C.
+sg_status autotune(sg_plan p) {
+  const size_t el = p->prec == SG_FP64 ? 8 : 4;
+  void *sig = nullptr, *fx = nullptr, *fy = nullptr;
+  sg_status s = SG_OK;
+  hipError_t e = hipMalloc(&sig, el * (size_t)p->total);
+  if (e == hipSuccess) e = hipMalloc(&fx, el * (size_t)p->total);
+  if (e == hipSuccess) e = hipMalloc(&fy, el * (size_t)p->total);
+  if (e == hipSuccess) e = hipMemsetAsync(sig, 0, el * (size_t)p->total, p->st);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    s = fail(SG_ERR_NOMEM, "autotune buffers: %s", hipGetErrorString(e));
+  }
+  const int prec = p->prec == SG_FP64 ? 0 : 1;
+  for (GridClass& c : p->classes) {
+    for (int pass = 0; pass < 3 && s == SG_OK; ++pass) {
+      const int cap = sg_max_tile(prec, pass, pass == 1 ? c.N : c.M);
+      int best_tile = 0;
+      float best = 1e30f;
+      for (int t = 1; t <= cap && s == SG_OK; t *= 2) {
+        float ms = 0.0f;
+        s = time_tile(p, c, pass, t, sig, fx, fy, &ms);
+        if (s == SG_OK && ms < best) {
+          best = ms;
+          best_tile = t;
+        }
+      }
+      if (s == SG_OK) c.tile[pass] = best_tile;
+    }
+  }
+  (void)hipStreamSynchronize(p->st);
+  if (sig) (void)hipFree(sig);
+  if (fx) (void)hipFree(fx);
+  if (fy) (void)hipFree(fy);
+  return s;
 }
 
 }  // namespace
@@ -256,7 +431,8 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
   *out = nullptr;
   if (!grids || ngrids < 1) return fail(SG_ERR_ARG, "need at least one grid (ngrids=%d)", ngrids);
   if (prec != SG_FP64 && prec != SG_FP32_SPLIT) return fail(SG_ERR_ARG, "unknown precision %d", (int)prec);
-  if (flags & ~SG_FLAG_CHECK_FINITE) return fail(SG_ERR_ARG, "unknown flags 0x%x", flags);
+  if (flags & ~(SG_FLAG_CHECK_FINITE | SG_FLAG_GRAPH | SG_FLAG_AUTOTUNE))
+    return fail(SG_ERR_ARG, "unknown flags 0x%x", flags);
   for (int i = 0; i < ngrids; ++i) {
     const sg_grid& g = grids[i];
     if (g.nx < 2 || g.ny < 2) return fail(SG_ERR_ARG, "grid %d: nx=%d ny=%d (need >= 2)", i, g.nx, g.ny);
@@ -290,6 +466,8 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
   }
   const size_t cb = prec == SG_FP64 ? 16 : 8;  // complex element bytes
   std::map<int, void*> roots64;
+  std::map<std::pair<int, int>, void*> tw;  // (pass, length) -> stage twiddles
+  std::map<std::tuple<int, int, int, double, double>, std::pair<void*, void*>> spectra;  // shared weight spectra
   sg_status s = SG_OK;
   int64_t off = 0;
   for (int i = 0; i < ngrids && s == SG_OK; ++i) {
@@ -305,8 +483,17 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
     off += (int64_t)G.M * G.N;
     const size_t tab_el = G.kind == 0 ? 8 : 16;  // odd k: one real (FP64 or hi+lo FP32); k=2: complex
     const size_t tab_n = G.kind == 0 ? (size_t)(G.M + 1) * (G.N + 1) : (size_t)(G.M + 1) * 2 * G.N;
-    if (s == SG_OK) s = dev_alloc(p, &G.tabx, tab_el * tab_n);
-    if (s == SG_OK) s = dev_alloc(p, &G.taby, tab_el * tab_n);
+    // grids of equal size, order and cell shape share one pair of spectra
+    const auto key = std::make_tuple(G.M, G.N, G.k, G.hx, G.hy);
+    const bool fresh = !spectra.count(key);
+    if (fresh) {
+      if (s == SG_OK) s = dev_alloc(p, &G.tabx, tab_el * tab_n);
+      if (s == SG_OK) s = dev_alloc(p, &G.taby, tab_el * tab_n);
+      if (s == SG_OK) spectra[key] = std::make_pair(G.tabx, G.taby);
+    } else {
+      G.tabx = spectra[key].first;
+      G.taby = spectra[key].second;
+    }
     if (s == SG_OK) s = dev_alloc(p, &G.X, cb * (size_t)G.M * G.N);
     if (s == SG_OK) s = dev_alloc(p, &G.V, cb * 2 * (size_t)G.M * G.N);
     for (int B : {2 * G.M, 2 * G.N}) {
@@ -326,14 +513,71 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
       G.r2m = p->roots[2 * G.M];
       G.r2n = p->roots[2 * G.N];
       const int pc = prec == SG_FP64 ? 0 : 1;
-      s = make_twiddles(p, pc, 0, G.M, G.r2m, &G.twA);
-      if (s == SG_OK) s = make_twiddles(p, pc, 1, G.N, G.r2n, &G.twB);
-      if (s == SG_OK) s = make_twiddles(p, pc, 2, G.M, G.r2m, &G.twC);
-      if (s == SG_OK) s = build_spectra(p, G, roots64[2 * G.M], roots64[2 * G.N]);
+      void** slots[3] = {&G.twA, &G.twB, &G.twC};
+      for (int pass = 0; pass < 3 && s == SG_OK; ++pass) {
+        const int len = pass == 1 ? G.N : G.M;
+        const auto tk = std::make_pair(pass, len);
+        if (!tw.count(tk)) {
+          void* d = nullptr;
+          s = make_twiddles(p, pc, pass, len, pass == 1 ? G.r2n : G.r2m, &d);
+          tw[tk] = d;
+        }
+        *slots[pass] = tw[tk];
+      }
+      if (s == SG_OK && fresh) s = build_spectra(p, G, roots64[2 * G.M], roots64[2 * G.N]);
     }
     p->grids.push_back(G);
   }
   p->total = off;
+  // classes of equal (nx, ny, order), in order of first appearance, with
+  // their device descriptors
+  for (int i = 0; i < (int)p->grids.size() && s == SG_OK; ++i) {
+    const GridPlan& G = p->grids[i];
+    GridClass* c = nullptr;
+    for (GridClass& x : p->classes)
+      if (x.M == G.M && x.N == G.N && x.k == G.k) c = &x;
+    if (!c) {
+      p->classes.push_back(GridClass{G.M, G.N, G.k, {}, nullptr, {0, 0, 0}});
+      c = &p->classes.back();
+    }
+    c->members.push_back(i);
+  }
+  for (GridClass& c : p->classes) {
+    if (s != SG_OK) break;
+    std::vector<sg_bgrid> h(c.members.size());
+    for (size_t j = 0; j < c.members.size(); ++j) {
+      const GridPlan& G = p->grids[c.members[j]];
+      h[j] = sg_bgrid{G.off, G.X, G.V, G.tabx, G.taby};
+    }
+    s = dev_alloc(p, (void**)&c.desc, h.size() * sizeof(sg_bgrid));
+    if (s == SG_OK)
+      s = hip_check(p, hipMemcpy(c.desc, h.data(), h.size() * sizeof(sg_bgrid), hipMemcpyHostToDevice),
+                    "descriptor upload");
+  }
+  if (s == SG_OK && (flags & SG_FLAG_GRAPH)) {
+    const int nside = std::min<int>(kSideStreams, (int)p->classes.size());
+    for (int i = 0; i < nside && s == SG_OK; ++i) {
+      hipStream_t q = nullptr;
+      hipEvent_t ev = nullptr;
+      if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess)
+        s = fail(SG_ERR_DEVICE, "hipStreamCreateWithFlags");
+      else
+        p->side.push_back(q);
+      if (s == SG_OK && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+        s = fail(SG_ERR_DEVICE, "hipEventCreateWithFlags");
+      else if (s == SG_OK)
+        p->sync_ev.push_back(ev);
+    }
+    // two more: the caller's stream -> side stream 0, and back
+    for (int i = 0; i < 2 && s == SG_OK; ++i) {
+      hipEvent_t ev = nullptr;
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+        s = fail(SG_ERR_DEVICE, "hipEventCreateWithFlags");
+      else
+        p->sync_ev.push_back(ev);
+    }
+  }
+  if (s == SG_OK && (flags & SG_FLAG_AUTOTUNE)) s = autotune(p);
   if (s == SG_OK) s = dev_alloc(p, (void**)&p->flag, sizeof(int));
   if (s != SG_OK) {
     std::string keep = g_msg;
@@ -426,7 +670,6 @@ sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy) {
   if (!sigma || !fx || !fy) return fail(SG_ERR_ARG, "sigma, fx or fy is NULL");
   if (fx == fy || fx == sigma || fy == sigma) return fail(SG_ERR_ARG, "fx, fy and sigma must not alias");
   const int prec = p->prec == SG_FP64 ? 0 : 1;
-  const size_t el = prec == 0 ? 8 : 4;
   if (p->flags & SG_FLAG_CHECK_FINITE) {
     int h = 0;
     hipError_t e = hipMemsetAsync(p->flag, 0, sizeof(int), p->st);
@@ -436,24 +679,92 @@ sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy) {
     if (e != hipSuccess) return hip_check(p, e, "finite check");
     if (h) return fail(SG_ERR_STATE, "sigma holds NaN or Inf");
   }
-  for (const GridPlan& G : p->grids) {
-    const char* src = (const char*)sigma + el * G.off;
-    char* ox = (char*)fx + el * G.off;
-    char* oy = (char*)fy + el * G.off;
-    const int solve = G.k == 3 ? 1 : 0;
+  if (p->flags & SG_FLAG_GRAPH) {
+    // replay the captured step for these buffers (capture it on first use),
+    // ordered after the caller's stream and before its later work
+    StepGraph* g = nullptr;
+    for (size_t i = 0; i < p->graphs.size(); ++i)
+      if (p->graphs[i].sigma == sigma && p->graphs[i].fx == fx && p->graphs[i].fy == fy) {
+        std::rotate(p->graphs.begin(), p->graphs.begin() + i, p->graphs.begin() + i + 1);
+        g = &p->graphs[0];
+        break;
+      }
+    if (!g) {
+      if (p->graphs.size() >= kMaxGraphs) {
+        StepGraph& old = p->graphs.back();
+        (void)hipGraphExecDestroy(old.exec);
+        (void)hipGraphDestroy(old.graph);
+        p->graphs.pop_back();
+      }
+      StepGraph ng;
+      s = capture_step(p, sigma, fx, fy, &ng);
+      if (s != SG_OK) return s;
+      p->graphs.insert(p->graphs.begin(), ng);
+      g = &p->graphs[0];
+    }
+    const size_t nside = p->side.size();
+    hipEvent_t in = p->sync_ev[nside], out = p->sync_ev[nside + 1];
+    hipError_t e = hipEventRecord(in, p->st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->side[0], in, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(g->exec, p->side[0]);
+    if (e == hipSuccess) e = hipEventRecord(out, p->side[0]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->st, out, 0);
+    if (e != hipSuccess) return hip_check(p, e, "graph launch");
+    if (p->timing) ++p->timed_calls;
+    return SG_OK;
+  }
+  for (const GridClass& c : p->classes) {
+    // one launch per pass for every grid of the class, timing marks around them
     hipError_t e = mark(p);
-    if (e == hipSuccess) e = sg_launch_row_fwd(prec, G.M, src, G.M, G.X, G.N, G.r2m, solve, 0, G.twA, p->st);
+    const GridPlan& G = p->grids[c.members[0]];
+    const int solve = c.k == 3 ? 1 : 0;
+    const int ng = (int)c.members.size();
+    const int tj = sg_row_tile(prec, c.M, c.N);
+    if (e == hipSuccess)
+      e = sg_launch_row_fwd(prec, c.M, sigma, c.M, nullptr, c.N, G.r2m, solve, 0, G.twA, c.desc, ng, c.tile[0], p->st);
     if (e == hipSuccess) e = mark(p);
     if (e == hipSuccess)
-      e = sg_launch_col(prec, G.N, G.X, G.V, G.M, sg_row_tile(prec, G.M, G.N), G.tabx, G.taby, G.kind, G.r2n, solve,
-                        G.twB, p->st);
+      e = sg_launch_col(prec, c.N, nullptr, nullptr, c.M, tj, nullptr, nullptr, G.kind, G.r2n, solve, G.twB, c.desc, ng,
+                        c.tile[1], p->st);
     if (e == hipSuccess) e = mark(p);
     if (e == hipSuccess)
-      e = sg_launch_row_inv(prec, G.M, G.V, ox, oy, G.N, sg_row_tile(prec, G.M, G.N), G.r2m, G.twC, p->st);
+      e = sg_launch_row_inv(prec, c.M, nullptr, fx, fy, c.N, tj, G.r2m, G.twC, c.desc, ng, c.tile[2], p->st);
     if (e == hipSuccess) e = mark(p);
     if (e != hipSuccess) return hip_check(p, e, "force launch");
   }
   if (p->timing) ++p->timed_calls;
+  return SG_OK;
+}
+
+sg_status sg_plan_classes(sg_plan p, int32_t* nclasses, int32_t* info, int32_t cap) {
+  g_msg.clear();
+  if (!p) return fail(SG_ERR_ARG, "plan is NULL");
+  if (nclasses) *nclasses = (int32_t)p->classes.size();
+  if (info) {
+    const int prec = p->prec == SG_FP64 ? 0 : 1;
+    for (int32_t i = 0; i < cap && i < (int32_t)p->classes.size(); ++i) {
+      const GridClass& c = p->classes[i];
+      int32_t* o = info + 8 * i;
+      o[0] = c.M;
+      o[1] = c.N;
+      o[2] = c.k;
+      o[3] = (int32_t)c.members.size();
+      for (int pass = 0; pass < 3; ++pass) {
+        // the tile the launch uses: rows capped by the row count; columns the
+        // largest power of two that divides nx
+        int t = c.tile[pass] > 0 ? c.tile[pass] : sg_max_tile(prec, pass, pass == 1 ? c.N : c.M);
+        if (pass == 1) {
+          int d = 1;
+          while (d < t && c.M % (2 * d) == 0) d *= 2;
+          t = d;
+        } else if (t > c.N) {
+          t = c.N;
+        }
+        o[4 + pass] = t;
+      }
+      o[7] = 0;
+    }
+  }
   return SG_OK;
 }
 
@@ -504,8 +815,8 @@ sg_status sg_forces_adjoint(sg_plan p, const void* gfx, const void* gfy, void* g
     // workspace: row spectra of gx in X, of gy in the first half of V, gC spectra in its second half
     void* Xy = G.V;
     void* Y = (char*)G.V + cb * (size_t)G.M * G.N;
-    hipError_t e = sg_launch_row_fwd(prec, G.M, gx, G.M, G.X, G.N, G.r2m, 0, 0, G.twA, p->st);
-    if (e == hipSuccess) e = sg_launch_row_fwd(prec, G.M, gy, G.M, Xy, G.N, G.r2m, 0, 0, G.twA, p->st);
+    hipError_t e = sg_launch_row_fwd(prec, G.M, gx, G.M, G.X, G.N, G.r2m, 0, 0, G.twA, nullptr, 1, 0, p->st);
+    if (e == hipSuccess) e = sg_launch_row_fwd(prec, G.M, gy, G.M, Xy, G.N, G.r2m, 0, 0, G.twA, nullptr, 1, 0, p->st);
     if (e == hipSuccess)
       e = sg_launch_adjoint_tail(prec, G.M, G.N, G.X, Xy, Y, out, sg_row_tile(prec, G.M, G.N), G.tabx, G.taby, G.kind,
                                  G.r2m, G.r2n, solve, G.twB, G.twA, p->st);

@@ -3,20 +3,40 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// One grid of a batched launch (device memory, read by the per-step
+// kernels): element offset of the grid in the packed sigma / force buffers,
+// its workspace and its spectrum tables.
+struct sg_bgrid {
+  int64_t off;
+  void* X;
+  void* V;
+  const void* tabx;
+  const void* taby;
+};
+
 // precision code: 0 = FP64, 1 = FP32 (complex arrays are interleaved pairs)
+// Per-step launches take an optional batch: bg = NULL runs one grid from the
+// pointer arguments; otherwise ngrids grids of the same sizes and order from
+// bg (blockIdx.y = grid), with the buffer arguments as bases of the packed
+// buffers.  tile: rows (passes A, C) or columns (pass B) per workgroup,
+// 0 = the compiled maximum.
 hipError_t sg_set_gl_tables(const double* x /*4x16*/, const double* w /*4x16*/);
 hipError_t sg_launch_weights(int k, double hx, double hy, int M, int N, double* wx, double* wy, int layout,
                              hipStream_t st);
 // tw: stage twiddle tables of the pass (sg_twiddles)
 hipError_t sg_launch_row_fwd(int prec, int M, const void* src, int64_t ld, void* X, int nrows, const void* r2m,
-                             int solve, int full, const void* tw, hipStream_t st);
+                             int solve, int full, const void* tw, const sg_bgrid* bg, int ngrids, int tile,
+                             hipStream_t st);
+// largest tile (rows or columns per workgroup) of a pass: 0 = A, 1 = B, 2 = C
+int sg_max_tile(int prec, int pass, int len);
 // X: column-major row spectra (bin p of row j at X[p*N + j]); V: tiles of
 // tj rows (sg_row_tile), the layout the inverse row pass reads
 hipError_t sg_launch_col(int prec, int N, const void* X, void* V, int M, int tj, const void* tx, const void* ty,
-                         int kind, const void* r2n, int solve, const void* tw, hipStream_t st);
+                         int kind, const void* r2n, int solve, const void* tw, const sg_bgrid* bg, int ngrids,
+                         int tile, hipStream_t st);
 int sg_row_tile(int prec, int M, int N);
 hipError_t sg_launch_row_inv(int prec, int M, const void* V, void* fx, void* fy, int nrows, int tj, const void* r2m,
-                             const void* tw, hipStream_t st);
+                             const void* tw, const sg_bgrid* bg, int ngrids, int tile, hipStream_t st);
 hipError_t sg_launch_spec_col(int N, const void* S, int M, void* tab, int kind, int fp32, double scale,
                               const void* r2n, const void* tw, hipStream_t st);
 // Stage twiddle tables of a pass's FFT (pass 0: forward rows, 1: columns,

@@ -271,7 +271,13 @@ template <typename R, typename In, int M>
 __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M>::T))
     SG_WPE(R, RF)
     k_row_fwd(const In* __restrict__ src, int64_t src_ld, cx<R>* __restrict__ X, int ldx, int nrows,
-              const cx<R>* __restrict__ r2m, int solve, int full, const cx<R>* __restrict__ tw) {
+              const cx<R>* __restrict__ r2m, int solve, int full, const cx<R>* __restrict__ tw,
+              const sg_bgrid* __restrict__ bg) {
+  if (bg) {  // batched: grid blockIdx.y of the class
+    const sg_bgrid d = bg[blockIdx.y];
+    src += d.off;
+    X = reinterpret_cast<cx<R>*>(d.X);
+  }
   using C = rowfwd_cfg<R, In, M>;
   constexpr int L = C::L, E = C::E, T = C::T, SLOT = C::SLOT, EC = C::EC;
   __shared__ cx<R> smem[C::G * SLOT];
@@ -465,9 +471,21 @@ template <typename R, typename TO, typename TC, int N, int MODE>
 __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     SG_WPE(R, COL) k_col(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
           const TO* __restrict__ toy, const TC* __restrict__ tcx, const TC* __restrict__ tcy,
-          const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ tw) {
+          const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ tw, const sg_bgrid* __restrict__ bg) {
   constexpr int kind = MODE == 1 ? 1 : 0;
   constexpr bool solve = MODE == 2;
+  if (bg) {  // batched: grid blockIdx.y of the class
+    const sg_bgrid d = bg[blockIdx.y];
+    X = reinterpret_cast<const cx<R>*>(d.X);
+    V = reinterpret_cast<cx<R>*>(d.V);
+    if (kind == 0) {
+      tox = reinterpret_cast<const TO*>(d.tabx);
+      toy = reinterpret_cast<const TO*>(d.taby);
+    } else {
+      tcx = reinterpret_cast<const TC*>(d.tabx);
+      tcy = reinterpret_cast<const TC*>(d.taby);
+    }
+  }
   using C = col_cfg<R, N>;
   constexpr int E = C::E, T = C::T, LL = C::SLOT, NBUF = C::NBUF;
   __shared__ cx<R> smem[C::P * LL * NBUF];
@@ -607,7 +625,13 @@ template <typename R, typename Out, int M>
 __global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
     SG_WPE(R, RI)
     k_row_inv(const cx<R>* __restrict__ V, Out* __restrict__ fx, Out* __restrict__ fy, int nrows, int tj,
-              const cx<R>* __restrict__ r2m, const cx<R>* __restrict__ tw) {
+              const cx<R>* __restrict__ r2m, const cx<R>* __restrict__ tw, const sg_bgrid* __restrict__ bg) {
+  if (bg) {  // batched: grid blockIdx.y of the class
+    const sg_bgrid d = bg[blockIdx.y];
+    V = reinterpret_cast<const cx<R>*>(d.V);
+    fx += d.off;
+    fy += d.off;
+  }
   using C = rowinv_cfg<R, M>;
   constexpr int E = C::E, T = C::T, LL = C::LL;
   __shared__ cx<R> smem[C::G * LL];
@@ -1016,47 +1040,58 @@ struct tabs {
       X(768) X(1536)
 #endif
 
+// rows (or columns) per workgroup: the requested tile if it is in [1, cap],
+// else cap, and never more than n
+static inline int pick_tile(int tile, int cap, int n) {
+  int g = (tile > 0 && tile <= cap) ? tile : cap;
+  return g < n ? g : n;
+}
+
 template <typename R, typename In, int M>
 static hipError_t launch_row_fwd_t(const In* src, int64_t src_ld, cx<R>* X, int nrows, const cx<R>* r2m,
-                                   int solve, int full, const cx<R>* tw, hipStream_t st) {
+                                   int solve, int full, const cx<R>* tw, const sg_bgrid* bg, int ngrids, int tile,
+                                   hipStream_t st) {
   using C = rowfwd_cfg<R, In, M>;
-  const int G = C::G < nrows ? C::G : nrows;
+  const int G = pick_tile(tile, C::G, nrows);
   const int blocks = (nrows + G - 1) / G;
-  hipLaunchKernelGGL((k_row_fwd<R, In, M>), dim3(blocks), dim3(G * C::T), 0, st, src, src_ld, X, nrows, nrows,
-                     r2m, solve, full, tw);
+  hipLaunchKernelGGL((k_row_fwd<R, In, M>), dim3(blocks, bg ? ngrids : 1), dim3(G * C::T), 0, st, src, src_ld, X,
+                     nrows, nrows, r2m, solve, full, tw, bg);
   return hipGetLastError();
 }
 
 template <typename R, int N>
 static hipError_t launch_col_t(const cx<R>* X, cx<R>* V, int M, int tj, const void* tx, const void* ty, int kind,
-                               const cx<R>* r2n, int solve, const cx<R>* tw, hipStream_t st) {
+                               const cx<R>* r2n, int solve, const cx<R>* tw, const sg_bgrid* bg, int ngrids,
+                               int tile, hipStream_t st) {
   using C = col_cfg<R, N>;
   using TO = typename tabs<R>::odd;
   using TC = typename tabs<R>::cplx;
-  const int P = pow2_div(M, C::P);
+  const int P = pow2_div(M, (tile > 0 && tile <= C::P) ? tile : C::P);
+  const dim3 grid(M / P, bg ? ngrids : 1);
   const TO* tox = kind == 0 ? (const TO*)tx : nullptr;
   const TO* toy = kind == 0 ? (const TO*)ty : nullptr;
   const TC* tcx = kind == 1 ? (const TC*)tx : nullptr;
   const TC* tcy = kind == 1 ? (const TC*)ty : nullptr;
   if (kind == 1)
-    hipLaunchKernelGGL((k_col<R, TO, TC, N, 1>), dim3(M / P), dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy,
-                       r2n, tw);
+    hipLaunchKernelGGL((k_col<R, TO, TC, N, 1>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy, r2n,
+                       tw, bg);
   else if (solve)
-    hipLaunchKernelGGL((k_col<R, TO, TC, N, 2>), dim3(M / P), dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy,
-                       r2n, tw);
+    hipLaunchKernelGGL((k_col<R, TO, TC, N, 2>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy, r2n,
+                       tw, bg);
   else
-    hipLaunchKernelGGL((k_col<R, TO, TC, N, 0>), dim3(M / P), dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy,
-                       r2n, tw);
+    hipLaunchKernelGGL((k_col<R, TO, TC, N, 0>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy, r2n,
+                       tw, bg);
   return hipGetLastError();
 }
 
 template <typename R, typename Out, int M>
 static hipError_t launch_row_inv_t(const cx<R>* V, Out* fx, Out* fy, int nrows, int tj, const cx<R>* r2m,
-                                   const cx<R>* tw, hipStream_t st) {
+                                   const cx<R>* tw, const sg_bgrid* bg, int ngrids, int tile, hipStream_t st) {
   using C = rowinv_cfg<R, M>;
-  const int G = C::G < nrows ? C::G : nrows;
+  const int G = pick_tile(tile, C::G, nrows);
   const int blocks = (nrows + G - 1) / G;
-  hipLaunchKernelGGL((k_row_inv<R, Out, M>), dim3(blocks), dim3(G * C::T), 0, st, V, fx, fy, nrows, tj, r2m, tw);
+  hipLaunchKernelGGL((k_row_inv<R, Out, M>), dim3(blocks, bg ? ngrids : 1), dim3(G * C::T), 0, st, V, fx, fy, nrows,
+                     tj, r2m, tw, bg);
   return hipGetLastError();
 }
 
@@ -1094,11 +1129,12 @@ hipError_t sg_set_gl_tables(const double* x, const double* w) {
 #if SG_IN_PART(1)
 template <typename R, typename In>
 static hipError_t row_fwd_dispatch(int M, const In* src, int64_t ld, cx<R>* X, int nrows, const cx<R>* r2m,
-                                   int solve, int full, const cx<R>* tw, hipStream_t st) {
+                                   int solve, int full, const cx<R>* tw, const sg_bgrid* bg, int ngrids, int tile,
+                                   hipStream_t st) {
   switch (M) {
 #define CASE(SZ) \
   case SZ:       \
-    return launch_row_fwd_t<R, In, SZ>(src, ld, X, nrows, r2m, solve, full, tw, st);
+    return launch_row_fwd_t<R, In, SZ>(src, ld, X, nrows, r2m, solve, full, tw, bg, ngrids, tile, st);
     SG_SIZES(CASE)
 #undef CASE
     default:
@@ -1111,11 +1147,12 @@ static hipError_t row_fwd_dispatch(int M, const In* src, int64_t ld, cx<R>* X, i
 #if SG_IN_PART(2)
 template <typename R>
 static hipError_t col_dispatch(int N, const cx<R>* X, cx<R>* V, int M, int tj, const void* tx, const void* ty,
-                               int kind, const cx<R>* r2n, int solve, const cx<R>* tw, hipStream_t st) {
+                               int kind, const cx<R>* r2n, int solve, const cx<R>* tw, const sg_bgrid* bg,
+                               int ngrids, int tile, hipStream_t st) {
   switch (N) {
 #define CASE(SZ) \
   case SZ:       \
-    return launch_col_t<R, SZ>(X, V, M, tj, tx, ty, kind, r2n, solve, tw, st);
+    return launch_col_t<R, SZ>(X, V, M, tj, tx, ty, kind, r2n, solve, tw, bg, ngrids, tile, st);
     SG_SIZES(CASE)
 #undef CASE
     default:
@@ -1128,11 +1165,11 @@ static hipError_t col_dispatch(int N, const cx<R>* X, cx<R>* V, int M, int tj, c
 #if SG_IN_PART(1)
 template <typename R, typename Out>
 static hipError_t row_inv_dispatch(int M, const cx<R>* V, Out* fx, Out* fy, int nrows, int tj, const cx<R>* r2m,
-                                   const cx<R>* tw, hipStream_t st) {
+                                   const cx<R>* tw, const sg_bgrid* bg, int ngrids, int tile, hipStream_t st) {
   switch (M) {
 #define CASE(SZ) \
   case SZ:       \
-    return launch_row_inv_t<R, Out, SZ>(V, fx, fy, nrows, tj, r2m, tw, st);
+    return launch_row_inv_t<R, Out, SZ>(V, fx, fy, nrows, tj, r2m, tw, bg, ngrids, tile, st);
     SG_SIZES(CASE)
 #undef CASE
     default:
@@ -1144,24 +1181,27 @@ static hipError_t row_inv_dispatch(int M, const cx<R>* V, Out* fx, Out* fy, int 
 
 #if SG_IN_PART(1)
 hipError_t sg_launch_row_fwd(int prec, int M, const void* src, int64_t ld, void* X, int nrows, const void* r2m,
-                             int solve, int full, const void* tw, hipStream_t st) {
+                             int solve, int full, const void* tw, const sg_bgrid* bg, int ngrids, int tile,
+                             hipStream_t st) {
   if (prec == 0)
     return row_fwd_dispatch<double, double>(M, (const double*)src, ld, (cx<double>*)X, nrows,
-                                            (const cx<double>*)r2m, solve, full, (const cx<double>*)tw, st);
+                                            (const cx<double>*)r2m, solve, full, (const cx<double>*)tw, bg, ngrids,
+                                            tile, st);
   return row_fwd_dispatch<float, float>(M, (const float*)src, ld, (cx<float>*)X, nrows, (const cx<float>*)r2m,
-                                        solve, full, (const cx<float>*)tw, st);
+                                        solve, full, (const cx<float>*)tw, bg, ngrids, tile, st);
 }
 
 #endif
 
 #if SG_IN_PART(2)
 hipError_t sg_launch_col(int prec, int N, const void* X, void* V, int M, int tj, const void* tx, const void* ty,
-                         int kind, const void* r2n, int solve, const void* tw, hipStream_t st) {
+                         int kind, const void* r2n, int solve, const void* tw, const sg_bgrid* bg, int ngrids,
+                         int tile, hipStream_t st) {
   if (prec == 0)
     return col_dispatch<double>(N, (const cx<double>*)X, (cx<double>*)V, M, tj, tx, ty, kind,
-                                (const cx<double>*)r2n, solve, (const cx<double>*)tw, st);
+                                (const cx<double>*)r2n, solve, (const cx<double>*)tw, bg, ngrids, tile, st);
   return col_dispatch<float>(N, (const cx<float>*)X, (cx<float>*)V, M, tj, tx, ty, kind, (const cx<float>*)r2n,
-                             solve, (const cx<float>*)tw, st);
+                             solve, (const cx<float>*)tw, bg, ngrids, tile, st);
 }
 
 int sg_row_tile(int prec, int M, int N) {
@@ -1174,13 +1214,32 @@ int sg_row_tile(int prec, int M, int N) {
 
 #if SG_IN_PART(1)
 hipError_t sg_launch_row_inv(int prec, int M, const void* V, void* fx, void* fy, int nrows, int tj, const void* r2m,
-                             const void* tw, hipStream_t st) {
+                             const void* tw, const sg_bgrid* bg, int ngrids, int tile, hipStream_t st) {
   if (prec == 0)
     return row_inv_dispatch<double, double>(M, (const cx<double>*)V, (double*)fx, (double*)fy, nrows, tj,
-                                            (const cx<double>*)r2m, (const cx<double>*)tw, st);
+                                            (const cx<double>*)r2m, (const cx<double>*)tw, bg, ngrids, tile, st);
   return row_inv_dispatch<float, float>(M, (const cx<float>*)V, (float*)fx, (float*)fy, nrows, tj,
-                                        (const cx<float>*)r2m, (const cx<float>*)tw, st);
+                                        (const cx<float>*)r2m, (const cx<float>*)tw, bg, ngrids, tile, st);
 }
+
+// Largest tile of a pass (0 = A rows, 1 = B columns, 2 = C rows) for a
+// transform length (M for A and C, N for B); 0 for an unsupported length.
+template <typename R>
+static int max_tile_t(int pass, int len) {
+  switch (len) {
+#define CASE(SZ)                                         \
+  case SZ:                                               \
+    if (pass == 0) return rowfwd_cfg<R, R, SZ>::G;       \
+    if (pass == 1) return col_cfg<R, SZ>::P;             \
+    return rowinv_cfg<R, SZ>::G;
+    SG_SIZES(CASE)
+#undef CASE
+    default:
+      return 0;
+  }
+}
+
+int sg_max_tile(int prec, int pass, int len) { return prec == 0 ? max_tile_t<double>(pass, len) : max_tile_t<float>(pass, len); }
 
 #endif
 
