@@ -171,6 +171,69 @@ def measured_traffic(kname, n):
     return None
 
 
+def batch_bench(sg, torch, steps, warmup, count=256):
+    """Batched disks: ``count`` seeded square grids of mixed sizes (2^a and
+    3*2^a, 96..2048) and orders on [-1,1]^2, FP32-split.  Times one step of
+    (a) one plan with SG_FLAG_GRAPH | SG_FLAG_AUTOTUNE, (b) the same plan
+    without graph or tuning, (c) a host loop of single-grid plans, and checks
+    that all three give bit-identical forces."""
+    import workloads
+    disks = workloads.batch_disks(4, count)
+    grids = [(n, n, -1.0, 1.0, -1.0, 1.0, k) for n, k, _ in disks]
+    prec = sg.SG_FP32_SPLIT
+    t0 = time.perf_counter()
+    pg = sg.Plan(grids, prec, flags=sg.SG_FLAG_GRAPH | sg.SG_FLAG_AUTOTUNE)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    sigma = torch.empty(pg.total, dtype=torch.float32, device="cuda")
+    for gi, (n, k, params) in enumerate(disks):
+        xs, ys = pg.sample_points(gi)
+        sigma[pg.offsets[gi]:pg.offsets[gi + 1]] = workloads.clump_sigma_torch(params, xs, ys).ravel().float()
+    cells = pg.total
+
+    def timed(step):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    gx, gy = pg.empty(), pg.empty()
+    ms_graph = timed(lambda: sg.sg_forces(pg.handle, sigma, gx, gy))
+    classes = sg.sg_plan_classes(pg.handle)
+    pb = sg.Plan(grids, prec)
+    bx, by = pb.empty(), pb.empty()
+    ms_batch = timed(lambda: sg.sg_forces(pb.handle, sigma, bx, by))
+    singles = [sg.Plan([g], prec) for g in grids]
+    lx, ly = pg.empty(), pg.empty()
+    views = [(sigma[pg.offsets[i]:pg.offsets[i + 1]], lx[pg.offsets[i]:pg.offsets[i + 1]],
+              ly[pg.offsets[i]:pg.offsets[i + 1]]) for i in range(len(grids))]
+
+    def loop():
+        for p, (s_, x_, y_) in zip(singles, views):
+            sg.sg_forces(p.handle, s_, x_, y_)
+
+    ms_loop = timed(loop)
+    same = bool(torch.equal(gx, bx) and torch.equal(gy, by) and torch.equal(gx, lx) and torch.equal(gy, ly))
+    for p in singles:
+        p.close()
+    pb.close()
+    pg.close()
+    return {"workload": f"{count} disks on [-1,1]^2, n ~ U{{96,128,192,256,384,512,768,1024,1536,2048}}, "
+                        "k ~ U{1,2,3}, 4-64 seeded clumps each (seed 4), FP32-split",
+            "cells": cells, "classes": len(classes), "steps": steps,
+            "value": cells / (ms_graph * 1e-3), "unit": "cells/s", "ms_per_step": round(ms_graph, 4),
+            "batched_no_graph": {"value": cells / (ms_batch * 1e-3), "ms_per_step": round(ms_batch, 4)},
+            "loop_of_single_plans": {"value": cells / (ms_loop * 1e-3), "ms_per_step": round(ms_loop, 4)},
+            "speedup_vs_loop": round(ms_loop / ms_graph, 3), "plan_s": round(plan_s, 3),
+            "bit_identical": same}
+
+
 def cpu_baseline(n, k, sigma_np, sample):
     """The oracle (direct O(N^4) FP64 sum, OpenMP) on a bounded sample of cells."""
     import numpy as np
@@ -216,6 +279,8 @@ def main():
     ap.add_argument("--k", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-disks measurement")
+    ap.add_argument("--batch-only", action="store_true", help="only the batched-disks measurement")
     ap.add_argument("--prec", choices=["both", "fp32", "fp64"], default="both",
                     help="both (default, the metric) or one path only (profiling)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -261,6 +326,9 @@ def main():
 
     if args.copy_calibration_mib:
         calibration_copy(torch, args.copy_calibration_mib)
+    if args.batch_only:
+        print(json.dumps(batch_bench(sg, torch, max(args.steps // 2, 3), 2)), flush=True)
+        return
     if args.prec != "both":
         prec = sg.SG_FP32_SPLIT if args.prec == "fp32" else sg.SG_FP64
         ms, passes, plan_s, _ = time_plan(sg, torch, grid, prec, sigma, args.steps, args.warmup)
@@ -306,6 +374,8 @@ def main():
         "speedup_fp32split_vs_fp64": round(ms64 / ms32, 3),
         "roofline": roofline,
     }
+    if not args.no_batch:
+        line["batch"] = batch_bench(sg, torch, max(args.steps // 2, 3), 2)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(n, k, sigma, args.cpu_sample)
     print(json.dumps(line), flush=True)

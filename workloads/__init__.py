@@ -14,7 +14,11 @@ Workloads (all synthetic; the paper uses no dataset):
   (r = 0.85 sqrt(u), theta = 2 pi v), drawn from numpy's PCG64
   ``default_rng(seed)`` in the order a, s, u, v;
 * sparse coefficient sets (a few seeded impulses) whose forces an exact
-  superposition can check at any grid size.
+  superposition can check at any grid size;
+* batches of disks of mixed sizes and orders: n ~ U{96, 128, 192, 256, 384,
+  512, 768, 1024, 1536, 2048}, k ~ U{1, 2, 3}, clump count ~ U{4..64}, all
+  from ``default_rng(seed)`` in that order, each disk's clumps from the
+  children of ``SeedSequence(seed)``.
 """
 from __future__ import annotations
 
@@ -82,3 +86,31 @@ def sample_cells(seed, M: int, N: int, count: int, extra=()):
     cells = rng.integers(0, M * N, count).astype(np.int64)
     border = [0, M - 1, (N - 1) * M, N * M - 1]
     return np.unique(np.concatenate([cells, np.asarray(border + list(extra), np.int64)]))
+
+
+BATCH_SIZES = (96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048)
+
+
+def batch_disks(seed=4, count=256):
+    """[(n, k, clump parameters), ...] for a seeded batch of square disks on [-1,1]^2."""
+    rng = np.random.default_rng(seed)
+    n = rng.choice(np.array(BATCH_SIZES), count)
+    k = rng.integers(1, 4, count)
+    nc = rng.integers(4, 65, count)
+    children = np.random.SeedSequence(seed).spawn(count)
+    return [(int(n[i]), int(k[i]), clump_params(children[i], int(nc[i]))) for i in range(count)]
+
+
+def clump_sigma_torch(params, xs, ys, device="cuda"):
+    """clump_sigma evaluated with torch on a device (float64)."""
+    import torch
+    a, s, cx, cy = (torch.as_tensor(np.asarray(v, np.float64), device=device) for v in params)
+    x = torch.as_tensor(np.asarray(xs, np.float64), device=device)
+    y = torch.as_tensor(np.asarray(ys, np.float64), device=device)
+    gx = torch.exp(-(x[None, :] - cx[:, None]) ** 2 / (2.0 * s[:, None] ** 2))     # [c][nx]
+    gy = torch.exp(-(y[None, :] - cy[:, None]) ** 2 / (2.0 * s[:, None] ** 2))     # [c][ny]
+    out = (gy * a[:, None]).transpose(0, 1).contiguous() @ gx.contiguous()           # [ny][nx]
+    X, Y = x[None, :], y[:, None]
+    rr = torch.sqrt(X * X + Y * Y) / 0.95
+    taper = torch.where(rr < 1.0, torch.clamp(1.0 - rr * rr, min=0.0) ** 4, torch.zeros_like(rr))
+    return out * taper
