@@ -340,6 +340,72 @@ __device__ __forceinline__ void fft2(cx<R>* v0, cx<R>* v1, cx<R>* lds0, cx<R>* l
   fft2_stages<INV, L, T, 0>(v0, v1, lds0, lds1, tw, t);
 }
 
+// NA independent transforms of the same length through the same stages,
+// sharing each exchange's barriers: v[i] in registers, exchange buffer i at
+// lds + i * stride.
+template <bool INV, int L, int T, int r, int Ns, int NA, typename R>
+__device__ __forceinline__ void stockham_stage_n(cx<R> (&v)[NA][L / T], cx<R>* lds, int stride,
+                                                 const cx<R>* __restrict__ tw, int t) {
+  constexpr int E = L / T;
+  constexpr int NB = E / r;
+  constexpr bool last = (Ns * r == L);
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int b = t + u * T;
+    cx<R> w[r];
+    if constexpr (Ns > 1) {
+      const unsigned k = (unsigned)b % (unsigned)Ns;
+#pragma unroll
+      for (int q = 1; q < r; ++q) w[q] = tw[(unsigned)((q - 1) * Ns) + k];
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      cx<R> a[r];
+#pragma unroll
+      for (int q = 0; q < r; ++q) a[q] = v[i][u + q * NB];
+      if constexpr (Ns > 1) {
+#pragma unroll
+        for (int q = 1; q < r; ++q) a[q] = INV ? cmulc(a[q], w[q]) : cmul(a[q], w[q]);
+      }
+      dft<r, INV>(a);
+      if constexpr (last) {
+#pragma unroll
+        for (int q = 0; q < r; ++q) v[i][u + q * NB] = a[q];
+      } else {
+        const int base = (b / Ns) * Ns * r + b % Ns;
+#pragma unroll
+        for (int q = 0; q < r; ++q) lds[i * stride + pad(base + q * Ns)] = a[q];
+      }
+    }
+  }
+  if constexpr (!last) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[i][e] = lds[i * stride + pad(t + e * T)];
+    __syncthreads();
+  }
+}
+
+template <bool INV, int L, int T, int S, int NA, typename R>
+__device__ __forceinline__ void fftn_stages(cx<R> (&v)[NA][L / T], cx<R>* lds, int stride,
+                                            const cx<R>* __restrict__ tw, int t) {
+  using P = plan<L, L / T>;
+  if constexpr (S < P::nstages) {
+    stockham_stage_n<INV, L, T, P::radix(S), P::ns_before(S), NA>(v, lds, stride, tw + P::tw_offset(S), t);
+    fftn_stages<INV, L, T, S + 1, NA>(v, lds, stride, tw, t);
+  }
+}
+
+// fft() on NA arrays at once (the barriers of one transform).
+template <bool INV, int L, int T, int NA, typename R>
+__device__ __forceinline__ void fftn(cx<R> (&v)[NA][L / T], cx<R>* lds, int stride, const cx<R>* __restrict__ tw,
+                                     int t) {
+  static_assert(L % T == 0, "L must be a multiple of T");
+  fftn_stages<INV, L, T, 0, NA>(v, lds, stride, tw, t);
+}
+
 // Fill the stage tables of plan<L, E> from a table of roots of unity
 // (roots(i) = exp(-2 pi i * i / L)); one thread per entry.
 template <int L, int E, typename R>

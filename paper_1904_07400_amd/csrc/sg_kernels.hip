@@ -52,7 +52,7 @@
 #define SG_RF_E32 16
 #endif
 #ifndef SG_COL_NBUF32
-#define SG_COL_NBUF32 2
+#define SG_COL_NBUF32 4
 #endif
 // persistent FP32 column pass: workgroups per grid (0 = off) and the
 // smallest column length that uses it
@@ -391,7 +391,8 @@ struct col_cfg {
   static constexpr int LL = lds_len<N>::value;
   static constexpr int TRI = (int)(sizeof(tri_smem<double2, T>) / sizeof(cx<R>)) + 1;
   static constexpr int SLOT = LL > TRI ? LL : TRI;  // per-column LDS slot (complex elements)
-  // exchange buffers per column: 2 lets two transforms share their barriers
+  // exchange buffers per column: 2 or 4 let as many transforms share their
+  // barriers
   static constexpr int NBUF = sizeof(R) == 4 ? SG_COL_NBUF32 : 1;
   static constexpr int BYTES = NBUF * SLOT * (int)sizeof(cx<R>);
   static constexpr int P0 = T >= 256 ? 1 : 256 / T;
@@ -543,7 +544,36 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     fe[e] = a[e];
   }
   cx<R> accx[E], accy[E];
-  if constexpr (NBUF == 2) {
+  if constexpr (NBUF == 4) {
+    // both forward transforms together, then all four products (x and y of
+    // each half) and their inverses together
+    {
+      cx<R> f2[2][E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        f2[0][e] = fe[e];
+        f2[1][e] = fo[e];
+      }
+      fftn<false, N, T, 2>(f2, lds, LL, tw, t);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        fe[e] = f2[0][e];
+        fo[e] = f2[1][e];
+      }
+    }
+    cx<R> g4[4][E];
+    col_product<R, TO, TC, N, E, T>(fe, g4[0], 0, c0 == 0, packed, lds, kind, tox, tcx, (R)1, c, M, t);
+    col_product<R, TO, TC, N, E, T>(fe, g4[1], 0, c0 == 0, packed, lds, kind, toy, tcy, (R)-1, c, M, t);
+    col_product<R, TO, TC, N, E, T>(fo, g4[2], 1, c0 == 0, packed, lds, kind, tox, tcx, (R)1, c, M, t);
+    col_product<R, TO, TC, N, E, T>(fo, g4[3], 1, c0 == 0, packed, lds, kind, toy, tcy, (R)-1, c, M, t);
+    fftn<true, N, T, 4>(g4, lds, LL, tw, t);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const cx<R> w = r2n[(unsigned)(t + e * T)];  // conj -> exp(+i pi j / N)
+      accx[e] = g4[0][e] + cmulc(g4[2][e], w);
+      accy[e] = g4[1][e] + cmulc(g4[3][e], w);
+    }
+  } else if constexpr (NBUF == 2) {
     // both forward transforms, then per half both components' inverses,
     // two at a time through the two exchange buffers
     fft2<false, N, T>(fe, fo, lds, lds2, tw, t);
