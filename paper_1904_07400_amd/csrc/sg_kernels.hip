@@ -54,6 +54,14 @@
 #ifndef SG_COL_NBUF32
 #define SG_COL_NBUF32 4
 #endif
+// exchange buffers per row of the FP32 row passes (2: both half-length
+// transforms share their barriers)
+#ifndef SG_RF_NBUF32
+#define SG_RF_NBUF32 2
+#endif
+#ifndef SG_RI_NBUF32
+#define SG_RI_NBUF32 2
+#endif
 // persistent FP32 column pass: workgroups per grid (0 = off) and the
 // smallest column length that uses it
 #ifndef SG_COL_PIPE
@@ -276,8 +284,9 @@ struct rowfwd_cfg {
   // for the reduced system of the x-solve
   static constexpr int TRI = (int)(sizeof(tri_smem<double, T>) / sizeof(cx<R>)) + 1;
   static constexpr int SLOT = LL > TRI ? LL : TRI;
+  static constexpr int NB = (sizeof(R) == 4 && sizeof(In) == 4) ? SG_RF_NBUF32 : 1;  // exchange buffers per row
   static constexpr int G0 = SG_RF_THREADS / T < 1 ? 1 : (SG_RF_THREADS / T < 16 ? SG_RF_THREADS / T : 16);
-  static constexpr int GL = kLdsBudget / (SLOT * (int)sizeof(cx<R>));
+  static constexpr int GL = kLdsBudget / (NB * SLOT * (int)sizeof(cx<R>));
   static constexpr int G = (G0 < GL ? G0 : GL) < 1 ? 1 : (G0 < GL ? G0 : GL);
   // e-values per transposed-store chunk (2T bins per e, G rows)
   static constexpr int EC = (SLOT / (2 * T)) < 1 ? 1 : ((SLOT / (2 * T)) > E ? E : SLOT / (2 * T));
@@ -295,13 +304,14 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
     X = reinterpret_cast<cx<R>*>(d.X);
   }
   using C = rowfwd_cfg<R, In, M>;
-  constexpr int L = C::L, E = C::E, T = C::T, SLOT = C::SLOT, EC = C::EC;
-  __shared__ cx<R> smem[C::G * SLOT];
+  constexpr int L = C::L, E = C::E, T = C::T, SLOT = C::SLOT, EC = C::EC, NB = C::NB;
+  __shared__ cx<R> smem[C::G * SLOT * NB];
   const int G = blockDim.x / T;  // rows per workgroup (<= C::G)
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int row0 = xcd_tile(blockIdx.x, gridDim.x) * G, row = row0 + g;
   const bool active = row < nrows;
-  cx<R>* lds = smem + g * SLOT;
+  cx<R>* lds = smem + g * SLOT * NB;
+  cx<R>* lds2 = lds + (NB - 1) * SLOT;
   const In* s = src + (int64_t)(active ? row : 0) * src_ld;
   cx<R> ze[E], zo[E];
   if (solve) {
@@ -335,12 +345,30 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
     }
     zo[e] = cmul(lo, r2m[2 * n]);  // w_M^n
   }
-  // even bins of Z
-  fft<false, L, T>(ze, lds, tw, t);
   cx<R> xe[E];
+  if constexpr (NB == 2) {
+    // even and odd bins of Z through the same stages
+    cx<R> z2[2][E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = ze[e];
-  __syncthreads();
+    for (int e = 0; e < E; ++e) {
+      z2[0][e] = ze[e];
+      z2[1][e] = zo[e];
+    }
+    fftn<false, L, T, 2>(z2, lds, SLOT, tw, t);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      ze[e] = z2[0][e];
+      zo[e] = z2[1][e];
+      lds[pad(t + e * T)] = ze[e];
+      lds2[pad(t + e * T)] = zo[e];
+    }
+    __syncthreads();
+  } else {
+    fft<false, L, T>(ze, lds, tw, t);  // even bins of Z
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = ze[e];
+    __syncthreads();
+  }
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int pp = t + e * T;                         // X bin p = 2 pp
@@ -349,16 +377,17 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
     xe[e] = cx<R>{(R)0.5 * (sum.x + dif.y), (R)0.5 * (sum.y - dif.x)};
     if (pp == 0) xe[e] = cx<R>{zp.x + zp.y, zp.x - zp.y};
   }
-  __syncthreads();
-  // odd bins of Z
-  fft<false, L, T>(zo, lds, tw, t);
+  if constexpr (NB != 2) {
+    __syncthreads();
+    fft<false, L, T>(zo, lds, tw, t);  // odd bins of Z
 #pragma unroll
-  for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = zo[e];
-  __syncthreads();
+    for (int e = 0; e < E; ++e) lds2[pad(t + e * T)] = zo[e];
+    __syncthreads();
+  }
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int pp = t + e * T;                         // X bin p = 2 pp + 1
-    const cx<R> zp = zo[e], zm = conj(lds[pad(L - 1 - pp)]);
+    const cx<R> zp = zo[e], zm = conj(lds2[pad(L - 1 - pp)]);
     const cx<R> sum = zp + zm, dif = cmul(r2m[2 * pp + 1], zp - zm);
     zo[e] = cx<R>{(R)0.5 * (sum.x + dif.y), (R)0.5 * (sum.y - dif.x)};
   }
@@ -848,8 +877,9 @@ struct rowinv_cfg {
   static constexpr int E = elems_for(L, sizeof(R) == 4 ? SG_RI_E32 : SG_RI_E64, SG_E3);
   static constexpr int T = L / E;
   static constexpr int LL = lds_len<L>::value;
+  static constexpr int NB = sizeof(R) == 4 ? SG_RI_NBUF32 : 1;  // exchange buffers per row
   static constexpr int G0 = SG_RI_THREADS / T < 1 ? 1 : (SG_RI_THREADS / T < 16 ? SG_RI_THREADS / T : 16);
-  static constexpr int GL = kLdsBudget / (LL * (int)sizeof(cx<R>));
+  static constexpr int GL = kLdsBudget / (NB * LL * (int)sizeof(cx<R>));
   static constexpr int G = (G0 < GL ? G0 : GL) < 1 ? 1 : (G0 < GL ? G0 : GL);
 };
 
@@ -865,22 +895,39 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
     fy += d.off;
   }
   using C = rowinv_cfg<R, M>;
-  constexpr int E = C::E, T = C::T, LL = C::LL;
-  __shared__ cx<R> smem[C::G * LL];
+  constexpr int E = C::E, T = C::T, LL = C::LL, NB = C::NB;
+  __shared__ cx<R> smem[C::G * LL * NB];
   const int G = blockDim.x / T;  // rows per workgroup
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int row = xcd_tile(blockIdx.x, gridDim.x) * G + g;
   const bool active = row < nrows;
-  cx<R>* lds = smem + g * LL;
+  cx<R>* lds = smem + g * LL * NB;
   const int jb = (active ? row : 0) / tj, jj = (active ? row : 0) % tj;
   cx<R> ve[E], vo[E];
+  if constexpr (NB == 2) {
+    // both half-length inverses through the same stages
+    cx<R> v2[2][E];
 #pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    const cx<R>* base = V + ((int64_t)jb * 2 + half) * M * tj + jj;
-    cx<R>* v = half ? vo : ve;
+    for (int half = 0; half < 2; ++half) {
+      const cx<R>* base = V + ((int64_t)jb * 2 + half) * M * tj + jj;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = base[(int64_t)(t + e * T) * tj];
-    fft<true, M, T>(v, lds, tw, t);
+      for (int e = 0; e < E; ++e) v2[half][e] = base[(int64_t)(t + e * T) * tj];
+    }
+    fftn<true, M, T, 2>(v2, lds, LL, tw, t);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      ve[e] = v2[0][e];
+      vo[e] = v2[1][e];
+    }
+  } else {
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const cx<R>* base = V + ((int64_t)jb * 2 + half) * M * tj + jj;
+      cx<R>* v = half ? vo : ve;
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = base[(int64_t)(t + e * T) * tj];
+      fft<true, M, T>(v, lds, tw, t);
+    }
   }
   if (active) {
 #pragma unroll
