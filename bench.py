@@ -220,6 +220,17 @@ def batch_bench(sg, torch, steps, warmup, count=256):
 
     ms_loop = timed(loop)
     same = bool(torch.equal(gx, bx) and torch.equal(gy, by) and torch.equal(gx, lx) and torch.equal(gy, ly))
+    # FP32-split error against the FP64 path, per grid (max|dF| / max|F|), worst grid
+    p64 = sg.Plan(grids, sg.SG_FP64)
+    hx, hy = p64.forces(sigma.double())
+    torch.cuda.synchronize()
+    err = 0.0
+    for i in range(len(grids)):
+        a, b = pg.offsets[i], pg.offsets[i + 1]
+        scale = max(hx[a:b].abs().max().item(), hy[a:b].abs().max().item())
+        dev = max((gx[a:b].double() - hx[a:b]).abs().max().item(), (gy[a:b].double() - hy[a:b]).abs().max().item())
+        err = max(err, dev / scale)
+    p64.close()
     for p in singles:
         p.close()
     pb.close()
@@ -231,7 +242,7 @@ def batch_bench(sg, torch, steps, warmup, count=256):
             "batched_no_graph": {"value": cells / (ms_batch * 1e-3), "ms_per_step": round(ms_batch, 4)},
             "loop_of_single_plans": {"value": cells / (ms_loop * 1e-3), "ms_per_step": round(ms_loop, 4)},
             "speedup_vs_loop": round(ms_loop / ms_graph, 3), "plan_s": round(plan_s, 3),
-            "bit_identical": same}
+            "bit_identical": same, "rel_err_vs_fp64_worst_grid": err}
 
 
 def cpu_baseline(n, k, sigma_np, sample):

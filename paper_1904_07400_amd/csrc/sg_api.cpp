@@ -115,6 +115,7 @@ struct GridClass {
   int M, N, k;
   std::vector<int> members;
   sg_bgrid* desc = nullptr;
+  sg_bgrid* desc_y = nullptr;  // the same with X = V (adjoint: row spectra of gy)
   int tile[3] = {0, 0, 0};  // rows / columns per workgroup of passes A, B, C (0 = compiled maximum)
 };
 
@@ -537,7 +538,7 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
     for (GridClass& x : p->classes)
       if (x.M == G.M && x.N == G.N && x.k == G.k) c = &x;
     if (!c) {
-      p->classes.push_back(GridClass{G.M, G.N, G.k, {}, nullptr, {0, 0, 0}});
+      p->classes.push_back(GridClass{G.M, G.N, G.k, {}, nullptr, nullptr, {0, 0, 0}});
       c = &p->classes.back();
     }
     c->members.push_back(i);
@@ -552,6 +553,11 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
     s = dev_alloc(p, (void**)&c.desc, h.size() * sizeof(sg_bgrid));
     if (s == SG_OK)
       s = hip_check(p, hipMemcpy(c.desc, h.data(), h.size() * sizeof(sg_bgrid), hipMemcpyHostToDevice),
+                    "descriptor upload");
+    for (sg_bgrid& d : h) d.X = d.V;
+    if (s == SG_OK) s = dev_alloc(p, (void**)&c.desc_y, h.size() * sizeof(sg_bgrid));
+    if (s == SG_OK)
+      s = hip_check(p, hipMemcpy(c.desc_y, h.data(), h.size() * sizeof(sg_bgrid), hipMemcpyHostToDevice),
                     "descriptor upload");
   }
   if (s == SG_OK && (flags & SG_FLAG_GRAPH)) {
@@ -806,20 +812,19 @@ sg_status sg_forces_adjoint(sg_plan p, const void* gfx, const void* gfy, void* g
   if (!gfx || !gfy || !gsigma) return fail(SG_ERR_ARG, "gfx, gfy or gsigma is NULL");
   if (gsigma == gfx || gsigma == gfy) return fail(SG_ERR_ARG, "gsigma must not alias gfx or gfy");
   const int prec = p->prec == SG_FP64 ? 0 : 1;
-  const size_t el = prec == 0 ? 8 : 4, cb = 2 * el;
-  for (const GridPlan& G : p->grids) {
-    const char* gx = (const char*)gfx + el * G.off;
-    const char* gy = (const char*)gfy + el * G.off;
-    char* out = (char*)gsigma + el * G.off;
-    const int solve = G.k == 3 ? 1 : 0;
-    // workspace: row spectra of gx in X, of gy in the first half of V, gC spectra in its second half
-    void* Xy = G.V;
-    void* Y = (char*)G.V + cb * (size_t)G.M * G.N;
-    hipError_t e = sg_launch_row_fwd(prec, G.M, gx, G.M, G.X, G.N, G.r2m, 0, 0, G.twA, nullptr, 1, 0, p->st);
-    if (e == hipSuccess) e = sg_launch_row_fwd(prec, G.M, gy, G.M, Xy, G.N, G.r2m, 0, 0, G.twA, nullptr, 1, 0, p->st);
+  // per class, all grids at once: row spectra of gx in X, of gy in the first
+  // half of V (descriptors desc_y), gC spectra in its second half
+  for (const GridClass& c : p->classes) {
+    const GridPlan& G = p->grids[c.members[0]];
+    const int solve = c.k == 3 ? 1 : 0;
+    const int ng = (int)c.members.size();
+    hipError_t e =
+        sg_launch_row_fwd(prec, c.M, gfx, c.M, nullptr, c.N, G.r2m, 0, 0, G.twA, c.desc, ng, c.tile[0], p->st);
     if (e == hipSuccess)
-      e = sg_launch_adjoint_tail(prec, G.M, G.N, G.X, Xy, Y, out, sg_row_tile(prec, G.M, G.N), G.tabx, G.taby, G.kind,
-                                 G.r2m, G.r2n, solve, G.twB, G.twA, p->st);
+      e = sg_launch_row_fwd(prec, c.M, gfy, c.M, nullptr, c.N, G.r2m, 0, 0, G.twA, c.desc_y, ng, c.tile[0], p->st);
+    if (e == hipSuccess)
+      e = sg_launch_adjoint_tail(prec, c.M, c.N, nullptr, nullptr, nullptr, gsigma, sg_row_tile(prec, c.M, c.N),
+                                 nullptr, nullptr, G.kind, G.r2m, G.r2n, solve, G.twB, G.twA, c.desc, ng, p->st);
     if (e != hipSuccess) return hip_check(p, e, "adjoint launch");
   }
   return SG_OK;

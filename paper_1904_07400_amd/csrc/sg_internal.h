@@ -50,6 +50,9 @@ hipError_t sg_launch_coeff_cols(int prec, int N, void* data, int M, hipStream_t 
 // Adjoint after the two forward row transforms of gx, gy (Xx, Xy
 // column-major like X): conjugate-spectrum column pass into Y (tiles of tj
 // rows), then the inverse real row pass with the x-solve into gsigma.
+// Batched (bg != NULL): Xx, Xy, Y and gsigma come from the descriptors (X,
+// the two halves of V, the offset into the packed gsigma base).
 hipError_t sg_launch_adjoint_tail(int prec, int M, int N, const void* Xx, const void* Xy, void* Y, void* gsigma,
                                   int tj, const void* tx, const void* ty, int kind, const void* r2m, const void* r2n,
-                                  int solve, const void* twB, const void* twA, hipStream_t st);
+                                  int solve, const void* twB, const void* twA, const sg_bgrid* bg, int ngrids,
+                                  hipStream_t st);

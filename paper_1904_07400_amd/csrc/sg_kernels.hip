@@ -29,7 +29,7 @@
 #define SG_RI_THREADS 256
 #endif
 #ifndef SG_RI_E32
-#define SG_RI_E32 16
+#define SG_RI_E32 8
 #endif
 #ifndef SG_RI_E64
 #define SG_RI_E64 16
@@ -1003,9 +1003,23 @@ template <typename R, typename TO, typename TC, int N, int MODE>
 __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     k_col_adj(const cx<R>* __restrict__ Xx, const cx<R>* __restrict__ Xy, cx<R>* __restrict__ Y, int M, int tj,
               const TO* __restrict__ tox, const TO* __restrict__ toy, const TC* __restrict__ tcx,
-              const TC* __restrict__ tcy, const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ tw) {
+              const TC* __restrict__ tcy, const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ tw,
+              const sg_bgrid* __restrict__ bg) {
   constexpr int kind = MODE == 1 ? 1 : 0;
   constexpr bool solve = MODE == 2;
+  if (bg) {  // batched: gx spectra in X, gy spectra in the first half of V, output in its second half
+    const sg_bgrid d = bg[blockIdx.y];
+    Xx = reinterpret_cast<const cx<R>*>(d.X);
+    Xy = reinterpret_cast<const cx<R>*>(d.V);
+    Y = reinterpret_cast<cx<R>*>(d.V) + (int64_t)M * N;
+    if (kind == 0) {
+      tox = reinterpret_cast<const TO*>(d.tabx);
+      toy = reinterpret_cast<const TO*>(d.taby);
+    } else {
+      tcx = reinterpret_cast<const TC*>(d.tabx);
+      tcy = reinterpret_cast<const TC*>(d.taby);
+    }
+  }
   using C = col_cfg<R, N>;
   constexpr int E = C::E, T = C::T, LL = C::SLOT;
   __shared__ cx<R> smem[C::P * LL];
@@ -1073,7 +1087,12 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
 template <typename R, typename Out, int M>
 __global__ void __launch_bounds__((rowfwd_cfg<R, R, M>::G * rowfwd_cfg<R, R, M>::T))
     k_row_c2r(const cx<R>* __restrict__ Y, Out* __restrict__ out, int nrows, int tj, const cx<R>* __restrict__ r2m,
-              int solve, const cx<R>* __restrict__ tw) {
+              int solve, const cx<R>* __restrict__ tw, const sg_bgrid* __restrict__ bg) {
+  if (bg) {  // batched: packed spectra in the second half of V
+    const sg_bgrid d = bg[blockIdx.y];
+    Y = reinterpret_cast<const cx<R>*>(d.V) + (int64_t)M * nrows;
+    out += d.off;
+  }
   using C = rowfwd_cfg<R, R, M>;
   constexpr int L = C::L, E = C::E, T = C::T, SLOT = C::SLOT;
   __shared__ cx<R> smem[C::G * SLOT];
@@ -1666,46 +1685,48 @@ int sg_twiddles(int prec, int pass, int len, const void* roots, void* out, hipSt
 template <typename R, int N>
 static hipError_t launch_col_adj_t(const cx<R>* Xx, const cx<R>* Xy, cx<R>* Y, int M, int tj, const void* tx,
                                    const void* ty, int kind, const cx<R>* r2n, int solve, const cx<R>* tw,
-                                   hipStream_t st) {
+                                   const sg_bgrid* bg, int ngrids, hipStream_t st) {
   using C = col_cfg<R, N>;
   using TO = typename tabs<R>::odd;
   using TC = typename tabs<R>::cplx;
   const int P = pow2_div(M, C::P);
+  const dim3 grid(M / P, bg ? ngrids : 1);
   const TO* tox = kind == 0 ? (const TO*)tx : nullptr;
   const TO* toy = kind == 0 ? (const TO*)ty : nullptr;
   const TC* tcx = kind == 1 ? (const TC*)tx : nullptr;
   const TC* tcy = kind == 1 ? (const TC*)ty : nullptr;
   if (kind == 1)
-    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 1>), dim3(M / P), dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy,
-                       tcx, tcy, r2n, tw);
+    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 1>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy, tcx, tcy,
+                       r2n, tw, bg);
   else if (solve)
-    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 2>), dim3(M / P), dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy,
-                       tcx, tcy, r2n, tw);
+    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 2>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy, tcx, tcy,
+                       r2n, tw, bg);
   else
-    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 0>), dim3(M / P), dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy,
-                       tcx, tcy, r2n, tw);
+    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 0>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy, tcx, tcy,
+                       r2n, tw, bg);
   return hipGetLastError();
 }
 
 template <typename R, int M>
 static hipError_t launch_row_c2r_t(const cx<R>* Y, R* out, int nrows, int tj, const cx<R>* r2m, int solve,
-                                   const cx<R>* tw, hipStream_t st) {
+                                   const cx<R>* tw, const sg_bgrid* bg, int ngrids, hipStream_t st) {
   using C = rowfwd_cfg<R, R, M>;
   const int G = C::G < nrows ? C::G : nrows;
-  hipLaunchKernelGGL((k_row_c2r<R, R, M>), dim3((nrows + G - 1) / G), dim3(G * C::T), 0, st, Y, out, nrows, tj, r2m,
-                     solve, tw);
+  hipLaunchKernelGGL((k_row_c2r<R, R, M>), dim3((nrows + G - 1) / G, bg ? ngrids : 1), dim3(G * C::T), 0, st, Y, out,
+                     nrows, tj, r2m, solve, tw, bg);
   return hipGetLastError();
 }
 
 template <typename R>
 static hipError_t adj_dispatch(int M, int N, const cx<R>* Xx, const cx<R>* Xy, cx<R>* Y, R* out, int tj,
                                const void* tx, const void* ty, int kind, const cx<R>* r2m, const cx<R>* r2n,
-                               int solve, const cx<R>* twB, const cx<R>* twA, hipStream_t st) {
+                               int solve, const cx<R>* twB, const cx<R>* twA, const sg_bgrid* bg, int ngrids,
+                               hipStream_t st) {
   hipError_t e = hipErrorInvalidValue;
   switch (N) {
-#define CASE(SZ)                                                                          \
-  case SZ:                                                                                \
-    e = launch_col_adj_t<R, SZ>(Xx, Xy, Y, M, tj, tx, ty, kind, r2n, solve, twB, st);     \
+#define CASE(SZ)                                                                                  \
+  case SZ:                                                                                        \
+    e = launch_col_adj_t<R, SZ>(Xx, Xy, Y, M, tj, tx, ty, kind, r2n, solve, twB, bg, ngrids, st); \
     break;
     SG_SIZES(CASE)
 #undef CASE
@@ -1716,7 +1737,7 @@ static hipError_t adj_dispatch(int M, int N, const cx<R>* Xx, const cx<R>* Xy, c
   switch (M) {
 #define CASE(SZ) \
   case SZ:       \
-    return launch_row_c2r_t<R, SZ>(Y, out, N, tj, r2m, solve, twA, st);
+    return launch_row_c2r_t<R, SZ>(Y, out, N, tj, r2m, solve, twA, bg, ngrids, st);
     SG_SIZES(CASE)
 #undef CASE
     default:
@@ -1726,13 +1747,14 @@ static hipError_t adj_dispatch(int M, int N, const cx<R>* Xx, const cx<R>* Xy, c
 
 hipError_t sg_launch_adjoint_tail(int prec, int M, int N, const void* Xx, const void* Xy, void* Y, void* gsigma,
                                   int tj, const void* tx, const void* ty, int kind, const void* r2m, const void* r2n,
-                                  int solve, const void* twB, const void* twA, hipStream_t st) {
+                                  int solve, const void* twB, const void* twA, const sg_bgrid* bg, int ngrids,
+                                  hipStream_t st) {
   if (prec == 0)
     return adj_dispatch<double>(M, N, (const cx<double>*)Xx, (const cx<double>*)Xy, (cx<double>*)Y, (double*)gsigma,
                                 tj, tx, ty, kind, (const cx<double>*)r2m, (const cx<double>*)r2n, solve,
-                                (const cx<double>*)twB, (const cx<double>*)twA, st);
+                                (const cx<double>*)twB, (const cx<double>*)twA, bg, ngrids, st);
   return adj_dispatch<float>(M, N, (const cx<float>*)Xx, (const cx<float>*)Xy, (cx<float>*)Y, (float*)gsigma, tj, tx,
                              ty, kind, (const cx<float>*)r2m, (const cx<float>*)r2n, solve, (const cx<float>*)twB,
-                             (const cx<float>*)twA, st);
+                             (const cx<float>*)twA, bg, ngrids, st);
 }
 #endif

@@ -211,3 +211,41 @@ def test_differentiation_at_scale_multigrid():
         a, b = offs[gi], offs[gi + 1]
         err = np.abs(g32[a:b] - g64h[a:b]).max() / np.abs(g64h[a:b]).max()
         assert err <= 1e-6 * amps[gi] + 1e-6, (gi, err, amps[gi])
+
+
+def test_autograd_multigrid_plan_equals_single_plans():
+    """A plan of several grids (mixed sizes and orders): its autograd
+    gradient equals, bit for bit, that of one plan per grid."""
+    sg = _sg()
+    import torch
+    grids = [(96, 48, -1.0, 1.0, -1.0, 1.0, 3), (64, 64, -1.0, 1.0, -1.0, 1.0, 2), (96, 48, -1.0, 1.0, -1.0, 1.0, 3),
+             (32, 128, -1.0, 1.0, -2.0, 2.0, 1)]
+    rng = np.random.default_rng(77)
+    sig = [rng.standard_normal(g[0] * g[1]) for g in grids]
+    tgt = [rng.standard_normal(2 * g[0] * g[1]) for g in grids]
+    for prec in (sg.SG_FP64, sg.SG_FP32_SPLIT):
+        plan = sg.Plan(grids, prec)
+        try:
+            s = to_dev(np.concatenate(sig), plan.dtype).requires_grad_(True)
+            fx, fy = sg.ThinDiskForces.apply(s, plan)
+            tx = to_dev(np.concatenate([t[: t.size // 2] for t in tgt]), plan.dtype)
+            ty = to_dev(np.concatenate([t[t.size // 2:] for t in tgt]), plan.dtype)
+            (((fx - tx) ** 2).sum() + ((fy - ty) ** 2).sum()).backward()
+            torch.cuda.synchronize()
+            batched = s.grad.clone()
+            offs = plan.offsets
+        finally:
+            plan.close()
+        for gi, g in enumerate(grids):
+            p1 = sg.Plan([g], prec)
+            try:
+                s1 = to_dev(sig[gi], p1.dtype).requires_grad_(True)
+                fx, fy = sg.ThinDiskForces.apply(s1, p1)
+                n = g[0] * g[1]
+                tx = to_dev(tgt[gi][:n], p1.dtype)
+                ty = to_dev(tgt[gi][n:], p1.dtype)
+                (((fx - tx) ** 2).sum() + ((fy - ty) ** 2).sum()).backward()
+                torch.cuda.synchronize()
+                assert torch.equal(s1.grad, batched[offs[gi]:offs[gi + 1]]), (prec, gi)
+            finally:
+                p1.close()
