@@ -23,8 +23,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC, "--offload-
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]
 # (source, extra flags, object name): the kernel file is compiled in four
-# parts (SG_PART) in parallel
-UNITS = [("sg_kernels.hip", ["-DSG_PART=%d" % i], "sg_kernels_p%d.o" % i) for i in range(4)] + \
+# parts (SG_PART, a bit mask of the parts) in parallel
+UNITS = [("sg_kernels.hip", ["-DSG_PART=%d" % (1 << i)], "sg_kernels_p%d.o" % i) for i in range(4)] + \
         [("sg_api.cpp", [], "sg_api.o")]
 
 

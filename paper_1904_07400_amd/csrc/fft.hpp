@@ -250,7 +250,8 @@ template <bool INV, int L, int T, int S, typename R>
 __device__ __forceinline__ void fft_stages(cx<R>* v, cx<R>* lds, const cx<R>* __restrict__ tw, int t) {
   using P = plan<L, L / T>;
   if constexpr (S < P::nstages) {
-    stockham_stage<INV, L, T, P::radix(S), P::ns_before(S)>(v, lds, tw + P::tw_offset(S), t);
+    constexpr int off = P::tw_offset(S);
+    stockham_stage<INV, L, T, P::radix(S), P::ns_before(S)>(v, lds, tw + off, t);
     fft_stages<INV, L, T, S + 1>(v, lds, tw, t);
   }
 }
@@ -327,7 +328,8 @@ __device__ __forceinline__ void fft2_stages(cx<R>* v0, cx<R>* v1, cx<R>* lds0, c
                                             const cx<R>* __restrict__ tw, int t) {
   using P = plan<L, L / T>;
   if constexpr (S < P::nstages) {
-    stockham_stage2<INV, L, T, P::radix(S), P::ns_before(S)>(v0, v1, lds0, lds1, tw + P::tw_offset(S), t);
+    constexpr int off = P::tw_offset(S);
+    stockham_stage2<INV, L, T, P::radix(S), P::ns_before(S)>(v0, v1, lds0, lds1, tw + off, t);
     fft2_stages<INV, L, T, S + 1>(v0, v1, lds0, lds1, tw, t);
   }
 }
@@ -393,7 +395,8 @@ __device__ __forceinline__ void fftn_stages(cx<R> (&v)[NA][L / T], cx<R>* lds, i
                                             const cx<R>* __restrict__ tw, int t) {
   using P = plan<L, L / T>;
   if constexpr (S < P::nstages) {
-    stockham_stage_n<INV, L, T, P::radix(S), P::ns_before(S), NA>(v, lds, stride, tw + P::tw_offset(S), t);
+    constexpr int off = P::tw_offset(S);
+    stockham_stage_n<INV, L, T, P::radix(S), P::ns_before(S), NA>(v, lds, stride, tw + off, t);
     fftn_stages<INV, L, T, S + 1, NA>(v, lds, stride, tw, t);
   }
 }

@@ -108,13 +108,13 @@
 #define SG_WPE(R, P) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? SG_##P##_WPE32 : SG_##P##_WPE64)))
 
 // The host dispatch is split into parts that can be compiled as separate
-// objects in parallel (SG_PART = 0: plan-time and helper kernels, 1: row
-// passes, 2: column pass, 3: adjoint column and row passes); without
-// SG_PART everything is compiled.
+// objects in parallel (bit 0: plan-time and helper kernels, 1: row passes,
+// 2: column pass, 3: adjoint column and row passes; SG_PART is a mask of
+// them); without SG_PART everything is compiled.
 #ifndef SG_PART
-#define SG_PART -1
+#define SG_PART 15
 #endif
-#define SG_IN_PART(n) (SG_PART < 0 || SG_PART == (n))
+#define SG_IN_PART(n) ((SG_PART >> (n)) & 1)
 
 namespace sg {
 
