@@ -35,7 +35,7 @@
 #define SG_RI_E64 16
 #endif
 #ifndef SG_COL_E32
-#define SG_COL_E32 8
+#define SG_COL_E32 4
 #endif
 // rows per tile of the column pass's output (its store segments hold
 // SG_TJ consecutive rows of one column)
