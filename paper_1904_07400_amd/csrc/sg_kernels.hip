@@ -23,7 +23,7 @@
 // Launch-shape knobs (compile-time; elements per thread E and threads per
 // workgroup of each pass).  Defaults are the measured best on MI355X.
 #ifndef SG_RF_THREADS
-#define SG_RF_THREADS 256
+#define SG_RF_THREADS 512
 #endif
 #ifndef SG_RI_THREADS
 #define SG_RI_THREADS 256
@@ -49,7 +49,7 @@
 #define SG_COL_E64 8
 #endif
 #ifndef SG_RF_E32
-#define SG_RF_E32 16
+#define SG_RF_E32 8
 #endif
 #ifndef SG_COL_NBUF32
 #define SG_COL_NBUF32 4
