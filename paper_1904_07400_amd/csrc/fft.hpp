@@ -202,13 +202,51 @@ struct roots_t {
   __device__ __forceinline__ cx<R> operator()(int i) const { return tab[i * S]; }
 };
 
+#ifndef SG_TW_EARLY_BYTES
+#define SG_TW_EARLY_BYTES 64
+#endif
+
+// Twiddles of stage S of plan<L, L/T> held by one thread: w[u][q] for its
+// butterfly u and input q >= 1 (nothing for the first stage, Ns = 1).
+template <int L, int T, int S, typename R>
+struct stage_tw {
+  using P = plan<L, L / T>;
+  static constexpr bool live = S < P::nstages;
+  static constexpr int r = live ? P::radix(S) : 1;
+  static constexpr int NB = (L / T) / r;
+  static constexpr int Ns = live ? P::ns_before(S) : 1;
+  static constexpr bool has = live && Ns > 1;
+  // loaded one stage ahead when they take few registers, else at the stage
+  static constexpr bool early = has && NB * (r - 1) * (int)sizeof(cx<R>) <= SG_TW_EARLY_BYTES;
+  cx<R> w[early ? NB : 1][early ? r : 1];
+  __device__ __forceinline__ cx<R> fetch(const cx<R>* __restrict__ tw, int t, int u, int q) const {
+    constexpr int off = P::tw_offset(S);
+    const unsigned k = (unsigned)(t + u * T) % (unsigned)Ns;
+    return tw[(unsigned)(off + (q - 1) * Ns) + k];
+  }
+  __device__ __forceinline__ void load(const cx<R>* __restrict__ tw, int t) {
+    if constexpr (early) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+#pragma unroll
+        for (int q = 1; q < r; ++q) w[u][q] = fetch(tw, t, u, q);
+    }
+  }
+  // twiddle q of butterfly u: from registers, or loaded now
+  __device__ __forceinline__ cx<R> get(const cx<R>* __restrict__ tw, int t, int u, int q) const {
+    if constexpr (early) return w[u][q];
+    else return fetch(tw, t, u, q);
+  }
+};
+
 // One Stockham stage.  v: E registers (strided distribution).  Unless this
 // is the last stage, the result is exchanged through lds (L padded slots)
 // and v again holds the strided distribution of the stage output.  tw: the
 // stage's twiddle table (see plan::tw_offset): consecutive butterflies read
 // consecutive entries.
-template <bool INV, int L, int T, int r, int Ns, typename R>
-__device__ __forceinline__ void stockham_stage(cx<R>* v, cx<R>* lds, const cx<R>* __restrict__ tw, int t) {
+template <bool INV, int L, int T, int r, int Ns, typename R, typename W>
+__device__ __forceinline__ void stockham_stage(cx<R>* v, cx<R>* lds, const W& tws, const cx<R>* __restrict__ tw,
+                                               int t) {
   constexpr int E = L / T;
   constexpr int NB = E / r;
   constexpr bool last = (Ns * r == L);
@@ -219,11 +257,9 @@ __device__ __forceinline__ void stockham_stage(cx<R>* v, cx<R>* lds, const cx<R>
 #pragma unroll
     for (int q = 0; q < r; ++q) a[q] = v[u + q * NB];
     if constexpr (Ns > 1) {
-      // unsigned 32-bit offsets from the uniform table base (scalar-base loads)
-      const unsigned k = (unsigned)b % (unsigned)Ns;
 #pragma unroll
       for (int q = 1; q < r; ++q) {
-        const cx<R> w = tw[(unsigned)((q - 1) * Ns) + k];
+        const cx<R> w = tws.get(tw, t, u, q);
         a[q] = INV ? cmulc(a[q], w) : cmul(a[q], w);
       }
     }
@@ -246,13 +282,17 @@ __device__ __forceinline__ void stockham_stage(cx<R>* v, cx<R>* lds, const cx<R>
   }
 }
 
+// Stage S onwards; the next stage's twiddles are loaded before this stage's
+// butterflies and barriers, so that their latency hides behind them.
 template <bool INV, int L, int T, int S, typename R>
-__device__ __forceinline__ void fft_stages(cx<R>* v, cx<R>* lds, const cx<R>* __restrict__ tw, int t) {
+__device__ __forceinline__ void fft_stages(cx<R>* v, cx<R>* lds, const cx<R>* __restrict__ tw,
+                                           const stage_tw<L, T, S, R>& cur, int t) {
   using P = plan<L, L / T>;
   if constexpr (S < P::nstages) {
-    constexpr int off = P::tw_offset(S);
-    stockham_stage<INV, L, T, P::radix(S), P::ns_before(S)>(v, lds, tw + off, t);
-    fft_stages<INV, L, T, S + 1>(v, lds, tw, t);
+    stage_tw<L, T, S + 1, R> nxt;
+    nxt.load(tw, t);
+    stockham_stage<INV, L, T, P::radix(S), P::ns_before(S)>(v, lds, cur, tw, t);
+    fft_stages<INV, L, T, S + 1>(v, lds, tw, nxt, t);
   }
 }
 
@@ -266,13 +306,14 @@ __device__ __forceinline__ void fft(cx<R>* v, cx<R>* lds, const cx<R>* __restric
   // keep the twiddle loads inside this transform (no hoisting across calls)
   __asm__ volatile("" ::: "memory");
 #endif
-  fft_stages<INV, L, T, 0>(v, lds, tw, t);
+  stage_tw<L, T, 0, R> s0;  // the first stage has no twiddles
+  fft_stages<INV, L, T, 0>(v, lds, tw, s0, t);
 }
 
 // Two independent transforms of the same length through the same stages,
 // sharing each exchange's barriers (lds0, lds1: separate padded buffers).
-template <bool INV, int L, int T, int r, int Ns, typename R>
-__device__ __forceinline__ void stockham_stage2(cx<R>* v0, cx<R>* v1, cx<R>* lds0, cx<R>* lds1,
+template <bool INV, int L, int T, int r, int Ns, typename R, typename W>
+__device__ __forceinline__ void stockham_stage2(cx<R>* v0, cx<R>* v1, cx<R>* lds0, cx<R>* lds1, const W& tws,
                                                 const cx<R>* __restrict__ tw, int t) {
   constexpr int E = L / T;
   constexpr int NB = E / r;
@@ -287,10 +328,9 @@ __device__ __forceinline__ void stockham_stage2(cx<R>* v0, cx<R>* v1, cx<R>* lds
       a1[q] = v1[u + q * NB];
     }
     if constexpr (Ns > 1) {
-      const unsigned k = (unsigned)b % (unsigned)Ns;
 #pragma unroll
       for (int q = 1; q < r; ++q) {
-        const cx<R> w = tw[(unsigned)((q - 1) * Ns) + k];
+        const cx<R> w = tws.get(tw, t, u, q);
         a0[q] = INV ? cmulc(a0[q], w) : cmul(a0[q], w);
         a1[q] = INV ? cmulc(a1[q], w) : cmul(a1[q], w);
       }
@@ -325,12 +365,13 @@ __device__ __forceinline__ void stockham_stage2(cx<R>* v0, cx<R>* v1, cx<R>* lds
 
 template <bool INV, int L, int T, int S, typename R>
 __device__ __forceinline__ void fft2_stages(cx<R>* v0, cx<R>* v1, cx<R>* lds0, cx<R>* lds1,
-                                            const cx<R>* __restrict__ tw, int t) {
+                                            const cx<R>* __restrict__ tw, const stage_tw<L, T, S, R>& cur, int t) {
   using P = plan<L, L / T>;
   if constexpr (S < P::nstages) {
-    constexpr int off = P::tw_offset(S);
-    stockham_stage2<INV, L, T, P::radix(S), P::ns_before(S)>(v0, v1, lds0, lds1, tw + off, t);
-    fft2_stages<INV, L, T, S + 1>(v0, v1, lds0, lds1, tw, t);
+    stage_tw<L, T, S + 1, R> nxt;
+    nxt.load(tw, t);
+    stockham_stage2<INV, L, T, P::radix(S), P::ns_before(S)>(v0, v1, lds0, lds1, cur, tw, t);
+    fft2_stages<INV, L, T, S + 1>(v0, v1, lds0, lds1, tw, nxt, t);
   }
 }
 
@@ -339,14 +380,15 @@ template <bool INV, int L, int T, typename R>
 __device__ __forceinline__ void fft2(cx<R>* v0, cx<R>* v1, cx<R>* lds0, cx<R>* lds1, const cx<R>* __restrict__ tw,
                                      int t) {
   static_assert(L % T == 0, "L must be a multiple of T");
-  fft2_stages<INV, L, T, 0>(v0, v1, lds0, lds1, tw, t);
+  stage_tw<L, T, 0, R> s0;
+  fft2_stages<INV, L, T, 0>(v0, v1, lds0, lds1, tw, s0, t);
 }
 
 // NA independent transforms of the same length through the same stages,
 // sharing each exchange's barriers: v[i] in registers, exchange buffer i at
-// lds + i * stride.
-template <bool INV, int L, int T, int r, int Ns, int NA, typename R>
-__device__ __forceinline__ void stockham_stage_n(cx<R> (&v)[NA][L / T], cx<R>* lds, int stride,
+// lds + i * stride.  W: this stage's twiddles, already loaded.
+template <bool INV, int L, int T, int r, int Ns, int NA, typename R, typename W>
+__device__ __forceinline__ void stockham_stage_n(cx<R> (&v)[NA][L / T], cx<R>* lds, int stride, const W& tws,
                                                  const cx<R>* __restrict__ tw, int t) {
   constexpr int E = L / T;
   constexpr int NB = E / r;
@@ -356,9 +398,8 @@ __device__ __forceinline__ void stockham_stage_n(cx<R> (&v)[NA][L / T], cx<R>* l
     const int b = t + u * T;
     cx<R> w[r];
     if constexpr (Ns > 1) {
-      const unsigned k = (unsigned)b % (unsigned)Ns;
 #pragma unroll
-      for (int q = 1; q < r; ++q) w[q] = tw[(unsigned)((q - 1) * Ns) + k];
+      for (int q = 1; q < r; ++q) w[q] = tws.get(tw, t, u, q);
     }
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
@@ -390,14 +431,18 @@ __device__ __forceinline__ void stockham_stage_n(cx<R> (&v)[NA][L / T], cx<R>* l
   }
 }
 
+// Stage S onwards.  The next stage's twiddles are loaded before this
+// stage's butterflies and barriers, so that their latency is hidden behind
+// them rather than exposed after the barrier.
 template <bool INV, int L, int T, int S, int NA, typename R>
 __device__ __forceinline__ void fftn_stages(cx<R> (&v)[NA][L / T], cx<R>* lds, int stride,
-                                            const cx<R>* __restrict__ tw, int t) {
+                                            const cx<R>* __restrict__ tw, const stage_tw<L, T, S, R>& cur, int t) {
   using P = plan<L, L / T>;
   if constexpr (S < P::nstages) {
-    constexpr int off = P::tw_offset(S);
-    stockham_stage_n<INV, L, T, P::radix(S), P::ns_before(S), NA>(v, lds, stride, tw + off, t);
-    fftn_stages<INV, L, T, S + 1, NA>(v, lds, stride, tw, t);
+    stage_tw<L, T, S + 1, R> nxt;
+    nxt.load(tw, t);
+    stockham_stage_n<INV, L, T, P::radix(S), P::ns_before(S), NA>(v, lds, stride, cur, tw, t);
+    fftn_stages<INV, L, T, S + 1, NA>(v, lds, stride, tw, nxt, t);
   }
 }
 
@@ -406,7 +451,8 @@ template <bool INV, int L, int T, int NA, typename R>
 __device__ __forceinline__ void fftn(cx<R> (&v)[NA][L / T], cx<R>* lds, int stride, const cx<R>* __restrict__ tw,
                                      int t) {
   static_assert(L % T == 0, "L must be a multiple of T");
-  fftn_stages<INV, L, T, 0, NA>(v, lds, stride, tw, t);
+  stage_tw<L, T, 0, R> s0;  // the first stage has no twiddles
+  fftn_stages<INV, L, T, 0, NA>(v, lds, stride, tw, s0, t);
 }
 
 // Fill the stage tables of plan<L, E> from a table of roots of unity

@@ -262,6 +262,23 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return (b % 8) * (nb / 8) + b / 8;
 }
 
+// The batch descriptor of grid blockIdx.y, read through the constant address
+// space: pointers loaded from constant memory are taken to be global, so
+// accesses through them compile to global instructions rather than flat ones
+// (flat accesses also count on the LDS wait counter, so every LDS wait would
+// wait for them too).  All of the library's buffers are device memory.
+__device__ __forceinline__ sg_bgrid grid_desc(const sg_bgrid* bg) {
+  using K = const __attribute__((address_space(4))) sg_bgrid;
+  const K* k = (const K*)bg + blockIdx.y;
+  sg_bgrid d;
+  d.off = k->off;
+  d.X = k->X;
+  d.V = k->V;
+  d.tabx = k->tabx;
+  d.taby = k->taby;
+  return d;
+}
+
 // ---------------------------------------------------------------- pass A --
 // Real FFT of length 2M of a row whose upper half is zero (or, with full,
 // of a row of 2M values), via the complex FFT of length M of
@@ -299,7 +316,7 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
               const cx<R>* __restrict__ r2m, int solve, int full, const cx<R>* __restrict__ tw,
               const sg_bgrid* __restrict__ bg) {
   if (bg) {  // batched: grid blockIdx.y of the class
-    const sg_bgrid d = bg[blockIdx.y];
+    const sg_bgrid d = grid_desc(bg);
     src += d.off;
     X = reinterpret_cast<cx<R>*>(d.X);
   }
@@ -430,18 +447,19 @@ struct col_cfg {
 };
 
 // spectrum lookup helpers: odd k (real tables, W = i A) and k = 2 (complex)
-template <typename R, typename TO>
-__device__ __forceinline__ cx<R> mul_iA(cx<R> z, const TO* tab, int idx, R sgn);
-template <>
-__device__ __forceinline__ cx<double> mul_iA(cx<double> z, const double* tab, int idx, double sgn) {
-  const double a = tab[(unsigned)idx] * sgn;
+// z * (i A sgn) with a table entry A (double, or a float hi+lo pair)
+__device__ __forceinline__ cx<double> apply_iA(cx<double> z, double a, double sgn) {
+  a *= sgn;
   return {-z.y * a, z.x * a};
 }
-template <>
-__device__ __forceinline__ cx<float> mul_iA(cx<float> z, const float2* tab, int idx, float sgn) {
-  const float2 a = tab[(unsigned)idx];
-  const float h = a.x * sgn, l = a.y * sgn;
-  return {-(z.y * h + z.y * l), z.x * h + z.x * l};
+__device__ __forceinline__ cx<float> apply_iA(cx<float> z, float2 a, float sgn) {
+  // the sign is applied last (exact either way), so that a prefetched entry
+  // is not needed before the product itself
+  return {-(z.y * a.x + z.y * a.y) * sgn, (z.x * a.x + z.x * a.y) * sgn};
+}
+template <typename R, typename TO>
+__device__ __forceinline__ cx<R> mul_iA(cx<R> z, const TO* tab, int idx, R sgn) {
+  return apply_iA(z, tab[(unsigned)idx], sgn);
 }
 template <typename R, typename TC>
 __device__ __forceinline__ cx<R> mul_W(cx<R> z, const TC* tab, int idx, bool cj);
@@ -463,6 +481,19 @@ __device__ __forceinline__ cx<float> mul_W(cx<float> z, const float4* tab, int i
 // Product of the column spectrum with W^d (or conj W^d, CJ) at column bin p.
 // half 0: bins q = 2q', half 1: q = 2q'+1.  eps: symmetry of the stored
 // table across q -> 2N - q (+1 for x, -1 for y) for odd k.
+// Odd k: the stored entry of the real table for column bin p, row bin qq of
+// half `half` (row: the table row of bin p), and its sign (+1, or eps past
+// the reflection q -> 2N - q).
+template <typename TO, int N>
+__device__ __forceinline__ TO odd_entry(const TO* row, int qq, int half) {
+  if (half == 0) return row[(unsigned)(qq <= N / 2 ? qq : N - qq)];
+  return row[(unsigned)(N / 2 + 1 + (qq < N / 2 ? qq : N - 1 - qq))];
+}
+template <typename R, int N>
+__device__ __forceinline__ R odd_sign(int qq, int half, R eps) {
+  return (half == 0 ? qq <= N / 2 : qq < N / 2) ? (R)1 : eps;
+}
+
 template <typename R, typename TO, typename TC, int N, bool CJ = false>
 __device__ __forceinline__ cx<R> spec_mul(cx<R> z, int kind, const TO* to, const TC* tc, int p, int qq,
                                           int half, R eps) {
@@ -488,11 +519,15 @@ __device__ __forceinline__ cx<R> spec_mul(cx<R> z, int kind, const TO* to, const
 template <typename R, typename TO, typename TC, int N, int E, int T>
 __device__ __forceinline__ void col_product(const cx<R>* f, cx<R>* g, int half, bool exch, bool packed, cx<R>* lds,
                                             int kind, const TO* to, const TC* tc, R eps, int c, int M, int t) {
-  if (exch) {
+  if (!exch) {
+    // no packed column in this workgroup: independent loads, no branches
 #pragma unroll
-    for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = f[e];
-    __syncthreads();
+    for (int e = 0; e < E; ++e) g[e] = spec_mul<R, TO, TC, N>(f[e], kind, to, tc, c, t + e * T, half, eps);
+    return;
   }
+#pragma unroll
+  for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = f[e];
+  __syncthreads();
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int qq = t + e * T;
@@ -508,7 +543,7 @@ __device__ __forceinline__ void col_product(const cx<R>* f, cx<R>* g, int half, 
       g[e] = spec_mul<R, TO, TC, N>(f[e], kind, to, tc, c, qq, half, eps);
     }
   }
-  if (exch) __syncthreads();
+  __syncthreads();
 }
 
 // MODE: 0 = k 1 (real tables, no solve), 1 = k 2 (complex tables), 2 = k 3
@@ -521,7 +556,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
   constexpr int kind = MODE == 1 ? 1 : 0;
   constexpr bool solve = MODE == 2;
   if (bg) {  // batched: grid blockIdx.y of the class
-    const sg_bgrid d = bg[blockIdx.y];
+    const sg_bgrid d = grid_desc(bg);
     X = reinterpret_cast<const cx<R>*>(d.X);
     V = reinterpret_cast<cx<R>*>(d.V);
     if (kind == 0) {
@@ -542,15 +577,32 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
   cx<R>* lds = smem + g * LL * NBUF;
   cx<R>* lds2 = lds + (NBUF - 1) * LL;
   const cx<R>* col = X + (int64_t)c * N;  // column c, contiguous (column-major X)
+  const bool exch = (c0 == 0);            // this workgroup holds the packed column 0
+  // the column: chunk of E per thread for the solve, else strided
   cx<R> a[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) a[e] = col[(unsigned)(solve ? t * E + e : t + e * T)];
+  // Odd k with four exchange buffers: every table entry of the four products
+  // is loaded here, after the column (loads complete in order), so that
+  // their latency overlaps the solve and the forward transforms (in order
+  // x even, y even, x odd, y odd).
+  constexpr bool pre = (kind == 0) && (NBUF == 4);
+  TO tv[pre ? 4 : 1][pre ? E : 1];
+  if constexpr (pre) {
+    // unconditional (unused by the packed workgroup), so that the waits
+    // for the column above can count them
+    const TO* rx = tox + (int64_t)c * (N + 1);
+    const TO* ry = toy + (int64_t)c * (N + 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < E; ++e) tv[i][e] = odd_entry<TO, N>((i & 1) ? ry : rx, t + e * T, i >> 1);
+  }
   if (solve) {
     // y-solve of Eq. (z_system) on the complex row spectra, FP64, chunk of E per thread
     double2 d[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const cx<R> v = col[(unsigned)(t * E + e)];
-      d[e] = make_double2(8.0 * (double)v.x, 8.0 * (double)v.y);
-    }
+    for (int e = 0; e < E; ++e) d[e] = make_double2(8.0 * (double)a[e].x, 8.0 * (double)a[e].y);
     tri_solve<E, T, double2>(d, t, *reinterpret_cast<tri_smem<double2, T>*>(lds));
 #pragma unroll
     for (int e = 0; e < E; ++e) lds[pad(t * E + e)] = cx<R>{(R)d[e].x, (R)d[e].y};
@@ -558,9 +610,6 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
 #pragma unroll
     for (int e = 0; e < E; ++e) a[e] = lds[pad(t + e * T)];
     __syncthreads();
-  } else {
-#pragma unroll
-    for (int e = 0; e < E; ++e) a[e] = col[(unsigned)(t + e * T)];
   }
 
   const bool packed = (c == 0);
@@ -591,10 +640,24 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
       }
     }
     cx<R> g4[4][E];
-    col_product<R, TO, TC, N, E, T>(fe, g4[0], 0, c0 == 0, packed, lds, kind, tox, tcx, (R)1, c, M, t);
-    col_product<R, TO, TC, N, E, T>(fe, g4[1], 0, c0 == 0, packed, lds, kind, toy, tcy, (R)-1, c, M, t);
-    col_product<R, TO, TC, N, E, T>(fo, g4[2], 1, c0 == 0, packed, lds, kind, tox, tcx, (R)1, c, M, t);
-    col_product<R, TO, TC, N, E, T>(fo, g4[3], 1, c0 == 0, packed, lds, kind, toy, tcy, (R)-1, c, M, t);
+    bool done = false;
+    if constexpr (pre) {
+      if (!exch) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int e = 0; e < E; ++e)
+            g4[i][e] = apply_iA((i >> 1) ? fo[e] : fe[e], tv[i][e],
+                                odd_sign<R, N>(t + e * T, i >> 1, (i & 1) ? (R)-1 : (R)1));
+        done = true;
+      }
+    }
+    if (!done) {
+      col_product<R, TO, TC, N, E, T>(fe, g4[0], 0, exch, packed, lds, kind, tox, tcx, (R)1, c, M, t);
+      col_product<R, TO, TC, N, E, T>(fe, g4[1], 0, exch, packed, lds, kind, toy, tcy, (R)-1, c, M, t);
+      col_product<R, TO, TC, N, E, T>(fo, g4[2], 1, exch, packed, lds, kind, tox, tcx, (R)1, c, M, t);
+      col_product<R, TO, TC, N, E, T>(fo, g4[3], 1, exch, packed, lds, kind, toy, tcy, (R)-1, c, M, t);
+    }
     fftn<true, N, T, 4>(g4, lds, LL, tw, t);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -610,8 +673,8 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     for (int half = 0; half < 2; ++half) {
       const cx<R>* f = half ? fo : fe;
       cx<R> gx[E], gy[E];
-      col_product<R, TO, TC, N, E, T>(f, gx, half, c0 == 0, packed, lds, kind, tox, tcx, (R)1, c, M, t);
-      col_product<R, TO, TC, N, E, T>(f, gy, half, c0 == 0, packed, lds, kind, toy, tcy, (R)-1, c, M, t);
+      col_product<R, TO, TC, N, E, T>(f, gx, half, exch, packed, lds, kind, tox, tcx, (R)1, c, M, t);
+      col_product<R, TO, TC, N, E, T>(f, gy, half, exch, packed, lds, kind, toy, tcy, (R)-1, c, M, t);
       fft2<true, N, T>(gx, gy, lds, lds2, tw, t);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -636,7 +699,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
 #pragma unroll
       for (int comp = 0; comp < 2; ++comp) {
         cx<R> g[E];
-        col_product<R, TO, TC, N, E, T>(f, g, half, c0 == 0, packed, lds, kind, comp ? toy : tox, comp ? tcy : tcx,
+        col_product<R, TO, TC, N, E, T>(f, g, half, exch, packed, lds, kind, comp ? toy : tox, comp ? tcy : tcx,
                                         comp ? (R)-1 : (R)1, c, M, t);
         fft<true, N, T>(g, lds, tw, t);
         cx<R>* acc = comp ? accy : accx;
@@ -730,7 +793,7 @@ __global__ void __launch_bounds__((col_cfg<float, N>::P * col_cfg<float, N>::T))
   constexpr int kind = MODE == 1 ? 1 : 0;
   constexpr bool solve = MODE == 2;
   if (bg) {
-    const sg_bgrid d = bg[blockIdx.y];
+    const sg_bgrid d = grid_desc(bg);
     X = reinterpret_cast<const cx<R>*>(d.X);
     V = reinterpret_cast<cx<R>*>(d.V);
     if (kind == 0) {
@@ -889,7 +952,7 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
     k_row_inv(const cx<R>* __restrict__ V, Out* __restrict__ fx, Out* __restrict__ fy, int nrows, int tj,
               const cx<R>* __restrict__ r2m, const cx<R>* __restrict__ tw, const sg_bgrid* __restrict__ bg) {
   if (bg) {  // batched: grid blockIdx.y of the class
-    const sg_bgrid d = bg[blockIdx.y];
+    const sg_bgrid d = grid_desc(bg);
     V = reinterpret_cast<const cx<R>*>(d.V);
     fx += d.off;
     fy += d.off;
@@ -1008,7 +1071,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
   constexpr int kind = MODE == 1 ? 1 : 0;
   constexpr bool solve = MODE == 2;
   if (bg) {  // batched: gx spectra in X, gy spectra in the first half of V, output in its second half
-    const sg_bgrid d = bg[blockIdx.y];
+    const sg_bgrid d = grid_desc(bg);
     Xx = reinterpret_cast<const cx<R>*>(d.X);
     Xy = reinterpret_cast<const cx<R>*>(d.V);
     Y = reinterpret_cast<cx<R>*>(d.V) + (int64_t)M * N;
@@ -1089,7 +1152,7 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, R, M>::G * rowfwd_cfg<R, R, M>:
     k_row_c2r(const cx<R>* __restrict__ Y, Out* __restrict__ out, int nrows, int tj, const cx<R>* __restrict__ r2m,
               int solve, const cx<R>* __restrict__ tw, const sg_bgrid* __restrict__ bg) {
   if (bg) {  // batched: packed spectra in the second half of V
-    const sg_bgrid d = bg[blockIdx.y];
+    const sg_bgrid d = grid_desc(bg);
     Y = reinterpret_cast<const cx<R>*>(d.V) + (int64_t)M * nrows;
     out += d.off;
   }
