@@ -387,7 +387,7 @@ __device__ __forceinline__ void fft2(cx<R>* v0, cx<R>* v1, cx<R>* lds0, cx<R>* l
 // NA independent transforms of the same length through the same stages,
 // sharing each exchange's barriers: v[i] in registers, exchange buffer i at
 // lds + i * stride.  W: this stage's twiddles, already loaded.
-template <bool INV, int L, int T, int r, int Ns, int NA, typename R, typename W>
+template <bool INV, int L, int T, int r, int Ns, int NA, typename R, typename W, bool TAIL = true>
 __device__ __forceinline__ void stockham_stage_n(cx<R> (&v)[NA][L / T], cx<R>* lds, int stride, const W& tws,
                                                  const cx<R>* __restrict__ tw, int t) {
   constexpr int E = L / T;
@@ -427,7 +427,7 @@ __device__ __forceinline__ void stockham_stage_n(cx<R> (&v)[NA][L / T], cx<R>* l
     for (int i = 0; i < NA; ++i)
 #pragma unroll
       for (int e = 0; e < E; ++e) v[i][e] = lds[i * stride + pad(t + e * T)];
-    __syncthreads();
+    if constexpr (TAIL) __syncthreads();
   }
 }
 
@@ -453,6 +453,32 @@ __device__ __forceinline__ void fftn(cx<R> (&v)[NA][L / T], cx<R>* lds, int stri
   static_assert(L % T == 0, "L must be a multiple of T");
   stage_tw<L, T, 0, R> s0;  // the first stage has no twiddles
   fftn_stages<INV, L, T, 0, NA>(v, lds, stride, tw, s0, t);
+}
+
+// fftn() with the exchanges alternating between two sets of NA buffers
+// (set s % 2 at lds + (s % 2) * NA * stride): a stage's writes cannot meet a
+// slower thread's reads of the previous stage, which used the other set, so
+// each exchange needs one barrier instead of two.  One barrier at the end
+// lets the caller reuse the buffers.  Needs 2 * NA buffers.
+template <bool INV, int L, int T, int S, int NA, typename R>
+__device__ __forceinline__ void fftn_pp_stages(cx<R> (&v)[NA][L / T], cx<R>* lds, int stride,
+                                               const cx<R>* __restrict__ tw, const stage_tw<L, T, S, R>& cur, int t) {
+  using P = plan<L, L / T>;
+  if constexpr (S < P::nstages) {
+    stage_tw<L, T, S + 1, R> nxt;
+    nxt.load(tw, t);
+    stockham_stage_n<INV, L, T, P::radix(S), P::ns_before(S), NA, R, stage_tw<L, T, S, R>, false>(
+        v, lds + (S % 2) * NA * stride, stride, cur, tw, t);
+    fftn_pp_stages<INV, L, T, S + 1, NA>(v, lds, stride, tw, nxt, t);
+  }
+}
+template <bool INV, int L, int T, int NA, typename R>
+__device__ __forceinline__ void fftn_pp(cx<R> (&v)[NA][L / T], cx<R>* lds, int stride, const cx<R>* __restrict__ tw,
+                                        int t) {
+  static_assert(L % T == 0, "L must be a multiple of T");
+  stage_tw<L, T, 0, R> s0;
+  fftn_pp_stages<INV, L, T, 0, NA>(v, lds, stride, tw, s0, t);
+  if constexpr (plan<L, L / T>::nstages > 1) __syncthreads();
 }
 
 // Fill the stage tables of plan<L, E> from a table of roots of unity

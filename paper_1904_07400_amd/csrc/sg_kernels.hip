@@ -28,6 +28,9 @@
 #ifndef SG_RI_THREADS
 #define SG_RI_THREADS 256
 #endif
+#ifndef SG_RI_ILV
+#define SG_RI_ILV 0
+#endif
 #ifndef SG_RI_E32
 #define SG_RI_E32 8
 #endif
@@ -35,12 +38,12 @@
 #define SG_RI_E64 16
 #endif
 #ifndef SG_COL_E32
-#define SG_COL_E32 4
+#define SG_COL_E32 8
 #endif
 // rows per tile of the column pass's output (its store segments hold
 // SG_TJ consecutive rows of one column)
 #ifndef SG_TJ32
-#define SG_TJ32 4
+#define SG_TJ32 8
 #endif
 #ifndef SG_TJ64
 #define SG_TJ64 2
@@ -50,6 +53,12 @@
 #endif
 #ifndef SG_RF_E32
 #define SG_RF_E32 8
+#endif
+#ifndef SG_COL_PP
+#define SG_COL_PP 1
+#endif
+#ifndef SG_COL_WG32
+#define SG_COL_WG32 256
 #endif
 #ifndef SG_COL_NBUF32
 #define SG_COL_NBUF32 4
@@ -441,8 +450,11 @@ struct col_cfg {
   // barriers
   static constexpr int NBUF = sizeof(R) == 4 ? SG_COL_NBUF32 : 1;
   static constexpr int BYTES = NBUF * SLOT * (int)sizeof(cx<R>);
-  static constexpr int P0 = T >= 256 ? 1 : 256 / T;
-  static constexpr int PL = (65536 / BYTES) < 1 ? 1 : (65536 / BYTES);
+  // columns per workgroup: up to SG_COL_WG threads, within the LDS budget
+  static constexpr int WG = sizeof(R) == 4 ? SG_COL_WG32 : 256;
+  static constexpr int LB = WG > 256 ? kLdsBudget : 65536;
+  static constexpr int P0 = T >= WG ? 1 : WG / T;
+  static constexpr int PL = (LB / BYTES) < 1 ? 1 : (LB / BYTES);
   static constexpr int P = P0 < PL ? P0 : PL;
 };
 
@@ -598,18 +610,34 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
 #pragma unroll
       for (int e = 0; e < E; ++e) tv[i][e] = odd_entry<TO, N>((i & 1) ? ry : rx, t + e * T, i >> 1);
   }
+  // with four buffers the forward transforms alternate between buffers
+  // {0, 1} and {2, 3} (one barrier per exchange)
+  constexpr bool pp = (NBUF == 4) && SG_COL_PP;
   if (solve) {
     // y-solve of Eq. (z_system) on the complex row spectra, FP64, chunk of E per thread
     double2 d[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) d[e] = make_double2(8.0 * (double)a[e].x, 8.0 * (double)a[e].y);
-    tri_solve<E, T, double2>(d, t, *reinterpret_cast<tri_smem<double2, T>*>(lds));
+    if constexpr (pp) {
+      // the solve's LDS lies in buffer 0; the transpose goes through buffer
+      // 2, and the forward transform's first exchange (buffers 0 and 1)
+      // follows the transpose's barrier, so neither needs a barrier after it
+      tri_solve<E, T, double2, false>(d, t, *reinterpret_cast<tri_smem<double2, T>*>(lds));
+      cx<R>* tb = lds + 2 * LL;
 #pragma unroll
-    for (int e = 0; e < E; ++e) lds[pad(t * E + e)] = cx<R>{(R)d[e].x, (R)d[e].y};
-    __syncthreads();
+      for (int e = 0; e < E; ++e) tb[pad(t * E + e)] = cx<R>{(R)d[e].x, (R)d[e].y};
+      __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) a[e] = lds[pad(t + e * T)];
-    __syncthreads();
+      for (int e = 0; e < E; ++e) a[e] = tb[pad(t + e * T)];
+    } else {
+      tri_solve<E, T, double2>(d, t, *reinterpret_cast<tri_smem<double2, T>*>(lds));
+#pragma unroll
+      for (int e = 0; e < E; ++e) lds[pad(t * E + e)] = cx<R>{(R)d[e].x, (R)d[e].y};
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < E; ++e) a[e] = lds[pad(t + e * T)];
+      __syncthreads();
+    }
   }
 
   const bool packed = (c == 0);
@@ -632,7 +660,10 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
         f2[0][e] = fe[e];
         f2[1][e] = fo[e];
       }
-      fftn<false, N, T, 2>(f2, lds, LL, tw, t);
+      if constexpr (pp)
+        fftn_pp<false, N, T, 2>(f2, lds, LL, tw, t);
+      else
+        fftn<false, N, T, 2>(f2, lds, LL, tw, t);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         fe[e] = f2[0][e];
@@ -959,12 +990,19 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
   }
   using C = rowinv_cfg<R, M>;
   constexpr int E = C::E, T = C::T, LL = C::LL, NB = C::NB;
-  __shared__ cx<R> smem[C::G * LL * NB];
+  // per-row LDS stride, offset by two slots so that interleaved rows fall
+  // on different banks
+  constexpr int RS = LL * NB + (SG_RI_ILV ? 2 : 0);
+  __shared__ cx<R> smem[C::G * RS];
   const int G = blockDim.x / T;  // rows per workgroup
-  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  // SG_RI_ILV: the rows of a workgroup interleave across lanes, so that the
+  // lanes of one load cover whole segments of a V tile (rows of a tile are
+  // adjacent in memory)
+  const int g = SG_RI_ILV ? threadIdx.x % G : threadIdx.x / T;
+  const int t = SG_RI_ILV ? threadIdx.x / G : threadIdx.x % T;
   const int row = xcd_tile(blockIdx.x, gridDim.x) * G + g;
   const bool active = row < nrows;
-  cx<R>* lds = smem + g * LL * NB;
+  cx<R>* lds = smem + g * RS;
   const int jb = (active ? row : 0) / tj, jj = (active ? row : 0) % tj;
   cx<R> ve[E], vo[E];
   if constexpr (NB == 2) {
@@ -1592,8 +1630,8 @@ hipError_t sg_launch_col(int prec, int N, const void* X, void* V, int M, int tj,
 
 int sg_row_tile(int prec, int M, int N) {
   (void)M;
-  const int tj = prec == 0 ? SG_TJ64 : SG_TJ32;
-  return tj < N ? tj : N;
+  // a power of two that divides N (tiles never straddle the last row)
+  return pow2_div(N, prec == 0 ? SG_TJ64 : SG_TJ32);
 }
 
 #endif

@@ -15,7 +15,8 @@
 // with a zero carry; the true carry into a chunk is a geometric sum of the
 // neighbouring chunks' end values with ratio q = (-r)^CH, truncated after S
 // terms where |r|^(S*CH) < 1e-18 (|r| = 0.17, so S = 3 for CH = 8).  Three
-// workgroup barriers in all (the last one lets the caller reuse the LDS);
+// workgroup barriers in all (the last one, optional, lets the caller reuse
+// the LDS);
 // z_i is below 1e-19 of z_0 past i = 24, so the rank-one term touches only
 // the first 24 unknowns.
 #pragma once
@@ -80,7 +81,7 @@ struct tri_smem {
 // Solve tridiag(1,6,1) x = d on a line of CH*T unknowns; d (this thread's
 // CH values, chunk t) is overwritten with x.  Every thread of the workgroup
 // must call it (it holds workgroup barriers); each line passes its own LDS.
-template <int CH, int T, typename V>
+template <int CH, int T, typename V, bool TAIL = true>
 __device__ __forceinline__ void tri_solve(V* d, int t, tri_smem<V, T>& sm) {
   using K = tri_consts<CH, T>;
   constexpr K k{};
@@ -126,7 +127,9 @@ __device__ __forceinline__ void tri_solve(V* d, int t, tri_smem<V, T>& sm) {
     for (int i = 0; i < K::H; ++i)  // compile-time indices into z and d
       if (i / CH == t) d[i % CH] = d[i % CH] - vscale(a, k.z[i]);
   }
-  __syncthreads();  // the caller may reuse the LDS
+  // the caller may reuse the LDS after this barrier (TAIL); without it, the
+  // caller must pass a barrier of its own before writing over sm
+  if constexpr (TAIL) __syncthreads();
 }
 
 }  // namespace sg
