@@ -22,8 +22,11 @@
 
 // Launch-shape knobs (compile-time; elements per thread E and threads per
 // workgroup of each pass).  Defaults are the measured best on MI355X.
-#ifndef SG_RF_THREADS
-#define SG_RF_THREADS 512
+#ifndef SG_RF_THREADS32
+#define SG_RF_THREADS32 1024
+#endif
+#ifndef SG_RF_THREADS64
+#define SG_RF_THREADS64 512
 #endif
 #ifndef SG_RI_THREADS
 #define SG_RI_THREADS 256
@@ -311,7 +314,9 @@ struct rowfwd_cfg {
   static constexpr int TRI = (int)(sizeof(tri_smem<double, T>) / sizeof(cx<R>)) + 1;
   static constexpr int SLOT = LL > TRI ? LL : TRI;
   static constexpr int NB = (sizeof(R) == 4 && sizeof(In) == 4) ? SG_RF_NBUF32 : 1;  // exchange buffers per row
-  static constexpr int G0 = SG_RF_THREADS / T < 1 ? 1 : (SG_RF_THREADS / T < 16 ? SG_RF_THREADS / T : 16);
+  // rows per workgroup: more rows make longer segments of the transposed store
+  static constexpr int WG = sizeof(R) == 4 ? SG_RF_THREADS32 : SG_RF_THREADS64;
+  static constexpr int G0 = WG / T < 1 ? 1 : (WG / T < 16 ? WG / T : 16);
   static constexpr int GL = kLdsBudget / (NB * SLOT * (int)sizeof(cx<R>));
   static constexpr int G = (G0 < GL ? G0 : GL) < 1 ? 1 : (G0 < GL ? G0 : GL);
   // e-values per transposed-store chunk (2T bins per e, G rows)
