@@ -186,11 +186,14 @@ struct plan {
   static_assert(E % (R3 ? 3 : 1) == 0 && (R0 == 1 ? L2 == 1 : true), "elements per thread do not fit the radices");
 };
 
-// LDS padding against bank conflicts: one slot every 16 elements
-__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+// LDS padding against bank conflicts: one slot every 2^SG_LDS_PAD elements
+#ifndef SG_LDS_PAD
+#define SG_LDS_PAD 5
+#endif
+__device__ __forceinline__ int pad(int i) { return i + (i >> SG_LDS_PAD); }
 template <int L>
 struct lds_len {
-  static constexpr int value = L + L / 16;
+  static constexpr int value = L + (L >> SG_LDS_PAD);
 };
 
 // roots(i) = exp(-2 pi i * i / L) read from a table of the RB-th roots with

@@ -28,8 +28,11 @@
 #ifndef SG_RF_THREADS64
 #define SG_RF_THREADS64 512
 #endif
-#ifndef SG_RI_THREADS
-#define SG_RI_THREADS 256
+#ifndef SG_RI_THREADS32
+#define SG_RI_THREADS32 256
+#endif
+#ifndef SG_RI_THREADS64
+#define SG_RI_THREADS64 1024
 #endif
 #ifndef SG_RI_ILV
 #define SG_RI_ILV 0
@@ -977,7 +980,8 @@ struct rowinv_cfg {
   static constexpr int T = L / E;
   static constexpr int LL = lds_len<L>::value;
   static constexpr int NB = sizeof(R) == 4 ? SG_RI_NBUF32 : 1;  // exchange buffers per row
-  static constexpr int G0 = SG_RI_THREADS / T < 1 ? 1 : (SG_RI_THREADS / T < 16 ? SG_RI_THREADS / T : 16);
+  static constexpr int WG = sizeof(R) == 4 ? SG_RI_THREADS32 : SG_RI_THREADS64;
+  static constexpr int G0 = WG / T < 1 ? 1 : (WG / T < 16 ? WG / T : 16);
   static constexpr int GL = kLdsBudget / (NB * LL * (int)sizeof(cx<R>));
   static constexpr int G = (G0 < GL ? G0 : GL) < 1 ? 1 : (G0 < GL ? G0 : GL);
 };
