@@ -618,6 +618,11 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
 #pragma unroll
       for (int e = 0; e < E; ++e) tv[i][e] = odd_entry<TO, N>((i & 1) ? ry : rx, t + e * T, i >> 1);
   }
+  // phases exp(-i pi j / N) of the odd-bin transforms (used twice), loaded
+  // now so that their latency hides behind the solve
+  cx<R> w2n[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) w2n[e] = r2n[(unsigned)(t + e * T)];
   // with four buffers the forward transforms alternate between buffers
   // {0, 1} and {2, 3} (one barrier per exchange)
   constexpr bool pp = (NBUF == 4) && SG_COL_PP;
@@ -654,7 +659,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
   cx<R> fe[E], fo[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    fo[e] = cmul(a[e], r2n[(unsigned)(t + e * T)]);
+    fo[e] = cmul(a[e], w2n[e]);
     fe[e] = a[e];
   }
   cx<R> accx[E], accy[E];
@@ -700,7 +705,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     fftn<true, N, T, 4>(g4, lds, LL, tw, t);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const cx<R> w = r2n[(unsigned)(t + e * T)];  // conj -> exp(+i pi j / N)
+      const cx<R> w = w2n[e];  // conj -> exp(+i pi j / N)
       accx[e] = g4[0][e] + cmulc(g4[2][e], w);
       accy[e] = g4[1][e] + cmulc(g4[3][e], w);
     }
@@ -721,7 +726,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
           accx[e] = gx[e];
           accy[e] = gy[e];
         } else {
-          const cx<R> w = r2n[(unsigned)(t + e * T)];  // conj -> exp(+i pi j / N)
+          const cx<R> w = w2n[e];  // conj -> exp(+i pi j / N)
           accx[e] = accx[e] + cmulc(gx[e], w);
           accy[e] = accy[e] + cmulc(gy[e], w);
         }
@@ -747,7 +752,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
           if (half == 0) {
             acc[e] = g[e];
           } else {
-            const cx<R> w = r2n[(unsigned)(t + e * T)];  // conj -> exp(+i pi j / N)
+            const cx<R> w = w2n[e];  // conj -> exp(+i pi j / N)
             acc[e] = acc[e] + cmulc(g[e], w);
           }
         }
@@ -1013,7 +1018,7 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
   const bool active = row < nrows;
   cx<R>* lds = smem + g * RS;
   const int jb = (active ? row : 0) / tj, jj = (active ? row : 0) % tj;
-  cx<R> ve[E], vo[E];
+  cx<R> ve[E], vo[E], wr[E];
   if constexpr (NB == 2) {
     // both half-length inverses through the same stages
     cx<R> v2[2][E];
@@ -1023,6 +1028,10 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
 #pragma unroll
       for (int e = 0; e < E; ++e) v2[half][e] = base[(int64_t)(t + e * T) * tj];
     }
+    // phases of the odd half, loaded now so that their latency hides behind
+    // the transforms
+#pragma unroll
+    for (int e = 0; e < E; ++e) wr[e] = r2m[t + e * T];
     fftn<true, M, T, 2>(v2, lds, LL, tw, t);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -1043,7 +1052,7 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int n = t + e * T;
-      const cx<R> r = ve[e] + cmulc(vo[e], r2m[n]);
+      const cx<R> r = ve[e] + cmulc(vo[e], NB == 2 ? wr[e] : r2m[n]);
       fx[(int64_t)row * M + n] = (Out)r.x;
       fy[(int64_t)row * M + n] = (Out)r.y;
     }
