@@ -34,9 +34,6 @@
 #ifndef SG_RI_THREADS64
 #define SG_RI_THREADS64 1024
 #endif
-#ifndef SG_RI_ILV
-#define SG_RI_ILV 0
-#endif
 #ifndef SG_RI_E32
 #define SG_RI_E32 8
 #endif
@@ -76,22 +73,6 @@
 #endif
 #ifndef SG_RI_NBUF32
 #define SG_RI_NBUF32 2
-#endif
-// persistent FP32 column pass: workgroups per grid (0 = off) and the
-// smallest column length that uses it
-#ifndef SG_COL_PIPE
-#define SG_COL_PIPE 0
-#endif
-#ifndef SG_COL_PIPE_MIN_N
-#define SG_COL_PIPE_MIN_N 1024
-#endif
-// prefetch the next tile's column during the current one
-#ifndef SG_COL_PIPE_NEXT
-#define SG_COL_PIPE_NEXT 1
-#endif
-// load each half's spectrum entries ahead of the products
-#ifndef SG_COL_PIPE_SPEC
-#define SG_COL_PIPE_SPEC 1
 #endif
 #ifndef SG_RF_E64
 #define SG_RF_E64 8
@@ -785,192 +766,6 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
   }
 }
 
-// Persistent, software-pipelined form of k_col for FP32 (column pass B):
-// each workgroup keeps the stage twiddles in LDS for its lifetime and walks
-// a contiguous range of column tiles (consecutive tiles on one XCD, so the
-// tiles that share V's cache lines meet in one L2), loading the next tile's
-// row spectra and each half's spectrum entries ahead of the transforms that
-// need them.  Same arithmetic as k_col.
-template <typename TO, typename TC, int N>
-struct colp_ent {  // one spectrum entry as stored: odd k real (hi+lo), k = 2 complex
-  TO o;
-  TC c;
-};
-
-template <typename TO, typename TC, int N, int MODE>
-__device__ __forceinline__ void spec_prefetch(colp_ent<TO, TC, N>* ent, const TO* to, const TC* tc, int c, int half,
-                                              int t, int T, int E) {
-  for (int e = 0; e < E; ++e) {
-    const int qq = t + e * T;
-    if (MODE != 1) {
-      const TO* row = to + (int64_t)c * (N + 1) + (half ? N / 2 + 1 : 0);
-      const bool lo = half ? qq < N / 2 : qq <= N / 2;
-      ent[e].o = row[(unsigned)(lo ? qq : (half ? N - 1 - qq : N - qq))];
-    } else {
-      ent[e].c = (tc + (int64_t)c * (2 * N))[(unsigned)(half * N + qq)];
-    }
-  }
-}
-
-// product with a prefetched entry; odd k: the reflection q -> 2N - q of the
-// stored quarter table flips the sign by eps (x: +1, y: -1)
-template <typename TO, typename TC, int N, int MODE>
-__device__ __forceinline__ cx<float> spec_apply(cx<float> z, const colp_ent<TO, TC, N>& w, int half, int qq,
-                                                float eps) {
-  if (MODE != 1) {
-    const bool lo = half ? qq < N / 2 : qq <= N / 2;
-    const float sgn = lo ? 1.0f : eps;
-    const float h = w.o.x * sgn, l = w.o.y * sgn;
-    return {-(z.y * h + z.y * l), z.x * h + z.x * l};
-  }
-  const float4 q = w.c;
-  return {(z.x * q.x - z.y * q.z) + (z.x * q.y - z.y * q.w), (z.x * q.z + z.y * q.x) + (z.x * q.w + z.y * q.y)};
-}
-
-template <typename TO, typename TC, int N, int MODE>
-__global__ void __launch_bounds__((col_cfg<float, N>::P * col_cfg<float, N>::T))
-    SG_WPE(float, COL) k_col_pipe(const cx<float>* __restrict__ X, cx<float>* __restrict__ V, int M, int tj,
-                                  const TO* __restrict__ tox, const TO* __restrict__ toy, const TC* __restrict__ tcx,
-                                  const TC* __restrict__ tcy, const cx<float>* __restrict__ r2n,
-                                  const cx<float>* __restrict__ tw, const sg_bgrid* __restrict__ bg) {
-  using R = float;
-  constexpr int kind = MODE == 1 ? 1 : 0;
-  constexpr bool solve = MODE == 2;
-  if (bg) {
-    const sg_bgrid d = grid_desc(bg);
-    X = reinterpret_cast<const cx<R>*>(d.X);
-    V = reinterpret_cast<cx<R>*>(d.V);
-    if (kind == 0) {
-      tox = reinterpret_cast<const TO*>(d.tabx);
-      toy = reinterpret_cast<const TO*>(d.taby);
-    } else {
-      tcx = reinterpret_cast<const TC*>(d.tabx);
-      tcy = reinterpret_cast<const TC*>(d.taby);
-    }
-  }
-  using C = col_cfg<R, N>;
-  constexpr int E = C::E, T = C::T, LL = C::SLOT;
-  constexpr int TW = plan<N, E>::tw_size;
-  __shared__ cx<R> smem[C::P * LL * 2];
-  __shared__ cx<R> stw[TW > 0 ? TW : 1];
-  const int P = blockDim.x / T;
-  const int g = threadIdx.x / T, t = threadIdx.x % T;
-  cx<R>* lds = smem + g * LL * 2;
-  cx<R>* lds2 = lds + LL;
-  for (int i = threadIdx.x; i < TW; i += blockDim.x) stw[i] = tw[i];
-  __syncthreads();
-  // this workgroup's tiles: XCD x = blockIdx.x % 8 owns the contiguous range
-  // [x*nt/8, (x+1)*nt/8); its workgroups take every (gridDim.x/8)-th tile of it
-  const int nt = M / P;
-  int tile0, tile1, step;
-  if (gridDim.x % 8 == 0 && nt % 8 == 0) {
-    const int x = blockIdx.x % 8, per = gridDim.x / 8;
-    tile0 = x * (nt / 8) + blockIdx.x / 8;
-    tile1 = (x + 1) * (nt / 8);
-    step = per;
-  } else {
-    tile0 = blockIdx.x;
-    tile1 = nt;
-    step = gridDim.x;
-  }
-  cx<R> an[E];  // next tile's column
-  auto load_col = [&](int tile) {
-    const cx<R>* col = X + (int64_t)(tile * P + g) * N;
-#pragma unroll
-    for (int e = 0; e < E; ++e) an[e] = col[solve ? (unsigned)(t * E + e) : (unsigned)(t + e * T)];
-  };
-  if (tile0 < tile1) load_col(tile0);
-  for (int tile = tile0; tile < tile1; tile += step) {
-    if (!SG_COL_PIPE_NEXT) load_col(tile);
-    const int c0 = tile * P, c = c0 + g;
-    const bool packed = (c == 0), exch = (c0 == 0);
-    cx<R> a[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) a[e] = an[e];
-    // spectrum entries of the even half, then the next tile's column, in flight
-    // during the solve and the forward transforms
-    colp_ent<TO, TC, N> wx[SG_COL_PIPE_SPEC ? E : 1], wy[SG_COL_PIPE_SPEC ? E : 1];
-    if (SG_COL_PIPE_SPEC) {
-      spec_prefetch<TO, TC, N, MODE>(wx, tox, tcx, c, 0, t, T, E);
-      spec_prefetch<TO, TC, N, MODE>(wy, toy, tcy, c, 0, t, T, E);
-    }
-    if (SG_COL_PIPE_NEXT && tile + step < tile1) load_col(tile + step);
-    if (solve) {
-      double2 d[E];
-#pragma unroll
-      for (int e = 0; e < E; ++e) d[e] = make_double2(8.0 * (double)a[e].x, 8.0 * (double)a[e].y);
-      tri_solve<E, T, double2>(d, t, *reinterpret_cast<tri_smem<double2, T>*>(lds));
-#pragma unroll
-      for (int e = 0; e < E; ++e) lds[pad(t * E + e)] = cx<R>{(R)d[e].x, (R)d[e].y};
-      __syncthreads();
-#pragma unroll
-      for (int e = 0; e < E; ++e) a[e] = lds[pad(t + e * T)];
-      __syncthreads();
-    }
-    cx<R> fe[E], fo[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      fo[e] = cmul(a[e], r2n[(unsigned)(t + e * T)]);
-      fe[e] = a[e];
-    }
-    fft2<false, N, T>(fe, fo, lds, lds2, stw, t);
-    cx<R> accx[E], accy[E];
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      const cx<R>* f = half ? fo : fe;
-      cx<R> gx[E], gy[E];
-      if (exch || !SG_COL_PIPE_SPEC) {
-        // generic products (always for the workgroup of the packed column 0)
-        col_product<R, TO, TC, N, E, T>(f, gx, half, true, packed, lds, kind, tox, tcx, (R)1, c, M, t);
-        col_product<R, TO, TC, N, E, T>(f, gy, half, true, packed, lds, kind, toy, tcy, (R)-1, c, M, t);
-      } else {
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          gx[e] = spec_apply<TO, TC, N, MODE>(f[e], wx[e], half, t + e * T, 1.0f);
-          gy[e] = spec_apply<TO, TC, N, MODE>(f[e], wy[e], half, t + e * T, -1.0f);
-        }
-      }
-      if (SG_COL_PIPE_SPEC && half == 0) {  // odd half's entries, in flight during the even inverses
-        spec_prefetch<TO, TC, N, MODE>(wx, tox, tcx, c, 1, t, T, E);
-        spec_prefetch<TO, TC, N, MODE>(wy, toy, tcy, c, 1, t, T, E);
-      }
-      fft2<true, N, T>(gx, gy, lds, lds2, stw, t);
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        if (half == 0) {
-          accx[e] = gx[e];
-          accy[e] = gy[e];
-        } else {
-          const cx<R> w = r2n[(unsigned)(t + e * T)];
-          accx[e] = accx[e] + cmulc(gx[e], w);
-          accy[e] = accy[e] + cmulc(gy[e], w);
-        }
-      }
-    }
-    const int pa = c, pb = packed ? M : 2 * M - c;
-    cx<R>* va = V + (int64_t)(pa & 1) * M * tj + (int64_t)(pa >> 1) * tj;
-    cx<R>* vb = V + (int64_t)(pb & 1) * M * tj + (int64_t)(pb >> 1) * tj;
-    const int64_t jstride = (int64_t)2 * M * tj;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int j = t + e * T;
-      const cx<R> yx = accx[e], yy = accy[e];
-      cx<R> v1, v2;
-      if (packed) {
-        v1 = cx<R>{yx.x, yy.x};
-        v2 = cx<R>{yx.y, yy.y};
-      } else {
-        v1 = cx<R>{yx.x - yy.y, yx.y + yy.x};
-        v2 = cx<R>{yx.x + yy.y, yy.x - yx.y};
-      }
-      const int64_t o = (int64_t)(j / tj) * jstride + (j % tj);
-      va[o] = v1;
-      vb[o] = v2;
-    }
-    __syncthreads();  // the next tile reuses the exchange buffers
-  }
-}
-
 // ---------------------------------------------------------------- pass C --
 // Rows j of the combined spectrum V: v = IFFT_2M(V) cropped to n < M via its
 // even and odd input bins (two inverse FFTs of length M); Fx = Re, Fy = Im.
@@ -1004,19 +799,12 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
   }
   using C = rowinv_cfg<R, M>;
   constexpr int E = C::E, T = C::T, LL = C::LL, NB = C::NB;
-  // per-row LDS stride, offset by two slots so that interleaved rows fall
-  // on different banks
-  constexpr int RS = LL * NB + (SG_RI_ILV ? 2 : 0);
-  __shared__ cx<R> smem[C::G * RS];
+  __shared__ cx<R> smem[C::G * LL * NB];
   const int G = blockDim.x / T;  // rows per workgroup
-  // SG_RI_ILV: the rows of a workgroup interleave across lanes, so that the
-  // lanes of one load cover whole segments of a V tile (rows of a tile are
-  // adjacent in memory)
-  const int g = SG_RI_ILV ? threadIdx.x % G : threadIdx.x / T;
-  const int t = SG_RI_ILV ? threadIdx.x / G : threadIdx.x % T;
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int row = xcd_tile(blockIdx.x, gridDim.x) * G + g;
   const bool active = row < nrows;
-  cx<R>* lds = smem + g * RS;
+  cx<R>* lds = smem + g * LL * NB;
   const int jb = (active ? row : 0) / tj, jj = (active ? row : 0) % tj;
   cx<R> ve[E], vo[E], wr[E];
   if constexpr (NB == 2) {
@@ -1484,31 +1272,6 @@ static hipError_t launch_col_t(const cx<R>* X, cx<R>* V, int M, int tj, const vo
   using TO = typename tabs<R>::odd;
   using TC = typename tabs<R>::cplx;
   const int P = pow2_div(M, (tile > 0 && tile <= C::P) ? tile : C::P);
-  if constexpr (sizeof(R) == 4 && SG_COL_PIPE > 0) {
-    if (N >= SG_COL_PIPE_MIN_N) {
-      // persistent: at most SG_COL_PIPE workgroups per grid walk the tiles
-      const int nt = M / P;
-      const dim3 grid(nt < SG_COL_PIPE ? nt : SG_COL_PIPE, bg ? ngrids : 1);
-      const TO* tox = kind == 0 ? (const TO*)tx : nullptr;
-      const TO* toy = kind == 0 ? (const TO*)ty : nullptr;
-      const TC* tcx = kind == 1 ? (const TC*)tx : nullptr;
-      const TC* tcy = kind == 1 ? (const TC*)ty : nullptr;
-      const cx<float>* Xf = (const cx<float>*)X;
-      cx<float>* Vf = (cx<float>*)V;
-      const cx<float>* r2f = (const cx<float>*)r2n;
-      const cx<float>* twf = (const cx<float>*)tw;
-      if (kind == 1)
-        hipLaunchKernelGGL((k_col_pipe<TO, TC, N, 1>), grid, dim3(P * C::T), 0, st, Xf, Vf, M, tj, tox, toy, tcx, tcy,
-                           r2f, twf, bg);
-      else if (solve)
-        hipLaunchKernelGGL((k_col_pipe<TO, TC, N, 2>), grid, dim3(P * C::T), 0, st, Xf, Vf, M, tj, tox, toy, tcx, tcy,
-                           r2f, twf, bg);
-      else
-        hipLaunchKernelGGL((k_col_pipe<TO, TC, N, 0>), grid, dim3(P * C::T), 0, st, Xf, Vf, M, tj, tox, toy, tcx, tcy,
-                           r2f, twf, bg);
-      return hipGetLastError();
-    }
-  }
   const dim3 grid(M / P, bg ? ngrids : 1);
   const TO* tox = kind == 0 ? (const TO*)tx : nullptr;
   const TO* toy = kind == 0 ? (const TO*)ty : nullptr;
