@@ -327,14 +327,18 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
   const bool active = row < nrows;
   cx<R>* lds = smem + g * SLOT * NB;
   cx<R>* lds2 = lds + (NB - 1) * SLOT;
+  // loads are unconditional (a row past nrows reads row 0 and is masked
+  // afterwards), so that they issue together rather than one at a time
+  // behind a branch each
   const In* s = src + (int64_t)(active ? row : 0) * src_ld;
+  const double msk = active ? 8.0 : 0.0;
   cx<R> ze[E], zo[E];
   if (solve) {
     // chunk of 2E reals per thread: x-solve of Eq. (C_system), FP64
     constexpr int CH = 2 * E;
     double d[CH];
 #pragma unroll
-    for (int e = 0; e < CH; ++e) d[e] = active ? 8.0 * (double)s[t * CH + e] : 0.0;
+    for (int e = 0; e < CH; ++e) d[e] = msk * (double)s[t * CH + e];
     tri_solve<CH, T, double>(d, t, *reinterpret_cast<tri_smem<double, T>*>(lds));
 #pragma unroll
     for (int e = 0; e < E; ++e) lds[pad(t * E + e)] = cx<R>{(R)d[2 * e], (R)d[2 * e + 1]};
@@ -343,22 +347,25 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
     for (int e = 0; e < E; ++e) ze[e] = lds[pad(t + e * T)];
     __syncthreads();
   } else {
+    const R m1 = active ? (R)1 : (R)0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int n = t + e * T;
-      ze[e] = active ? cx<R>{(R)s[2 * n], (R)s[2 * n + 1]} : cx<R>{0, 0};
+      ze[e] = cx<R>{m1 * (R)s[2 * n], m1 * (R)s[2 * n + 1]};
     }
   }
+  if (full) {  // rows of 2M values (plan time): fold the upper half in
+    const R m1 = active ? (R)1 : (R)0;
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int n = t + e * T;
-    cx<R> lo = ze[e];
-    if (full) {
-      const cx<R> hi = active ? cx<R>{(R)s[2 * (n + L)], (R)s[2 * (n + L) + 1]} : cx<R>{0, 0};
+    for (int e = 0; e < E; ++e) {
+      const int n = t + e * T;
+      const cx<R> lo = ze[e], hi{m1 * (R)s[2 * (n + L)], m1 * (R)s[2 * (n + L) + 1]};
       ze[e] = lo + hi;
-      lo = lo - hi;
+      zo[e] = cmul(lo - hi, r2m[2 * n]);  // w_M^n
     }
-    zo[e] = cmul(lo, r2m[2 * n]);  // w_M^n
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) zo[e] = cmul(ze[e], r2m[2 * (t + e * T)]);  // w_M^n
   }
   cx<R> xe[E];
   if constexpr (NB == 2) {
@@ -859,9 +866,19 @@ template <typename R, typename TO, typename TC, int N, int E, int T>
 __device__ __forceinline__ void col_products_adj(const cx<R>* fx, const cx<R>* fy, cx<R>* h, int half, bool exch,
                                                  bool packed, cx<R>* lds, int kind, const TO* tox, const TO* toy,
                                                  const TC* tcx, const TC* tcy, int c, int M, int t) {
+  if (!exch) {
+    // no packed column in this workgroup: independent loads, no branches
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int qq = t + e * T;
+      h[e] = spec_mul<R, TO, TC, N, true>(fx[e], kind, tox, tcx, c, qq, half, (R)1) +
+             spec_mul<R, TO, TC, N, true>(fy[e], kind, toy, tcy, c, qq, half, (R)-1);
+    }
+    return;
+  }
   // packed column: each spectrum U carries bins p = 0 and p = M; split both
   cx<R> umx[E], umy[E];
-  if (exch) {
+  {
 #pragma unroll
     for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = fx[e];
     __syncthreads();
@@ -1186,8 +1203,11 @@ __global__ void __launch_bounds__((coeff_cfg<M>::G * coeff_cfg<M>::T))
   const int row = blockIdx.x * C::G + g;
   const bool active = row < nrows;
   double d[CH];
+  // unconditional loads (row 0 stands in for rows past nrows), masked
+  const R* s = src + (int64_t)(active ? row : 0) * M + t * CH;
+  const double msk = active ? 8.0 : 0.0;
 #pragma unroll
-  for (int e = 0; e < CH; ++e) d[e] = active ? 8.0 * (double)src[(int64_t)row * M + t * CH + e] : 0.0;
+  for (int e = 0; e < CH; ++e) d[e] = msk * (double)s[e];
   tri_solve<CH, T, double>(d, t, *reinterpret_cast<tri_smem<double, T>*>(smem + g * C::SLOT));
   if (active) {
 #pragma unroll
