@@ -12,8 +12,9 @@ adjoint's own rounding).
 * autograd gradient of L = sum |F - F_target|^2 against the oracle at 256^2;
 * central finite differences of L on the FP64 path at 256 x 128 (L is
   quadratic in sigma, so the differences are exact up to rounding);
-* 8192^2 plus four 2048^2 grids in one plan: FP32-split adjoint against the
-  FP64 adjoint, and finite differences at 64 seeded cells of the 8192^2 grid.
+* 4096^2 plus four 2048^2 grids in one plan: FP32-split gradient against the
+  FP64 gradient, and finite differences at 64 seeded cells of the 4096^2
+  grid (the 8192^2 form of this case is skipped: the library refuses 8192).
 """
 import numpy as np
 import pytest
@@ -162,24 +163,27 @@ def test_gradient_central_differences_fp64():
     assert err <= 1e-8, err
 
 
-@_FAULT_SKIP
-def test_differentiation_at_scale_multigrid():
-    """8192^2 with four 2048^2 grids alongside, in one plan (packed buffers)."""
+def _at_scale(grids):
+    """Config-5 style check on one plan of several grids (the first one
+    large): FP64 gradient of L = sum |F - F_target|^2 against central
+    differences at 64 seeded cells of the first grid (exact for a quadratic
+    L), and the FP32-split autograd gradient against the FP64 one per grid
+    (bar R10)."""
     sg = _sg()
     import torch
-    k = 3
-    grids = [(8192, 8192, -1.0, 1.0, -1.0, 1.0, k)] + [(2048, 2048, -1.0, 1.0, -1.0, 1.0, k)] * 4
+    k = grids[0][6]
     sig_parts, tgt_parts = [], []
     for gi, g in enumerate(grids):
-        s, t = _loss_setup(g[0], k, seed=5 + gi)
-        sig_parts.append(s.ravel())
-        tgt_parts.append(t.ravel())
-    sigma = np.concatenate(sig_parts)
-    tsig = np.concatenate(tgt_parts)
+        xs, ys = oracle.sample_lattice(k, g[0], g[1])
+        params = workloads.clump_params(5 + gi, 64)
+        sig_parts.append(workloads.clump_sigma_torch(params, xs, ys).reshape(-1))
+        tgt_parts.append(workloads.clump_sigma_torch(workloads.perturb_clumps(params, 55), xs, ys).reshape(-1))
+    s64 = torch.cat(sig_parts)
+    tsig = torch.cat(tgt_parts)
+    del sig_parts, tgt_parts
     p64 = sg.Plan(grids, sg.SG_FP64)
     try:
-        s64 = to_dev(sigma, torch.float64)
-        tgt = p64.forces(to_dev(tsig, torch.float64))
+        tgt = [t.clone() for t in p64.forces(tsig)]
         fx, fy = p64.forces(s64)
         g64 = p64.adjoint(2 * (fx - tgt[0]), 2 * (fy - tgt[1]))
         amps = []
@@ -188,8 +192,8 @@ def test_differentiation_at_scale_multigrid():
             fmax = max(fx[a:b].abs().max().item(), fy[a:b].abs().max().item())
             rmax = max((fx[a:b] - tgt[0][a:b]).abs().max().item(), (fy[a:b] - tgt[1][a:b]).abs().max().item())
             amps.append(fmax / rmax)
-        # finite differences on the 8192^2 grid (offset 0), exact for a quadratic loss
-        cells = workloads.sample_cells(555, 8192, 8192, 64)
+        # finite differences on the first grid (offset 0), exact for a quadratic loss
+        cells = workloads.sample_cells(555, grids[0][0], grids[0][1], 64)
         fd_err = _fd_check(p64, s64, tgt, g64.cpu().numpy(), cells, 1e-2)
         tgt32 = (tgt[0].float(), tgt[1].float())
         g64h = g64.cpu().numpy()
@@ -198,7 +202,7 @@ def test_differentiation_at_scale_multigrid():
     assert fd_err <= 1e-6, fd_err
     p32 = sg.Plan(grids, sg.SG_FP32_SPLIT)
     try:
-        s32 = to_dev(sigma, torch.float32).requires_grad_(True)
+        s32 = s64.float().requires_grad_(True)
         fx, fy = sg.ThinDiskForces.apply(s32, p32)
         loss = ((fx - tgt32[0]) ** 2).sum() + ((fy - tgt32[1]) ** 2).sum()
         loss.backward()
@@ -211,6 +215,18 @@ def test_differentiation_at_scale_multigrid():
         a, b = offs[gi], offs[gi + 1]
         err = np.abs(g32[a:b] - g64h[a:b]).max() / np.abs(g64h[a:b]).max()
         assert err <= 1e-6 * amps[gi] + 1e-6, (gi, err, amps[gi])
+
+
+def test_differentiation_at_scale_multigrid_4096():
+    """4096^2 (the largest supported size) with four 2048^2 grids alongside,
+    in one plan (packed buffers)."""
+    _at_scale([(4096, 4096, -1.0, 1.0, -1.0, 1.0, 3)] + [(2048, 2048, -1.0, 1.0, -1.0, 1.0, 3)] * 4)
+
+
+@_FAULT_SKIP
+def test_differentiation_at_scale_multigrid():
+    """8192^2 with four 2048^2 grids alongside, in one plan (packed buffers)."""
+    _at_scale([(8192, 8192, -1.0, 1.0, -1.0, 1.0, 3)] + [(2048, 2048, -1.0, 1.0, -1.0, 1.0, 3)] * 4)
 
 
 def test_autograd_multigrid_plan_equals_single_plans():
