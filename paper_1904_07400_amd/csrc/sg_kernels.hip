@@ -536,10 +536,12 @@ __device__ __forceinline__ void col_product(const cx<R>* f, cx<R>* g, int half, 
 #pragma unroll
   for (int e = 0; e < E; ++e) lds[pad(t + e * T)] = f[e];
   __syncthreads();
+  // one branch around each loop (uniform per column group), so that the
+  // loads of a loop issue together
+  if (packed) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int qq = t + e * T;
-    if (packed) {
+    for (int e = 0; e < E; ++e) {
+      const int qq = t + e * T;
       const int qm = half == 0 ? (qq == 0 ? 0 : N - qq) : (N - 1 - qq);
       const cx<R> u = f[e], um = conj(lds[pad(qm)]);
       const cx<R> c0v{(R)0.5 * (u.x + um.x), (R)0.5 * (u.y + um.y)};
@@ -547,9 +549,10 @@ __device__ __forceinline__ void col_product(const cx<R>* f, cx<R>* g, int half, 
       const cx<R> w0 = spec_mul<R, TO, TC, N>(c0v, kind, to, tc, 0, qq, half, eps);
       const cx<R> wm = spec_mul<R, TO, TC, N>(cmv, kind, to, tc, M, qq, half, eps);
       g[e] = cx<R>{w0.x - wm.y, w0.y + wm.x};
-    } else {
-      g[e] = spec_mul<R, TO, TC, N>(f[e], kind, to, tc, c, qq, half, eps);
     }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) g[e] = spec_mul<R, TO, TC, N>(f[e], kind, to, tc, c, t + e * T, half, eps);
   }
   __syncthreads();
 }
