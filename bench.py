@@ -245,6 +245,29 @@ def batch_bench(sg, torch, steps, warmup, count=256):
             "bit_identical": same, "rel_err_vs_fp64_worst_grid": err}
 
 
+def aniso_bench(sg, torch, k, steps, warmup):
+    """Non-square cells on a rectangular domain: 4096 x 2048 cells on
+    [-2,2] x [-0.5,0.5] (dx = 2 dy), the same clump recipe, FP32-split timed
+    and checked against FP64."""
+    import numpy as np
+    import workloads
+    M, N = 4096, 2048
+    grid = (M, N, -2.0, 2.0, -0.5, 0.5, k)
+    hx, hy = 4.0 / M, 1.0 / N
+    off = 0.5 if k % 2 == 1 else 1.0  # cell centres (odd k) or vertices x0 + (i+1) dx (k = 2)
+    xs = -2.0 + hx * (off + np.arange(M))
+    ys = -0.5 + hy * (off + np.arange(N))
+    sigma = workloads.clump_sigma(workloads.clump_params(2, 32), xs, ys)
+    ms64, _, _, (gx, gy) = time_plan(sg, torch, grid, sg.SG_FP64, sigma, steps, warmup)
+    ms32, pass32, _, (fx, fy) = time_plan(sg, torch, grid, sg.SG_FP32_SPLIT, sigma, steps, warmup)
+    scale = max(np.abs(gx).max(), np.abs(gy).max())
+    err = max(np.abs(fx - gx).max(), np.abs(fy - gy).max()) / scale
+    return {"workload": f"{M}x{N} cells on [-2,2]x[-0.5,0.5] (dx = 2 dy), k={k}, 32 seeded clumps x taper",
+            "value": M * N / (ms32 * 1e-3), "unit": "cells/s", "ms_per_step": round(ms32, 4),
+            "pass_ms": [round(x, 4) for x in pass32], "fp64_ms_per_step": round(ms64, 4),
+            "rel_err_vs_fp64": err, "meets_1e-6": bool(err <= 1e-6)}
+
+
 def cpu_baseline(n, k, sigma_np, sample):
     """The oracle (direct O(N^4) FP64 sum, OpenMP) on a bounded sample of cells."""
     import numpy as np
@@ -292,6 +315,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-disks measurement")
     ap.add_argument("--batch-only", action="store_true", help="only the batched-disks measurement")
+    ap.add_argument("--no-aniso", action="store_true", help="skip the anisotropic-cell measurement")
     ap.add_argument("--prec", choices=["both", "fp32", "fp64"], default="both",
                     help="both (default, the metric) or one path only (profiling)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -387,6 +411,8 @@ def main():
     }
     if not args.no_batch:
         line["batch"] = batch_bench(sg, torch, max(args.steps // 2, 3), 2)
+    if not args.no_aniso:
+        line["anisotropic"] = aniso_bench(sg, torch, k, max(args.steps // 2, 3), 2)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(n, k, sigma, args.cpu_sample)
     print(json.dumps(line), flush=True)

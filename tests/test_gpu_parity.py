@@ -149,6 +149,34 @@ def test_forces_full_size_sparse_impulses(k, n):
         assert err <= tol, (prec, err)
 
 
+ANISO = [(k, M, N, dom) for k in (1, 2, 3)
+         for (M, N, dom) in ((2048, 2048, (-2.0, 2.0, -1.0, 1.0)), (4096, 1024, (-1.0, 1.0, -1.0, 1.0)),
+                             (1536, 768, (-1.0, 1.0, -0.25, 0.25)))]
+
+
+@pytest.mark.parametrize("k,M,N,dom", ANISO, ids=[f"k{c[0]}-{c[1]}x{c[2]}-dx{(c[3][1]-c[3][0])/c[1]/((c[3][3]-c[3][2])/c[2]):g}dy"
+                                                 for c in ANISO])
+def test_forces_anisotropic_full_size(k, M, N, dom):
+    """Non-square cells at full size on rectangular domains (dx = 2 dy and
+    dx = dy / 4, for 2^a and 3 * 2^a sizes): seeded impulses, the oracle's
+    exact superposition at sampled cells and around every impulse."""
+    sg = _sg()
+    hx, hy = (dom[1] - dom[0]) / M, (dom[3] - dom[2]) / N
+    si, sj, sc = workloads.sparse_coeffs(300 + k, M, N, 12)
+    C = np.zeros((N, M))
+    np.add.at(C, (sj, si), sc)
+    sigma = oracle.bspline_apply(C, k)
+    near = [int(min(max(b + db, 0), N - 1)) * M + int(min(max(a + da, 0), M - 1))
+            for a, b in zip(si, sj) for da in (-1, 0, 1) for db in (-1, 0, 1)]
+    cells = workloads.sample_cells(400 + k, M, N, 200, extra=near)
+    rx, ry = oracle.forces_sparse(k, hx, hy, M, si, sj, sc, cells)
+    scale = max(np.abs(rx).max(), np.abs(ry).max())
+    for prec, tol in ((sg.SG_FP64, FP64_TOL), (sg.SG_FP32_SPLIT, FP32_TOL)):
+        gx, gy = run_forces((M, N, *dom, k), prec, sigma)
+        err = max(np.abs(gx.ravel()[cells] - rx).max(), np.abs(gy.ravel()[cells] - ry).max()) / scale
+        assert err <= tol, (prec, err)
+
+
 def test_forces_deterministic_and_linear():
     sg = _sg()
     import torch
