@@ -305,10 +305,6 @@ __device__ __forceinline__ void fft_stages(cx<R>* v, cx<R>* lds, const cx<R>* __
 template <bool INV, int L, int T, typename R>
 __device__ __forceinline__ void fft(cx<R>* v, cx<R>* lds, const cx<R>* __restrict__ tw, int t) {
   static_assert(L % T == 0, "L must be a multiple of T");
-#ifdef SG_FFT_FENCE
-  // keep the twiddle loads inside this transform (no hoisting across calls)
-  __asm__ volatile("" ::: "memory");
-#endif
   stage_tw<L, T, 0, R> s0;  // the first stage has no twiddles
   fft_stages<INV, L, T, 0>(v, lds, tw, s0, t);
 }
