@@ -11,7 +11,9 @@ Everything here is plain FP64 on the CPU and uses no FFT:
 
 * ``sample_lattice``     - where sigma is sampled for order k (Sec. 2.2, Sec. 2.3)
 * ``bspline_coeffs``     - sigma -> C by the two tridiagonal systems of
-                           Eqs. (z_system) and (C_system), Thomas algorithm
+                           Eqs. (z_system) and (C_system), Thomas algorithm;
+                           k = 4, 5 by the banded systems of the same
+                           construction (LAPACK banded LU)
 * ``weights``            - w^x, w^y of Eq. (eqnwB) by quadrature of their
                            defining integral (C code, ``csrc/sg_oracle.c``)
 * ``forces``             - F = C * w by direct summation, Eq. (eqnF)
@@ -21,14 +23,14 @@ Everything here is plain FP64 on the CPU and uses no FFT:
 * ``antiderivative``     - the closed forms of Appendix A and Eq. (intF) (mpmath)
 
 Where the paper is silent or ambiguous the oracle takes these readings: the
-k = 2 splines are centred on the vertices x0 + i dx and sampled there; the
-k = 3 labels are shifted so that C_i is centred on cell i; the weight
+k = 2 and k = 4 splines are centred on the vertices x0 + i dx and sampled
+there; the k = 3 and k = 5 labels are shifted so that C_i is centred on cell i; the weight
 integral over the piece holding the singular point is a principal value;
 the error norms are weighted by the cell area; G = 1 and the force is
 attractive.
 """
 from .core import (  # noqa: F401
-    sample_lattice, cell_centres, thomas, bspline_coeffs, bspline_apply, bspline_value,
+    sample_lattice, cell_centres, thomas, banded_solve, STENCIL, bspline_coeffs, bspline_apply, bspline_value,
     weights, weights_at, forces, forces_from_coeffs, forces_sparse, forces_adjoint,
     coeffs_transpose_solve, disk_force_radial, error_norms, accuracy_order,
     antiderivative, antiderivative_intF, build,

@@ -26,9 +26,10 @@ def sample_lattice(k: int, M: int, N: int, domain=(-1.0, 1.0, -1.0, 1.0)):
     """Points where sigma must be sampled so that C can be obtained from it.
 
     Odd k: the cell centres (Sec. 2.3, interpolation condition Eq. (eqnSigmaB)).
-    k = 2: the spline attached to C_i' spans x_{i'-1/2} .. x_{i'+3/2} (Case 2), so
-    it peaks at the vertex x_{i'+1/2} = L + i' dx, i' = 1..M, and C = sigma
-    there (the "C = sigma for k = 1, 2" remark of Sec. 2.3).
+    Even k: the spline attached to C_i' is centred on the vertex
+    x_{i'+1/2} = L + i' dx, i' = 1..M (k = 2 spans x_{i'-1/2} .. x_{i'+3/2},
+    Case 2, and C = sigma there by the "C = sigma for k = 1, 2" remark of
+    Sec. 2.3; k = 4 spans x_{i'-3/2} .. x_{i'+5/2}).
     """
     x0, x1, y0, y1 = domain
     hx, hy = (x1 - x0) / M, (y1 - y0) / N
@@ -67,6 +68,33 @@ def thomas(a: float, b: float, c: float, d: np.ndarray, axis: int) -> np.ndarray
     return np.moveaxis(x, 0, axis)
 
 
+# Orders above 3 (the extension the end of Sec. 2.3 and Case 3 of Sec. 2.2
+# state): the interpolation condition of Eq. (sigmaW) with the order-k
+# spline in place of the quadratic one.  Per axis, sigma at a sample point is
+# the sum of the coefficients of the splines that cover it, each times that
+# spline's value there: the uniform cubic at its centre and one cell away
+# (4/6, 1/6), the uniform quartic at its centre, one and two cells away
+# (230/384, 76/384, 1/384).  With C = 0 outside the grid, as after
+# Eq. (C_system), each axis is a symmetric banded Toeplitz system.
+STENCIL = {4: (1.0 / 6, 4.0 / 6, 1.0 / 6),
+           5: (1.0 / 384, 76.0 / 384, 230.0 / 384, 76.0 / 384, 1.0 / 384)}
+
+
+def banded_solve(stencil, d: np.ndarray, axis: int) -> np.ndarray:
+    """Solve the Toeplitz system with the symmetric ``stencil`` (x = 0 outside
+    the line) along ``axis`` of ``d`` for every line, by LAPACK's banded LU
+    (scipy.linalg.solve_banded)."""
+    from scipy.linalg import solve_banded
+    h = len(stencil) // 2
+    d = np.moveaxis(np.array(d, dtype=np.float64, copy=True), axis, 0)
+    n = d.shape[0]
+    ab = np.zeros((2 * h + 1, n))
+    for r in range(2 * h + 1):
+        ab[r, :] = stencil[r]
+    x = solve_banded((h, h), ab, d.reshape(n, -1)).reshape(d.shape)
+    return np.moveaxis(x, 0, axis)
+
+
 def bspline_coeffs(sigma: np.ndarray, k: int) -> np.ndarray:
     """sigma -> C (Sec. 2.3).
 
@@ -79,8 +107,10 @@ def bspline_coeffs(sigma: np.ndarray, k: int) -> np.ndarray:
     s = np.asarray(sigma, dtype=np.float64)
     if k in (1, 2):
         return s.copy()
+    if k in STENCIL:  # k = 4, 5: along j, then along i
+        return banded_solve(STENCIL[k], banded_solve(STENCIL[k], s, axis=0), axis=1)
     if k != 3:
-        raise ValueError("oracle implements k = 1, 2, 3")
+        raise ValueError("oracle implements k = 1..5")
     z = thomas(1.0, 6.0, 1.0, s, axis=0)              # along j (rows of the [N][M] array)
     return thomas(1.0 / 64, 6.0 / 64, 1.0 / 64, z, axis=1)   # along i
 
@@ -91,6 +121,16 @@ def bspline_apply(C: np.ndarray, k: int) -> np.ndarray:
     C = np.asarray(C, dtype=np.float64)
     if k in (1, 2):
         return C.copy()
+    if k in STENCIL:
+        st = STENCIL[k]
+        h = len(st) // 2
+        P = np.zeros((C.shape[0] + 2 * h, C.shape[1] + 2 * h))
+        P[h:-h, h:-h] = C
+        out = np.zeros_like(C)
+        for dj in range(2 * h + 1):
+            for di in range(2 * h + 1):
+                out += st[dj] * st[di] * P[dj:dj + C.shape[0], di:di + C.shape[1]]
+        return out
     P = np.zeros((C.shape[0] + 2, C.shape[1] + 2))
     P[1:-1, 1:-1] = C
     Wm = np.array([[1, 6, 1], [6, 36, 6], [1, 6, 1]], dtype=np.float64) / 64.0
@@ -103,7 +143,8 @@ def bspline_apply(C: np.ndarray, k: int) -> np.ndarray:
 
 def coeffs_transpose_solve(g: np.ndarray, k: int) -> np.ndarray:
     """Transpose of sigma -> C.  The two matrices of Eqs. (z_system) and
-    (C_system) are symmetric, so the transpose is the same two solves."""
+    (C_system) are symmetric (so are the banded ones of k = 4, 5), so the
+    transpose is the same two solves."""
     return bspline_coeffs(g, k)
 
 

@@ -4,11 +4,13 @@
 * the explicit B-splines of Eqs. (Bspline2)/(Bspline3) and the centre values
   of Eq. (weight_matrix) / the Fig. 1 caption (golden file);
 * the Thomas solve against a dense solve, and against the forward stencil of
-  Eq. (sigmaW);
+  Eq. (sigmaW); for k = 4, 5 the stencils against the truncated-power form
+  and the Cox-de Boor recursion, the spline sum at the sample points, and
+  the banded solve against a dense solve;
 * the weights: exact k = 1 closed form (Appendix A, (alpha,beta) = (1,0)),
-  an adaptive library quadrature on every piece for k = 2, 3, the origin
-  piece against the closed forms of Appendix A, symmetries, far-field
-  expansion;
+  an adaptive library quadrature on every piece for k = 2..5, the origin
+  piece against the closed forms of Appendix A and Eq. (intF), symmetries,
+  far-field expansion;
 * the direct sum: brute-force principal-value quadrature of the force
   integral Eq. (Fx_convolution) applied to the spline interpolant on 8x8
   grids, the momentum invariant, the adjoint identity;
@@ -71,6 +73,14 @@ def cardinal(k, u):
         out[m] = (-2 * u[m] ** 2 + 6 * u[m] - 3) / 2
         m = (u >= 2) & (u < 3)
         out[m] = (3 - u[m]) ** 2 / 2
+    else:
+        # orders above 3: the truncated-power form of the uniform B-spline,
+        # sum_j (-1)^j binom(k, j) (u - j)_+^(k-1) / (k-1)!, zero outside [0, k)
+        inside = (u >= 0) & (u < k)
+        acc = np.zeros_like(u)
+        for j in range(k + 1):
+            acc += (-1) ** j * math.comb(k, j) * np.maximum(u - j, 0.0) ** (k - 1)
+        out[inside] = acc[inside] / math.factorial(k - 1)
     return out
 
 
@@ -93,6 +103,60 @@ def test_bspline_explicit_and_centre_values():
         for x in rng.uniform(0, 1, 20):
             s = sum(oracle.bspline_value(k, np.arange(k + 1, dtype=float) - j, x) for j in range(k))
             assert abs(s - 1) < 1e-14
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_higher_order_stencils(k):
+    """The k = 4, 5 interpolation stencils are the spline's values at its
+    centre and at whole cells from it: the explicit truncated-power form,
+    the Cox-de Boor recursion of Eq. (eqnBk) (C library) and the exact
+    fractions (1, 4, 1) / 6 and (1, 76, 230, 76, 1) / 384 agree."""
+    st = np.array(oracle.STENCIL[k])
+    h = len(st) // 2
+    u = k / 2.0 + np.arange(-h, h + 1)  # centre of [0, k) and whole cells off it
+    assert np.allclose(cardinal(k, u), st, rtol=0, atol=1e-15)
+    t = np.arange(k + 1, dtype=np.float64)
+    assert np.allclose([oracle.bspline_value(k, t, x) for x in u], st, rtol=0, atol=1e-15)
+    exact = {4: [1, 4, 1], 5: [1, 76, 230, 76, 1]}[k]
+    assert np.array_equal(st * (6 if k == 4 else 384), np.array(exact, float))
+    # both forms agree everywhere, and form a partition of unity
+    rng = np.random.default_rng(k)
+    for x in rng.uniform(0, k, 40):
+        assert abs(oracle.bspline_value(k, t, x) - cardinal(k, [x])[0]) < 1e-14
+    for x in rng.uniform(0, 1, 10):
+        assert abs(sum(cardinal(k, [x + j])[0] for j in range(k)) - 1) < 1e-14
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_higher_order_interpolation(k):
+    """sigma at ``sample_lattice`` from the spline sum itself (each C_i'
+    times its spline, placed by the knot rule t0 = L + (i' - shift) dx of the
+    oracle's weights, evaluated by the truncated-power form) equals
+    ``bspline_apply``, and ``bspline_coeffs`` recovers C from it."""
+    rng = np.random.default_rng(20 + k)
+    M, N = 11, 7
+    dom = (-1.0, 1.0, -0.5, 1.5)
+    hx, hy = (dom[1] - dom[0]) / M, (dom[3] - dom[2]) / N
+    C = rng.standard_normal((N, M))
+    xs, ys = oracle.sample_lattice(k, M, N, dom)
+    shift = (k - 1) // 2
+    Bx = cardinal(k, ((xs[:, None] - (dom[0] + (np.arange(M)[None, :] - shift) * hx)) / hx).ravel())
+    By = cardinal(k, ((ys[:, None] - (dom[2] + (np.arange(N)[None, :] - shift) * hy)) / hy).ravel())
+    sig = By.reshape(N, N) @ C @ Bx.reshape(M, M).T
+    assert np.max(np.abs(sig - oracle.bspline_apply(C, k))) < 1e-14
+    assert np.max(np.abs(oracle.bspline_coeffs(sig, k) - C)) < 1e-12
+
+
+def test_banded_solve_matches_dense_solve():
+    rng = np.random.default_rng(4)
+    for k in (4, 5):
+        st = oracle.STENCIL[k]
+        h = len(st) // 2
+        for n in (1, 2, 3, 40):
+            A = sum(st[h + o] * np.eye(n, k=o) for o in range(-h, h + 1))
+            d = rng.standard_normal((n, 3))
+            assert np.allclose(oracle.banded_solve(st, d, axis=0), np.linalg.solve(A, d), rtol=0, atol=1e-13)
+            assert np.allclose(oracle.banded_solve(st, d.T, axis=1), np.linalg.solve(A, d).T, rtol=0, atol=1e-13)
 
 
 # -------------------------------------------------------- coefficient solve --
@@ -171,7 +235,8 @@ def _pieces_by_dblquad(k, m, n, hx, hy, skip_origin):
 @pytest.mark.parametrize("k,m,n,hx,hy", [(2, 1, 2, 1, 1), (2, -3, 0, 1, 1), (2, 0, 3, 1, 1), (3, 2, 1, 1, 1),
                                          (3, -1, 3, 1, 1), (3, 4, -2, 1, 1), (3, 0, 2, 1, 1),
                                          (3, 0, 2, 3, 1), (3, 2, 0, 1, 3), (1, 0, 1, 3, 1), (2, 2, 1, 2, 1),
-                                         (2, 0, 2, 1, 2.5)])
+                                         (2, 0, 2, 1, 2.5), (4, 3, 1, 1, 1), (4, -2, 0, 2, 1), (5, 3, -1, 1, 1),
+                                         (5, 0, 3, 1, 1)])
 def test_weights_library_quadrature(k, m, n, hx, hy):
     """Every spline piece integrated by scipy's adaptive quadrature (also
     for cells with dx != dy, which the grid of Sec. 2 allows)."""
@@ -193,20 +258,25 @@ def _origin_piece_closed(k, m, n, hx=1.0, hy=1.0):
     tx, bx = _piece_poly_1d(k, m, shift, hx)
     ty, by = _piece_poly_1d(k, n, shift, hy)
     # polynomial coefficients of the spline pieces on the centred square
-    nx_ = np.array([-0.25, 0.0, 0.25]) * hx
-    ny_ = np.array([-0.25, 0.0, 0.25]) * hy
-    px = np.polyfit(nx_, [bx(x) for x in nx_], 2)[::-1]   # p0 + p1 x + p2 x^2
-    py = np.polyfit(ny_, [by(y) for y in ny_], 2)[::-1]
+    deg = max(k - 1, 2)
+    nx_ = np.linspace(-0.25, 0.25, deg + 1) * hx
+    ny_ = np.linspace(-0.25, 0.25, deg + 1) * hy
+    px = np.polyfit(nx_, [bx(x) for x in nx_], deg)[::-1]   # p0 + p1 x + p2 x^2 + ...
+    py = np.polyfit(ny_, [by(y) for y in ny_], deg)[::-1]
     eps = mp.mpf("1e-40")
     X, Y = mp.mpf(hx) / 2, mp.mpf(hy) / 2
 
     def quad_pos(al, be):
-        F = lambda x, y: oracle.antiderivative(x, y, al, be)
+        # Appendix A up to alpha + beta = 4, Eq. (intF) beyond
+        if al + be <= 4:
+            F = lambda x, y: oracle.antiderivative(x, y, al, be)
+        else:
+            F = lambda x, y: oracle.antiderivative_intF(x, y, al, be)
         return F(X, Y) - F(eps, Y) - F(X, eps) + F(eps, eps)
 
     wx = wy = mp.mpf(0)
-    for a in range(3):
-        for b in range(3):
+    for a in range(deg + 1):
+        for b in range(deg + 1):
             if px[a] == 0 or py[b] == 0:
                 continue
             if (a + 1) % 2 == 0 and b % 2 == 0:      # kernel x~ times x~^a y~^b
@@ -219,7 +289,8 @@ def _origin_piece_closed(k, m, n, hx=1.0, hy=1.0):
 @pytest.mark.parametrize("k,m,n,hx,hy", [(1, 0, 0, 1, 1), (2, 0, 0, 1, 1), (2, 1, 0, 1, 1), (2, 0, 1, 1, 1),
                                          (2, 1, 1, 1, 1), (3, 0, 0, 1, 1), (3, 1, 0, 1, 1), (3, -1, 1, 1, 1),
                                          (3, 1, 1, 1, 1), (3, 0, 1, 1, 1), (3, 1, 0, 3, 1), (3, 1, -1, 1, 2.5),
-                                         (2, 1, 0, 2, 1)])
+                                         (2, 1, 0, 2, 1), (4, 0, 0, 1, 1), (4, 2, -1, 1, 1), (4, 1, 1, 2, 1),
+                                         (5, 0, 0, 1, 1), (5, 2, 1, 1, 1), (5, -1, 0, 3, 1)])
 def test_weights_origin_piece(k, m, n, hx, hy):
     """Offsets whose spline has a piece on the singularity: that piece by the
     closed forms, the other pieces by scipy's adaptive quadrature."""
@@ -234,7 +305,7 @@ def test_weight_symmetries_and_scale():
     rng = np.random.default_rng(3)
     ms = rng.integers(-60, 61, 200)
     ns = rng.integers(-60, 61, 200)
-    for k in (1, 3):
+    for k in (1, 3, 5):
         wx, wy = oracle.weights_at(k, 1.0, 1.0, ms, ns)
         wxm, _ = oracle.weights_at(k, 1.0, 1.0, -ms, ns)
         wxn, _ = oracle.weights_at(k, 1.0, 1.0, ms, -ns)
@@ -247,19 +318,20 @@ def test_weight_symmetries_and_scale():
         assert np.max(np.abs(w0)) < 1e-15
         wh, _ = oracle.weights_at(k, 0.03125, 0.03125, ms, ns)
         assert np.max(np.abs(wh - wx)) < 1e-14 * s
-    # k = 2: antisymmetric about m = 1/2 and symmetric about n = 1/2
-    wx, _ = oracle.weights_at(2, 1.0, 1.0, ms, ns)
-    wxm, _ = oracle.weights_at(2, 1.0, 1.0, 1 - ms, ns)
-    wxn, _ = oracle.weights_at(2, 1.0, 1.0, ms, 1 - ns)
-    s = np.max(np.abs(wx))
-    assert np.max(np.abs(wx + wxm)) < 1e-15 * s
-    assert np.max(np.abs(wx - wxn)) < 1e-15 * s
+    # even k: antisymmetric about m = 1/2 and symmetric about n = 1/2
+    for k in (2, 4):
+        wx, _ = oracle.weights_at(k, 1.0, 1.0, ms, ns)
+        wxm, _ = oracle.weights_at(k, 1.0, 1.0, 1 - ms, ns)
+        wxn, _ = oracle.weights_at(k, 1.0, 1.0, ms, 1 - ns)
+        s = np.max(np.abs(wx))
+        assert np.max(np.abs(wx + wxm)) < 1e-15 * s
+        assert np.max(np.abs(wx - wxn)) < 1e-15 * s
 
 
 def test_weights_far_field():
     """w^x -> -m/R^3 (1 + k/(8R^2) + O(R^-4)) for centred splines: the second
     moment k/12 of the order-k spline acting on the 2-D Laplacian of x/r^3."""
-    for k in (1, 3):
+    for k in (1, 3, 5):
         offs = [(20, 0), (30, 40), (100, 7), (400, -300), (1500, 2000), (4000, 100)]
         ms, ns = zip(*offs)
         wx, _ = oracle.weights_at(k, 1.0, 1.0, ms, ns)
@@ -331,7 +403,7 @@ def _brute_force_pv(k, C, domain, i, j):
     return total_x, total_y
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
 def test_direct_sum_brute_force_8x8(k):
     rng = np.random.default_rng(10 + k)
     C = rng.uniform(-1, 1, (8, 8))
@@ -374,7 +446,7 @@ def test_sparse_superposition_matches_full_sum():
     assert np.allclose(sy, fy, rtol=0, atol=1e-13)
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
 def test_adjoint_identity(k):
     rng = np.random.default_rng(20 + k)
     N, M = 12, 17
