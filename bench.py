@@ -268,6 +268,30 @@ def aniso_bench(sg, torch, k, steps, warmup):
             "rel_err_vs_fp64": err, "meets_1e-6": bool(err <= 1e-6)}
 
 
+def orders_bench(sg, torch, n, steps, warmup):
+    """The cubic and quartic splines (k = 4, 5) on the headline grid: n x n
+    cells on [-1,1]^2, the same clump recipe, FP32-split timed and checked
+    against FP64."""
+    import numpy as np
+    import workloads
+    out = {}
+    h = 2.0 / n
+    for k in (4, 5):
+        grid = (n, n, -1.0, 1.0, -1.0, 1.0, k)
+        off = 0.5 if k % 2 == 1 else 1.0  # cell centres (odd k) or vertices x0 + (i+1) dx (even k)
+        xs = -1.0 + h * (off + np.arange(n))
+        sigma = workloads.clump_sigma(workloads.clump_params(2, 32), xs, xs)
+        ms64, pass64, _, (gx, gy) = time_plan(sg, torch, grid, sg.SG_FP64, sigma, steps, warmup)
+        ms32, pass32, plan32, (fx, fy) = time_plan(sg, torch, grid, sg.SG_FP32_SPLIT, sigma, steps, warmup)
+        scale = max(np.abs(gx).max(), np.abs(gy).max())
+        err = max(np.abs(fx - gx).max(), np.abs(fy - gy).max()) / scale
+        out[f"k{k}"] = {"value": n * n / (ms32 * 1e-3), "unit": "cells/s", "ms_per_step": round(ms32, 4),
+                        "pass_ms": [round(x, 4) for x in pass32], "plan_s": round(plan32, 3),
+                        "fp64_ms_per_step": round(ms64, 4), "fp64_pass_ms": [round(x, 4) for x in pass64],
+                        "rel_err_vs_fp64": err, "meets_1e-6": bool(err <= 1e-6)}
+    return out
+
+
 def cpu_baseline(n, k, sigma_np, sample):
     """The oracle (direct O(N^4) FP64 sum, OpenMP) on a bounded sample of cells."""
     import numpy as np
@@ -316,6 +340,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-disks measurement")
     ap.add_argument("--batch-only", action="store_true", help="only the batched-disks measurement")
     ap.add_argument("--no-aniso", action="store_true", help="skip the anisotropic-cell measurement")
+    ap.add_argument("--no-orders", action="store_true", help="skip the k = 4, 5 measurement")
     ap.add_argument("--prec", choices=["both", "fp32", "fp64"], default="both",
                     help="both (default, the metric) or one path only (profiling)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -413,6 +438,8 @@ def main():
         line["batch"] = batch_bench(sg, torch, max(args.steps // 2, 3), 2)
     if not args.no_aniso:
         line["anisotropic"] = aniso_bench(sg, torch, k, max(args.steps // 2, 3), 2)
+    if not args.no_orders:
+        line["higher_orders"] = orders_bench(sg, torch, n, max(args.steps // 2, 3), 2)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(n, k, sigma, args.cpu_sample)
     print(json.dumps(line), flush=True)

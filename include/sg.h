@@ -7,7 +7,8 @@
  * a surface density sigma confined to the rectangle [x0,x1] x [y0,y1], cut
  * into nx x ny equal cells, is interpolated with order-k tensor B-splines
  * (k = 1, 2, 3: piecewise constant, linear, quadratic; Sec. 2, Eqs.
- * (Bspline1)-(Bspline3)); the forces at the cell centres are the discrete
+ * (Bspline1)-(Bspline3); k = 4, 5: cubic and quartic, the extension to
+ * higher orders that Case 3 of Sec. 2.2 and the end of Sec. 2.3 state); the forces at the cell centres are the discrete
  * convolutions  F^x_ij = sum_{i'j'} C_{i'j'} w^x_{i-i',j-j'}  (Eq. (eqnF)) with
  * the kernel weights of Eq. (eqnwB), G = 1, attractive sign (the integrand
  * is (x'-x)/r^3, Sec. 2.2 Case 1).  The convolutions are evaluated with
@@ -49,7 +50,7 @@ typedef struct sg_plan_s* sg_plan;
 typedef enum {
   SG_OK = 0,
   SG_ERR_ARG = 1,         /* null pointer, bad size, empty or non-finite domain, bad index */
-  SG_ERR_UNSUPPORTED = 2, /* order outside 1..3, grid size without a kernel instantiation */
+  SG_ERR_UNSUPPORTED = 2, /* order outside 1..5, grid size without a kernel instantiation */
   SG_ERR_NOMEM = 3,       /* device or host allocation failed */
   SG_ERR_DEVICE = 4,      /* a HIP call or kernel launch failed (message holds the HIP error) */
   SG_ERR_STATE = 5        /* plan is in the sticky error state, or a non-finite input was found */
@@ -67,7 +68,7 @@ typedef enum {
 typedef struct {
   int32_t nx, ny;
   double x0, x1, y0, y1;
-  int32_t order; /* k in {1, 2, 3} */
+  int32_t order; /* k in {1, 2, 3, 4, 5} */
 } sg_grid;
 
 /* plan flags */
@@ -98,8 +99,9 @@ sg_status sg_plan_info(sg_plan p, int32_t* ngrids, int32_t* prec, int64_t* devic
 
 /* Where sigma of grid g must be sampled (HOST outputs): point (i, j), 0-based,
  * is (xs0 + i*dx, ys0 + j*dy).  Odd k: the cell centres (interpolation
- * condition Eq. (eqnSigmaB)); k = 2: the vertices x0 + (i+1) dx, i.e. the
- * peaks of the order-2 splines of Case 2 (Sec. 2.2), where C = sigma. */
+ * condition Eq. (eqnSigmaB)); even k: the vertices x0 + (i+1) dx, i.e. the
+ * centres of the order-2 splines of Case 2 (Sec. 2.2), where C = sigma, and
+ * of the cubic splines. */
 sg_status sg_sample_points(sg_plan p, int32_t g, double* xs0, double* ys0, double* dx, double* dy);
 
 /* Export the weights of grid g (Eq. (eqnwB)), FP64 DEVICE arrays of
@@ -110,7 +112,9 @@ sg_status sg_weights(sg_plan p, int32_t g, double* wx, double* wy);
 
 /* sigma -> spline coefficients C for every grid of the plan (Sec. 2.3): the
  * identity for k = 1, 2; for k = 3 the tridiagonal systems of Eqs.
- * (z_system) and (C_system), C = 0 outside the grid.  Packed buffers;
+ * (z_system) and (C_system), C = 0 outside the grid; for k = 4, 5 the
+ * systems of the same construction with the cubic spline's values
+ * (1, 4, 1) / 6 and the quartic's (1, 76, 230, 76, 1) / 384 per axis.  Packed buffers;
  * sigma and coeffs may alias. */
 sg_status sg_bspline_coeffs(sg_plan p, const void* sigma, void* coeffs);
 

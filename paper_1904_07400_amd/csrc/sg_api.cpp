@@ -278,7 +278,7 @@ hipError_t issue_class(sg_plan p, const GridClass& c, const void* sigma, void* f
                        const int* tile) {
   const int prec = p->prec == SG_FP64 ? 0 : 1;
   const GridPlan& G = p->grids[c.members[0]];
-  const int solve = c.k == 3 ? 1 : 0;
+  const int solve = c.k >= 3 ? c.k : 0;
   const int ng = (int)c.members.size();
   const int tj = sg_row_tile(prec, c.M, c.N);
   hipError_t e = sg_launch_row_fwd(prec, c.M, sigma, c.M, nullptr, c.N, G.r2m, solve, 0, G.twA, c.desc, ng, tile[0], q);
@@ -333,7 +333,7 @@ sg_status time_tile(sg_plan p, GridClass& c, int pass, int tile, const void* sig
   t3[pass] = tile;
   const int prec = p->prec == SG_FP64 ? 0 : 1;
   const GridPlan& G = p->grids[c.members[0]];
-  const int solve = c.k == 3 ? 1 : 0;
+  const int solve = c.k >= 3 ? c.k : 0;
   const int ng = (int)c.members.size();
   const int tj = sg_row_tile(prec, c.M, c.N);
   hipEvent_t a, b;
@@ -440,7 +440,7 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
     if (!isfinite(g.x0) || !isfinite(g.x1) || !isfinite(g.y0) || !isfinite(g.y1) || !(g.x1 > g.x0) ||
         !(g.y1 > g.y0))
       return fail(SG_ERR_ARG, "grid %d: empty or non-finite domain", i);
-    if (g.order < 1 || g.order > 3) return fail(SG_ERR_UNSUPPORTED, "grid %d: order %d (supported: 1..3)", i, g.order);
+    if (g.order < 1 || g.order > 5) return fail(SG_ERR_UNSUPPORTED, "grid %d: order %d (supported: 1..5)", i, g.order);
     if (!size_ok(g.nx) || !size_ok(g.ny))
       return fail(SG_ERR_UNSUPPORTED, "grid %d: %dx%d (supported: 2^a from 4 to 4096, 3*2^a from 12 to 1536)", i,
                   g.nx, g.ny);
@@ -477,12 +477,12 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
     G.M = grids[i].nx;
     G.N = grids[i].ny;
     G.k = grids[i].order;
-    G.kind = (G.k == 2) ? 1 : 0;
+    G.kind = (G.k % 2 == 0) ? 1 : 0;  // even k: splines centred on vertices, complex spectra
     G.hx = (grids[i].x1 - grids[i].x0) / G.M;
     G.hy = (grids[i].y1 - grids[i].y0) / G.N;
     G.off = off;
     off += (int64_t)G.M * G.N;
-    const size_t tab_el = G.kind == 0 ? 8 : 16;  // odd k: one real (FP64 or hi+lo FP32); k=2: complex
+    const size_t tab_el = G.kind == 0 ? 8 : 16;  // odd k: one real (FP64 or hi+lo FP32); even k: complex
     const size_t tab_n = G.kind == 0 ? (size_t)(G.M + 1) * (G.N + 1) : (size_t)(G.M + 1) * 2 * G.N;
     // grids of equal size, order and cell shape share one pair of spectra
     const auto key = std::make_tuple(G.M, G.N, G.k, G.hx, G.hy);
@@ -629,7 +629,7 @@ sg_status sg_sample_points(sg_plan p, int32_t g, double* xs0, double* ys0, doubl
   if (!p) return fail(SG_ERR_ARG, "plan is NULL");
   if (g < 0 || g >= (int32_t)p->grids.size()) return fail(SG_ERR_ARG, "grid index %d out of range", g);
   const GridPlan& G = p->grids[g];
-  const double off = (G.k % 2 == 1) ? 0.5 : 1.0;  // cell centres (odd k) or vertices x0 + (i+1) dx (k = 2)
+  const double off = (G.k % 2 == 1) ? 0.5 : 1.0;  // cell centres (odd k) or vertices x0 + (i+1) dx (even k)
   if (xs0) *xs0 = G.g.x0 + off * G.hx;
   if (ys0) *ys0 = G.g.y0 + off * G.hy;
   if (dx) *dx = G.hx;
@@ -658,9 +658,9 @@ sg_status sg_bspline_coeffs(sg_plan p, const void* sigma, void* coeffs) {
     const char* src = (const char*)sigma + el * G.off;
     char* dst = (char*)coeffs + el * G.off;
     hipError_t e = hipSuccess;
-    if (G.k == 3) {
-      e = sg_launch_coeff_rows(prec, G.M, src, dst, G.N, p->st);
-      if (e == hipSuccess) e = sg_launch_coeff_cols(prec, G.N, dst, G.M, p->st);
+    if (G.k >= 3) {
+      e = sg_launch_coeff_rows(prec, G.M, src, dst, G.N, G.k, p->st);
+      if (e == hipSuccess) e = sg_launch_coeff_cols(prec, G.N, dst, G.M, G.k, p->st);
     } else if (src != dst) {
       e = hipMemcpyAsync(dst, src, el * (size_t)G.M * G.N, hipMemcpyDeviceToDevice, p->st);
     }
@@ -723,7 +723,7 @@ sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy) {
     // one launch per pass for every grid of the class, timing marks around them
     hipError_t e = mark(p);
     const GridPlan& G = p->grids[c.members[0]];
-    const int solve = c.k == 3 ? 1 : 0;
+    const int solve = c.k >= 3 ? c.k : 0;
     const int ng = (int)c.members.size();
     const int tj = sg_row_tile(prec, c.M, c.N);
     if (e == hipSuccess)
@@ -816,7 +816,7 @@ sg_status sg_forces_adjoint(sg_plan p, const void* gfx, const void* gfy, void* g
   // half of V (descriptors desc_y), gC spectra in its second half
   for (const GridClass& c : p->classes) {
     const GridPlan& G = p->grids[c.members[0]];
-    const int solve = c.k == 3 ? 1 : 0;
+    const int solve = c.k >= 3 ? c.k : 0;
     const int ng = (int)c.members.size();
     hipError_t e =
         sg_launch_row_fwd(prec, c.M, gfx, c.M, nullptr, c.N, G.r2m, 0, 0, G.twA, c.desc, ng, c.tile[0], p->st);

@@ -23,7 +23,8 @@ struct sg_bgrid {
 hipError_t sg_set_gl_tables(const double* x /*4x16*/, const double* w /*4x16*/);
 hipError_t sg_launch_weights(int k, double hx, double hy, int M, int N, double* wx, double* wy, int layout,
                              hipStream_t st);
-// tw: stage twiddle tables of the pass (sg_twiddles)
+// tw: stage twiddle tables of the pass (sg_twiddles).  solve: 0 for k = 1, 2,
+// else the order k (3, 4, 5) of the interpolation system solved on the way
 hipError_t sg_launch_row_fwd(int prec, int M, const void* src, int64_t ld, void* X, int nrows, const void* r2m,
                              int solve, int full, const void* tw, const sg_bgrid* bg, int ngrids, int tile,
                              hipStream_t st);
@@ -45,8 +46,8 @@ hipError_t sg_launch_spec_col(int N, const void* S, int M, void* tab, int kind, 
 // NULL) or fills out on st; -1 for an unsupported size.
 int sg_twiddles(int prec, int pass, int len, const void* roots, void* out, hipStream_t st);
 hipError_t sg_launch_check_finite(int prec, const void* x, int64_t n, int* flag, hipStream_t st);
-hipError_t sg_launch_coeff_rows(int prec, int M, const void* src, void* dst, int nrows, hipStream_t st);
-hipError_t sg_launch_coeff_cols(int prec, int N, void* data, int M, hipStream_t st);
+hipError_t sg_launch_coeff_rows(int prec, int M, const void* src, void* dst, int nrows, int k, hipStream_t st);
+hipError_t sg_launch_coeff_cols(int prec, int N, void* data, int M, int k, hipStream_t st);
 // Adjoint after the two forward row transforms of gx, gy (Xx, Xy
 // column-major like X): conjugate-spectrum column pass into Y (tiles of tj
 // rows), then the inverse real row pass with the x-solve into gsigma.

@@ -119,13 +119,69 @@ namespace sg {
 __constant__ double c_glx[4][16];
 __constant__ double c_glw[4][16];
 __constant__ int c_glq[4] = {4, 6, 10, 16};
-// Spline pieces as polynomials c0 + c1 xi + c2 xi^2 in the piece-centred
-// variable xi in [-1/2, 1/2] (Eqs. (Bspline1)-(Bspline3) on uniform knots):
-// order k, piece r (piece r spans [t_r, t_{r+1}]).
-__constant__ double c_piece[3][3][3] = {
-    {{1.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}},
-    {{0.5, 1.0, 0.0}, {0.5, -1.0, 0.0}, {0.0, 0.0, 0.0}},
-    {{0.125, 0.5, 0.5}, {0.75, 0.0, -1.0}, {0.125, -0.5, 0.5}}};
+// Spline pieces as polynomials c0 + c1 xi + ... + c_{k-1} xi^{k-1} in the
+// piece-centred variable xi in [-1/2, 1/2] (Eqs. (Bspline1)-(Bspline3) on
+// uniform knots, and the recursion of Eq. (eqnBk) carried to the cubic and
+// quartic): order k, piece r (piece r spans [t_r, t_{r+1}]).
+__constant__ double c_piece[5][5][5] = {
+    {{1.0}},
+    {{0.5, 1.0}, {0.5, -1.0}},
+    {{0.125, 0.5, 0.5}, {0.75, 0.0, -1.0}, {0.125, -0.5, 0.5}},
+    {{1.0 / 48, 1.0 / 8, 1.0 / 4, 1.0 / 6},
+     {23.0 / 48, 5.0 / 8, -1.0 / 4, -1.0 / 2},
+     {23.0 / 48, -5.0 / 8, -1.0 / 4, 1.0 / 2},
+     {1.0 / 48, -1.0 / 8, 1.0 / 4, -1.0 / 6}},
+    {{1.0 / 384, 1.0 / 48, 1.0 / 16, 1.0 / 12, 1.0 / 24},
+     {19.0 / 96, 11.0 / 24, 1.0 / 4, -1.0 / 6, -1.0 / 6},
+     {115.0 / 192, 0.0, -5.0 / 8, 0.0, 1.0 / 4},
+     {19.0 / 96, -11.0 / 24, 1.0 / 4, 1.0 / 6, -1.0 / 6},
+     {1.0 / 384, -1.0 / 48, 1.0 / 16, -1.0 / 12, 1.0 / 24}}};
+
+// a piece's polynomial at xi (Horner, degree k - 1)
+__device__ __forceinline__ double piece_at(const double* p, int k, double xi) {
+  double v = p[k - 1];
+  for (int d = k - 2; d >= 0; --d) v = p[d] + xi * v;
+  return v;
+}
+
+// int_0^T t^n (1 + t^2)^(-3/2) dt for even n: the moments of Eq. (intMoment)
+// with a = 1, by their recursion from n = 0, 2; below T = 1/2 by the power
+// series of (1 + t^2)^(-3/2) instead, where the closed forms cancel.
+__device__ double gmoment(int n, double T) {
+  if (T < 0.5) {
+    const double T2 = T * T;
+    double tp = T, c = 1.0, acc = 0.0;
+    for (int j = 0; j < n; ++j) tp *= T;
+    for (int m = 0; m < 40; ++m) {
+      acc += c * tp / (double)(n + 2 * m + 1);
+      tp *= T2;
+      c *= (-1.5 - m) / (double)(m + 1);
+    }
+    return acc;
+  }
+  const double rho = sqrt(1.0 + T * T);
+  if (n == 0) return T / rho;
+  double g = asinh(T) - T / rho, tp = T;
+  for (int j = 4; j <= n; j += 2) {
+    tp *= T * T;
+    g = tp / ((double)(j - 2) * rho) - (double)(j - 1) / (double)(j - 2) * g;
+  }
+  return g;
+}
+
+// Principal value of x^al y^be / r^3 over [-X, X] x [-Y, Y] (al, be even,
+// al + be >= 2): four times the quarter [0, X] x [0, Y], which polar
+// coordinates split at the diagonal into two one-dimensional moments (the
+// form of Eq. (intF)).
+__device__ double pv_moment(int al, int be, double X, double Y) {
+  const int s = al + be - 1;
+  double xs = 1.0, ys = 1.0;
+  for (int j = 0; j < s; ++j) {
+    xs *= X;
+    ys *= Y;
+  }
+  return 4.0 * (xs * gmoment(be, Y / X) + ys * gmoment(al, X / Y)) / (double)s;
+}
 
 // Both weight components at offset (m, n): the integrals of x~/r^3 and
 // y~/r^3 against the tensor spline attached to C_{i-m, j-n} (Eq. (eqnwB)).
@@ -146,6 +202,23 @@ __device__ void weight_pair(int k, double hx, double hy, int m, int n, double& w
       const int oy = s - n - shift;
       const double cyp = (double)oy * hy;
       const double* py = c_piece[k - 1][s];
+      if (ox == 0 && oy == 0 && k > 3) {
+        // cubic and quartic pieces: every monomial pair odd in the force
+        // direction and even across it
+        const double X = 0.5 * hx, Y = 0.5 * hy;
+        double sa = 1.0;
+        for (int a = 0; a < k; ++a) {
+          double sb = 1.0;
+          for (int b = 0; b < k; ++b) {
+            const double c = px[a] * py[b] / (sa * sb);
+            if ((a & 1) && !(b & 1)) sx += c * pv_moment(a + 1, b, X, Y);
+            if (!(a & 1) && (b & 1)) sy += c * pv_moment(a, b + 1, X, Y);
+            sb *= hy;
+          }
+          sa *= hx;
+        }
+        continue;
+      }
       if (ox == 0 && oy == 0) {
         const double X = 0.5 * hx, Y = 0.5 * hy, Rr = sqrt(X * X + Y * Y);
         const double LX = log((X + Rr) / Y), LY = log((Y + Rr) / X);
@@ -175,14 +248,14 @@ __device__ void weight_pair(int k, double hx, double hy, int m, int n, double& w
         for (int a = 0; a < q; ++a) {
           const double xi = xic + (0.5 / nsx) * c_glx[qi][a];
           const double x = cxp + xi * hx;
-          const double bx = (px[0] + xi * (px[1] + xi * px[2])) * c_glw[qi][a];
+          const double bx = piece_at(px, k, xi) * c_glw[qi][a];
           double ix = 0.0, iy = 0.0;
           for (int sb = 0; sb < nsy; ++sb) {
             const double etc = -0.5 + (sb + 0.5) / nsy;
             for (int b = 0; b < q; ++b) {
               const double eta = etc + (0.5 / nsy) * c_glx[qi][b];
               const double y = cyp + eta * hy;
-              const double by = (py[0] + eta * (py[1] + eta * py[2])) * c_glw[qi][b];
+              const double by = piece_at(py, k, eta) * c_glw[qi][b];
               const double r2 = x * x + y * y;
               const double inv = by / (r2 * sqrt(r2));
               ix += x * inv;
@@ -213,7 +286,7 @@ __global__ void k_weights(int k, double hx, double hy, int M, int N, double* __r
   const int W = layout == 0 ? 2 * M : 2 * M - 1;
   const int H = layout == 0 ? 2 * N : 2 * N - 1;
   const int64_t total = (int64_t)W * H;
-  const int s2 = (k == 2) ? 1 : 0;  // twice the spline-centre offset, in cells
+  const int s2 = (k % 2 == 0) ? 1 : 0;  // twice the spline-centre offset, in cells
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int p = (int)(idx % W), q = (int)(idx / W);
@@ -295,7 +368,7 @@ struct rowfwd_cfg {
   static constexpr int LL = lds_len<L>::value;
   // per-row LDS slot (complex elements): FFT exchange buffer, also used
   // for the reduced system of the x-solve
-  static constexpr int TRI = (int)(sizeof(tri_smem<double, T>) / sizeof(cx<R>)) + 1;
+  static constexpr int TRI = band_smem<double, T>::BYTES / (int)sizeof(cx<R>) + 1;
   static constexpr int SLOT = LL > TRI ? LL : TRI;
   static constexpr int NB = (sizeof(R) == 4 && sizeof(In) == 4) ? SG_RF_NBUF32 : 1;  // exchange buffers per row
   // rows per workgroup: more rows make longer segments of the transposed store
@@ -307,7 +380,10 @@ struct rowfwd_cfg {
   static constexpr int EC = (SLOT / (2 * T)) < 1 ? 1 : ((SLOT / (2 * T)) > E ? E : SLOT / (2 * T));
 };
 
-template <typename R, typename In, int M>
+// HI: the x-solve of k = 4, 5 (solve = 4, 5); otherwise that of k = 3 (solve
+// = 3) or none (solve = 0).  Separate instantiations keep the registers of
+// the k <= 3 kernels those of their own solve.
+template <typename R, typename In, int M, bool HI = false>
 __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M>::T))
     SG_WPE(R, RF)
     k_row_fwd(const In* __restrict__ src, int64_t src_ld, cx<R>* __restrict__ X, int ldx, int nrows,
@@ -331,15 +407,21 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
   // afterwards), so that they issue together rather than one at a time
   // behind a branch each
   const In* s = src + (int64_t)(active ? row : 0) * src_ld;
-  const double msk = active ? 8.0 : 0.0;
+  const double msk = active ? (HI ? band_scale(solve) : band_scale(3)) : 0.0;
   cx<R> ze[E], zo[E];
   if (solve) {
-    // chunk of 2E reals per thread: x-solve of Eq. (C_system), FP64
+    // chunk of 2E reals per thread: x-solve of Eq. (C_system) (order
+    // solve = 3, 4 or 5), FP64
     constexpr int CH = 2 * E;
     double d[CH];
 #pragma unroll
     for (int e = 0; e < CH; ++e) d[e] = msk * (double)s[t * CH + e];
-    tri_solve<CH, T, double>(d, t, *reinterpret_cast<tri_smem<double, T>*>(lds));
+    if constexpr (!HI)
+      band_solve<3, CH, T>(d, t, lds);
+    else if (solve == 4)
+      band_solve<4, CH, T>(d, t, lds);
+    else
+      band_solve<5, CH, T>(d, t, lds);
 #pragma unroll
     for (int e = 0; e < E; ++e) lds[pad(t * E + e)] = cx<R>{(R)d[2 * e], (R)d[2 * e + 1]};
     __syncthreads();
@@ -440,7 +522,7 @@ struct col_cfg {
   static constexpr int E = elems_for(N, E0, SG_E3);
   static constexpr int T = N / E;
   static constexpr int LL = lds_len<N>::value;
-  static constexpr int TRI = (int)(sizeof(tri_smem<double2, T>) / sizeof(cx<R>)) + 1;
+  static constexpr int TRI = band_smem<double2, T>::BYTES / (int)sizeof(cx<R>) + 1;
   static constexpr int SLOT = LL > TRI ? LL : TRI;  // per-column LDS slot (complex elements)
   // exchange buffers per column: 2 or 4 let as many transforms share their
   // barriers
@@ -558,14 +640,16 @@ __device__ __forceinline__ void col_product(const cx<R>* f, cx<R>* g, int half, 
 }
 
 // MODE: 0 = k 1 (real tables, no solve), 1 = k 2 (complex tables), 2 = k 3
-// (real tables, y-solve)
+// (real tables, y-solve), 3 = k 4 (complex tables, y-solve), 4 = k 5 (real
+// tables, pentadiagonal y-solve)
 template <typename R, typename TO, typename TC, int N, int MODE>
 __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     SG_WPE(R, COL) k_col(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
           const TO* __restrict__ toy, const TC* __restrict__ tcx, const TC* __restrict__ tcy,
           const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ tw, const sg_bgrid* __restrict__ bg) {
-  constexpr int kind = MODE == 1 ? 1 : 0;
-  constexpr bool solve = MODE == 2;
+  constexpr int kind = (MODE == 1 || MODE == 3) ? 1 : 0;
+  constexpr bool solve = MODE >= 2;
+  constexpr int SYS = MODE == 2 ? 3 : (MODE == 3 ? 4 : 5);  // order of the y-solve
   if (bg) {  // batched: grid blockIdx.y of the class
     const sg_bgrid d = grid_desc(bg);
     X = reinterpret_cast<const cx<R>*>(d.X);
@@ -621,12 +705,12 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     // y-solve of Eq. (z_system) on the complex row spectra, FP64, chunk of E per thread
     double2 d[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) d[e] = make_double2(8.0 * (double)a[e].x, 8.0 * (double)a[e].y);
+    for (int e = 0; e < E; ++e) d[e] = make_double2(band_scale(SYS) * (double)a[e].x, band_scale(SYS) * (double)a[e].y);
     if constexpr (pp) {
       // the solve's LDS lies in buffer 0; the transpose goes through buffer
       // 2, and the forward transform's first exchange (buffers 0 and 1)
       // follows the transpose's barrier, so neither needs a barrier after it
-      tri_solve<E, T, double2, false>(d, t, *reinterpret_cast<tri_smem<double2, T>*>(lds));
+      band_solve<SYS, E, T, double2, false>(d, t, lds);
       cx<R>* tb = lds + 2 * LL;
 #pragma unroll
       for (int e = 0; e < E; ++e) tb[pad(t * E + e)] = cx<R>{(R)d[e].x, (R)d[e].y};
@@ -634,7 +718,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
 #pragma unroll
       for (int e = 0; e < E; ++e) a[e] = tb[pad(t + e * T)];
     } else {
-      tri_solve<E, T, double2>(d, t, *reinterpret_cast<tri_smem<double2, T>*>(lds));
+      band_solve<SYS, E, T, double2>(d, t, lds);
 #pragma unroll
       for (int e = 0; e < E; ++e) lds[pad(t * E + e)] = cx<R>{(R)d[e].x, (R)d[e].y};
       __syncthreads();
@@ -932,8 +1016,9 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
               const TO* __restrict__ tox, const TO* __restrict__ toy, const TC* __restrict__ tcx,
               const TC* __restrict__ tcy, const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ tw,
               const sg_bgrid* __restrict__ bg) {
-  constexpr int kind = MODE == 1 ? 1 : 0;
-  constexpr bool solve = MODE == 2;
+  constexpr int kind = (MODE == 1 || MODE == 3) ? 1 : 0;
+  constexpr bool solve = MODE >= 2;
+  constexpr int SYS = MODE == 2 ? 3 : (MODE == 3 ? 4 : 5);  // order of the y-solve
   if (bg) {  // batched: gx spectra in X, gy spectra in the first half of V, output in its second half
     const sg_bgrid d = grid_desc(bg);
     Xx = reinterpret_cast<const cx<R>*>(d.X);
@@ -988,10 +1073,10 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const cx<R> v = lds[pad(t * E + e)];
-      d[e] = make_double2(8.0 * (double)v.x, 8.0 * (double)v.y);
+      d[e] = make_double2(band_scale(SYS) * (double)v.x, band_scale(SYS) * (double)v.y);
     }
     __syncthreads();
-    tri_solve<E, T, double2>(d, t, *reinterpret_cast<tri_smem<double2, T>*>(lds));
+    band_solve<SYS, E, T, double2>(d, t, lds);
 #pragma unroll
     for (int e = 0; e < E; ++e) lds[pad(t * E + e)] = cx<R>{(R)d[e].x, (R)d[e].y};
     __syncthreads();
@@ -1011,7 +1096,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
 // the half-length complex inverse FFT (z = x_even + i x_odd, its first M/2
 // outputs from the even and odd input bins: two inverse FFTs of length M/2),
 // then the transposed x-solve (Eq. (C_system) is symmetric).
-template <typename R, typename Out, int M>
+template <typename R, typename Out, int M, bool HI = false>  // HI: as in k_row_fwd
 __global__ void __launch_bounds__((rowfwd_cfg<R, R, M>::G * rowfwd_cfg<R, R, M>::T))
     k_row_c2r(const cx<R>* __restrict__ Y, Out* __restrict__ out, int nrows, int tj, const cx<R>* __restrict__ r2m,
               int solve, const cx<R>* __restrict__ tw, const sg_bgrid* __restrict__ bg) {
@@ -1068,11 +1153,16 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, R, M>::G * rowfwd_cfg<R, R, M>:
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const cx<R> v = lds[pad(t * E + e)];
-      d[2 * e] = 8.0 * (double)v.x;
-      d[2 * e + 1] = 8.0 * (double)v.y;
+      d[2 * e] = (HI ? band_scale(solve) : band_scale(3)) * (double)v.x;
+      d[2 * e + 1] = (HI ? band_scale(solve) : band_scale(3)) * (double)v.y;
     }
     __syncthreads();
-    tri_solve<CH, T, double>(d, t, *reinterpret_cast<tri_smem<double, T>*>(lds));
+    if constexpr (!HI)
+      band_solve<3, CH, T>(d, t, lds);
+    else if (solve == 4)
+      band_solve<4, CH, T>(d, t, lds);
+    else
+      band_solve<5, CH, T>(d, t, lds);
     if (active) {
 #pragma unroll
       for (int e = 0; e < CH; ++e) out[(int64_t)row * M + t * CH + e] = (Out)d[e];
@@ -1185,7 +1275,7 @@ __global__ void k_check_finite(const In* __restrict__ x, int64_t n, int* __restr
 }
 
 // ------------------------------------------------- coefficients (C out) --
-// sigma -> C for k = 3 written out (sg_bspline_coeffs): the x-solve along
+// sigma -> C for k = 3, 4, 5 written out (sg_bspline_coeffs): the x-solve along
 // rows (Eq. (C_system)) then the y-solve along columns (Eq. (z_system));
 // the two commute.  The per-step force path fuses them into passes A and B.
 template <int M>
@@ -1193,12 +1283,12 @@ struct coeff_cfg {
   static constexpr int CH = elems_for(M, 16, 12);
   static constexpr int T = M / CH;
   static constexpr int G = T >= 256 ? 1 : 256 / T;
-  static constexpr int SLOT = (int)sizeof(tri_smem<double, T>) / 8 + 1;
+  static constexpr int SLOT = band_smem<double, T>::BYTES / 8 + 1;
 };
 
 template <typename R, int M>
 __global__ void __launch_bounds__((coeff_cfg<M>::G * coeff_cfg<M>::T))
-    k_coeff_rows(const R* __restrict__ src, R* __restrict__ dst, int nrows) {
+    k_coeff_rows(const R* __restrict__ src, R* __restrict__ dst, int nrows, int sys) {
   using C = coeff_cfg<M>;
   constexpr int CH = C::CH, T = C::T;
   __shared__ double smem[C::G * C::SLOT];
@@ -1208,10 +1298,16 @@ __global__ void __launch_bounds__((coeff_cfg<M>::G * coeff_cfg<M>::T))
   double d[CH];
   // unconditional loads (row 0 stands in for rows past nrows), masked
   const R* s = src + (int64_t)(active ? row : 0) * M + t * CH;
-  const double msk = active ? 8.0 : 0.0;
+  const double msk = active ? band_scale(sys) : 0.0;
 #pragma unroll
   for (int e = 0; e < CH; ++e) d[e] = msk * (double)s[e];
-  tri_solve<CH, T, double>(d, t, *reinterpret_cast<tri_smem<double, T>*>(smem + g * C::SLOT));
+  double* sl = smem + g * C::SLOT;
+  if (sys == 3)
+    band_solve<3, CH, T>(d, t, sl);
+  else if (sys == 4)
+    band_solve<4, CH, T>(d, t, sl);
+  else
+    band_solve<5, CH, T>(d, t, sl);
   if (active) {
 #pragma unroll
     for (int e = 0; e < CH; ++e) dst[(int64_t)row * M + t * CH + e] = (R)d[e];
@@ -1223,13 +1319,13 @@ struct coeffc_cfg {
   static constexpr int CH = elems_for(N, 16, 12);
   static constexpr int T = N / CH;
   static constexpr int P = T >= 64 ? 1 : 64 / T;
-  static constexpr int TRI = (int)sizeof(tri_smem<double, T>) / 8 + 1;
+  static constexpr int TRI = band_smem<double, T>::BYTES / 8 + 1;
   static constexpr int SLOT = (N + 1) > TRI ? (N + 1) : TRI;
 };
 
 template <typename R, int N>
 __global__ void __launch_bounds__((coeffc_cfg<N>::P * coeffc_cfg<N>::T))
-    k_coeff_cols(R* __restrict__ data, int M) {
+    k_coeff_cols(R* __restrict__ data, int M, int sys) {
   using C = coeffc_cfg<N>;
   constexpr int CH = C::CH, T = C::T, SLOT = C::SLOT;
   __shared__ double smem[C::P * SLOT];
@@ -1243,9 +1339,14 @@ __global__ void __launch_bounds__((coeffc_cfg<N>::P * coeffc_cfg<N>::T))
   __syncthreads();
   double d[CH];
 #pragma unroll
-  for (int e = 0; e < CH; ++e) d[e] = 8.0 * smem[g * SLOT + t * CH + e];
+  for (int e = 0; e < CH; ++e) d[e] = band_scale(sys) * smem[g * SLOT + t * CH + e];
   __syncthreads();
-  tri_solve<CH, T, double>(d, t, *reinterpret_cast<tri_smem<double, T>*>(smem + g * SLOT));
+  if (sys == 3)
+    band_solve<3, CH, T>(d, t, smem + g * SLOT);
+  else if (sys == 4)
+    band_solve<4, CH, T>(d, t, smem + g * SLOT);
+  else
+    band_solve<5, CH, T>(d, t, smem + g * SLOT);
 #pragma unroll
   for (int e = 0; e < CH; ++e) smem[g * SLOT + t * CH + e] = d[e];
   __syncthreads();
@@ -1282,8 +1383,12 @@ static hipError_t launch_row_fwd_t(const In* src, int64_t src_ld, cx<R>* X, int 
   using C = rowfwd_cfg<R, In, M>;
   const int G = pick_tile(tile, C::G, nrows);
   const int blocks = (nrows + G - 1) / G;
-  hipLaunchKernelGGL((k_row_fwd<R, In, M>), dim3(blocks, bg ? ngrids : 1), dim3(G * C::T), 0, st, src, src_ld, X,
-                     nrows, nrows, r2m, solve, full, tw, bg);
+  if (solve >= 4)
+    hipLaunchKernelGGL((k_row_fwd<R, In, M, true>), dim3(blocks, bg ? ngrids : 1), dim3(G * C::T), 0, st, src,
+                       src_ld, X, nrows, nrows, r2m, solve, full, tw, bg);
+  else
+    hipLaunchKernelGGL((k_row_fwd<R, In, M>), dim3(blocks, bg ? ngrids : 1), dim3(G * C::T), 0, st, src, src_ld, X,
+                       nrows, nrows, r2m, solve, full, tw, bg);
   return hipGetLastError();
 }
 
@@ -1300,7 +1405,14 @@ static hipError_t launch_col_t(const cx<R>* X, cx<R>* V, int M, int tj, const vo
   const TO* toy = kind == 0 ? (const TO*)ty : nullptr;
   const TC* tcx = kind == 1 ? (const TC*)tx : nullptr;
   const TC* tcy = kind == 1 ? (const TC*)ty : nullptr;
-  if (kind == 1)
+  // modes: 0 = k 1, 1 = k 2, 2 = k 3, 3 = k 4, 4 = k 5 (solve = k for k >= 3)
+  if (solve == 4)
+    hipLaunchKernelGGL((k_col<R, TO, TC, N, 3>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy, r2n,
+                       tw, bg);
+  else if (solve == 5)
+    hipLaunchKernelGGL((k_col<R, TO, TC, N, 4>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy, r2n,
+                       tw, bg);
+  else if (kind == 1)
     hipLaunchKernelGGL((k_col<R, TO, TC, N, 1>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy, r2n,
                        tw, bg);
   else if (solve)
@@ -1498,13 +1610,13 @@ hipError_t sg_launch_check_finite(int prec, const void* x, int64_t n, int* flag,
 }
 
 template <typename R>
-static hipError_t coeff_rows_dispatch(int M, const R* src, R* dst, int nrows, hipStream_t st) {
+static hipError_t coeff_rows_dispatch(int M, const R* src, R* dst, int nrows, int sys, hipStream_t st) {
   switch (M) {
 #define CASE(SZ)                                                                                     \
   case SZ: {                                                                                         \
     using C = coeff_cfg<SZ>;                                                                         \
     hipLaunchKernelGGL((k_coeff_rows<R, SZ>), dim3((nrows + C::G - 1) / C::G), dim3(C::G * C::T), 0, st, src, \
-                       dst, nrows);                                                                 \
+                       dst, nrows, sys);                                                            \
     return hipGetLastError();                                                                       \
   }
     SG_SIZES(CASE)
@@ -1515,13 +1627,13 @@ static hipError_t coeff_rows_dispatch(int M, const R* src, R* dst, int nrows, hi
 }
 
 template <typename R>
-static hipError_t coeff_cols_dispatch(int N, R* data, int M, hipStream_t st) {
+static hipError_t coeff_cols_dispatch(int N, R* data, int M, int sys, hipStream_t st) {
   switch (N) {
 #define CASE(SZ)                                                                                      \
   case SZ: {                                                                                          \
     using C = coeffc_cfg<SZ>;                                                                         \
     const int P = pow2_div(M, C::P);                                                               \
-    hipLaunchKernelGGL((k_coeff_cols<R, SZ>), dim3(M / P), dim3(P * C::T), 0, st, data, M);           \
+    hipLaunchKernelGGL((k_coeff_cols<R, SZ>), dim3(M / P), dim3(P * C::T), 0, st, data, M, sys);      \
     return hipGetLastError();                                                                        \
   }
     SG_SIZES(CASE)
@@ -1531,14 +1643,16 @@ static hipError_t coeff_cols_dispatch(int N, R* data, int M, hipStream_t st) {
   }
 }
 
-hipError_t sg_launch_coeff_rows(int prec, int M, const void* src, void* dst, int nrows, hipStream_t st) {
-  if (prec == 0) return coeff_rows_dispatch<double>(M, (const double*)src, (double*)dst, nrows, st);
-  return coeff_rows_dispatch<float>(M, (const float*)src, (float*)dst, nrows, st);
+hipError_t sg_launch_coeff_rows(int prec, int M, const void* src, void* dst, int nrows, int k, hipStream_t st) {
+  if (k < 3 || k > 5) return hipErrorInvalidValue;
+  if (prec == 0) return coeff_rows_dispatch<double>(M, (const double*)src, (double*)dst, nrows, k, st);
+  return coeff_rows_dispatch<float>(M, (const float*)src, (float*)dst, nrows, k, st);
 }
 
-hipError_t sg_launch_coeff_cols(int prec, int N, void* data, int M, hipStream_t st) {
-  if (prec == 0) return coeff_cols_dispatch<double>(N, (double*)data, M, st);
-  return coeff_cols_dispatch<float>(N, (float*)data, M, st);
+hipError_t sg_launch_coeff_cols(int prec, int N, void* data, int M, int k, hipStream_t st) {
+  if (k < 3 || k > 5) return hipErrorInvalidValue;
+  if (prec == 0) return coeff_cols_dispatch<double>(N, (double*)data, M, k, st);
+  return coeff_cols_dispatch<float>(N, (float*)data, M, k, st);
 }
 
 // ------------------------------------------------- stage twiddle tables --
@@ -1600,7 +1714,14 @@ static hipError_t launch_col_adj_t(const cx<R>* Xx, const cx<R>* Xy, cx<R>* Y, i
   const TO* toy = kind == 0 ? (const TO*)ty : nullptr;
   const TC* tcx = kind == 1 ? (const TC*)tx : nullptr;
   const TC* tcy = kind == 1 ? (const TC*)ty : nullptr;
-  if (kind == 1)
+  // modes: 0 = k 1, 1 = k 2, 2 = k 3, 3 = k 4, 4 = k 5 (solve = k for k >= 3)
+  if (solve == 4)
+    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 3>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy, tcx, tcy,
+                       r2n, tw, bg);
+  else if (solve == 5)
+    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 4>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy, tcx, tcy,
+                       r2n, tw, bg);
+  else if (kind == 1)
     hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 1>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy, tcx, tcy,
                        r2n, tw, bg);
   else if (solve)
@@ -1617,8 +1738,12 @@ static hipError_t launch_row_c2r_t(const cx<R>* Y, R* out, int nrows, int tj, co
                                    const cx<R>* tw, const sg_bgrid* bg, int ngrids, hipStream_t st) {
   using C = rowfwd_cfg<R, R, M>;
   const int G = C::G < nrows ? C::G : nrows;
-  hipLaunchKernelGGL((k_row_c2r<R, R, M>), dim3((nrows + G - 1) / G, bg ? ngrids : 1), dim3(G * C::T), 0, st, Y, out,
-                     nrows, tj, r2m, solve, tw, bg);
+  if (solve >= 4)
+    hipLaunchKernelGGL((k_row_c2r<R, R, M, true>), dim3((nrows + G - 1) / G, bg ? ngrids : 1), dim3(G * C::T), 0, st,
+                       Y, out, nrows, tj, r2m, solve, tw, bg);
+  else
+    hipLaunchKernelGGL((k_row_c2r<R, R, M>), dim3((nrows + G - 1) / G, bg ? ngrids : 1), dim3(G * C::T), 0, st, Y,
+                       out, nrows, tj, r2m, solve, tw, bg);
   return hipGetLastError();
 }
 

@@ -39,7 +39,8 @@ def test_status_strings_and_arg_errors():
     assert "grid" in sg.sg_last_error_message()
     # bad order / sizes / domain / precision / flags: rejected before any device call
     bad = [
-        (sg.sg_grid(64, 64, -1, 1, -1, 1, 4), 0, 0, 2),
+        (sg.sg_grid(64, 64, -1, 1, -1, 1, 6), 0, 0, 2),
+        (sg.sg_grid(64, 64, -1, 1, -1, 1, 0), 0, 0, 2),
         (sg.sg_grid(1, 64, -1, 1, -1, 1, 3), 0, 0, 1),
         (sg.sg_grid(64, 64, 1, -1, -1, 1, 3), 0, 0, 1),
         (sg.sg_grid(64, 64, -1, 1, -1, float("nan"), 3), 0, 0, 1),

@@ -33,7 +33,9 @@ def _sg():
 
 ADJ_CASES = [(1, 16, 16, (-1, 1, -1, 1)), (2, 32, 16, (-1, 1, -1, 1)), (3, 64, 64, (-1, 1, -1, 1)),
              (3, 8, 128, (-1, 1, -0.5, 1.5)), (2, 4, 4, (-1, 1, -1, 1)), (3, 256, 128, (-1, 1, -1, 1)),
-             (3, 96, 48, (-1, 1, -1, 1)), (2, 24, 12, (-1, 1, -1, 1)), (1, 192, 96, (-1, 1, -1, 1))]
+             (3, 96, 48, (-1, 1, -1, 1)), (2, 24, 12, (-1, 1, -1, 1)), (1, 192, 96, (-1, 1, -1, 1)),
+             (4, 32, 64, (-1, 1, -1, 1)), (5, 64, 32, (-1, 1, -0.5, 0.5)), (5, 96, 48, (-1, 1, -1, 1)),
+             (4, 4, 4, (-1, 1, -1, 1)), (5, 256, 128, (-1, 1, -1, 1))]
 
 
 @pytest.mark.parametrize("k,M,N,dom", ADJ_CASES, ids=[f"k{c[0]}-{c[1]}x{c[2]}" for c in ADJ_CASES])
@@ -56,11 +58,11 @@ def test_adjoint_matches_oracle(k, M, N, dom):
         assert err <= tol, (prec, err)
 
 
-@pytest.mark.parametrize("n", [1024, 4096])
-def test_adjoint_identity_full_size(n):
+@pytest.mark.parametrize("n,k", [(1024, 3), (4096, 3), (4096, 4), (4096, 5)])
+def test_adjoint_identity_full_size(n, k):
     sg = _sg()
     import torch
-    plan = sg.Plan([(n, n, -1.0, 1.0, -1.0, 1.0, 3)], sg.SG_FP64)
+    plan = sg.Plan([(n, n, -1.0, 1.0, -1.0, 1.0, k)], sg.SG_FP64)
     try:
         g = torch.Generator(device="cuda").manual_seed(n)
         s = torch.randn(n * n, dtype=torch.float64, device="cuda", generator=g)

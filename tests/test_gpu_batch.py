@@ -25,6 +25,9 @@ GRIDS = [
     (12, 24, -1.0, 1.0, -1.0, 1.0, 1),
     (384, 96, -1.0, 1.0, -0.5, 0.5, 3),
     (128, 64, -1.0, 1.0, -1.0, 1.0, 1),
+    (96, 96, -1.0, 1.0, -1.0, 1.0, 5),
+    (64, 128, -1.0, 1.0, -1.0, 1.0, 4),
+    (96, 96, -1.0, 1.0, -1.0, 1.0, 4),      # same size as the k = 3, 5 grids, own class
 ]
 
 
@@ -77,11 +80,12 @@ def test_batched_equals_single_plans_and_oracle(flags):
             plan.close()
         # classes of equal (nx, ny, order), in order of first appearance
         assert [c[:4] for c in classes] == [(96, 96, 3, 3), (128, 64, 1, 2), (48, 192, 2, 1), (256, 256, 2, 1),
-                                            (12, 24, 1, 1), (384, 96, 3, 1)]
+                                            (12, 24, 1, 1), (384, 96, 3, 1), (96, 96, 5, 1), (64, 128, 4, 1),
+                                            (96, 96, 4, 1)]
         assert all(c[4] >= 1 and c[5] >= 1 and c[6] >= 1 for c in classes)
         sx, sy = _single(GRIDS, prec, sigma)
         assert np.array_equal(bx, sx) and np.array_equal(by, sy)
-        for gi in (0, 3, 4, 6):
+        for gi in (0, 3, 4, 6, 9, 10):
             g = GRIDS[gi]
             a, b = offs[gi], offs[gi + 1]
             rx, ry = oracle.forces(sigma[a:b].reshape(g[1], g[0]), g[6], g[2:6])

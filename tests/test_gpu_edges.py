@@ -23,6 +23,7 @@ def _sg():
 
 
 @pytest.mark.parametrize("grid", [(4, 4, -1.0, 1.0, -1.0, 1.0, 3), (96, 48, -1.0, 1.0, -2.0, 2.0, 2),
+                                  (64, 4, -1.0, 1.0, -1.0, 1.0, 5), (12, 96, -1.0, 1.0, -1.0, 1.0, 4),
                                   (1024, 12, -1.0, 1.0, -1.0, 1.0, 1), (4096, 4, -1.0, 1.0, -1.0, 1.0, 3)])
 def test_zero_density_gives_zero_forces(grid):
     sg = _sg()
@@ -32,7 +33,7 @@ def test_zero_density_gives_zero_forces(grid):
         assert not np.any(fx) and not np.any(fy), prec
 
 
-CORNER_CASES = [(k, M, N) for k in (1, 2, 3) for (M, N) in ((64, 32), (1536, 24), (8, 4096))]
+CORNER_CASES = [(k, M, N) for k in (1, 2, 3, 4, 5) for (M, N) in ((64, 32), (1536, 24), (8, 4096))]
 
 
 @pytest.mark.parametrize("k,M,N", CORNER_CASES, ids=[f"k{c[0]}-{c[1]}x{c[2]}" for c in CORNER_CASES])

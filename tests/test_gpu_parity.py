@@ -31,7 +31,8 @@ def _clumps(k, M, N, domain, seed=2, n=32):
 @pytest.mark.parametrize("k,M,N,dom", [
     (1, 8, 8, (-1, 1, -1, 1)), (2, 16, 8, (-1, 1, -1, 1)), (3, 16, 16, (-1, 1, -1, 1)),
     (3, 32, 64, (-1, 1, -0.5, 1.0)), (2, 64, 64, (-1, 1, -1, 1)), (1, 128, 32, (0, 3, 0, 1)),
-    (3, 256, 256, (-1, 1, -1, 1))])
+    (3, 256, 256, (-1, 1, -1, 1)), (4, 16, 8, (-1, 1, -1, 1)), (5, 32, 64, (-1, 1, -0.5, 1.0)),
+    (4, 64, 64, (-1, 1, -1, 1)), (5, 96, 48, (-1, 1, -2, 2)), (4, 48, 96, (0, 3, 0, 1))])
 def test_weights_match_oracle(k, M, N, dom):
     sg = _sg()
     import torch
@@ -52,7 +53,7 @@ def test_weights_match_oracle(k, M, N, dom):
 
 def test_sample_points_match_oracle():
     sg = _sg()
-    for k in (1, 2, 3):
+    for k in (1, 2, 3, 4, 5):
         grid = (16, 8, -1.0, 1.0, -0.5, 0.5, k)
         plan = sg.Plan([grid], sg.SG_FP64)
         try:
@@ -63,15 +64,16 @@ def test_sample_points_match_oracle():
         assert np.allclose(xs, oxs, rtol=0, atol=1e-15) and np.allclose(ys, oys, rtol=0, atol=1e-15)
 
 
-@pytest.mark.parametrize("M,N", [(4, 4), (16, 16), (64, 32), (8, 256), (256, 256)])
-def test_coeffs_match_oracle(M, N):
+@pytest.mark.parametrize("k", [3, 4, 5])
+@pytest.mark.parametrize("M,N", [(4, 4), (16, 16), (64, 32), (8, 256), (256, 256), (96, 12)])
+def test_coeffs_match_oracle(M, N, k):
     sg = _sg()
     import torch
     rng = np.random.default_rng(M * 1000 + N)
     sigma = rng.standard_normal((N, M))
-    ref = oracle.bspline_coeffs(sigma, 3)
+    ref = oracle.bspline_coeffs(sigma, k)
     for prec, tol in ((sg.SG_FP64, 1e-13), (sg.SG_FP32_SPLIT, 1e-6)):
-        plan = sg.Plan([(M, N, -1.0, 1.0, -1.0, 1.0, 3)], prec)
+        plan = sg.Plan([(M, N, -1.0, 1.0, -1.0, 1.0, k)], prec)
         try:
             c = plan.coeffs(to_dev(sigma.ravel(), plan.dtype))
             torch.cuda.synchronize()
@@ -98,6 +100,19 @@ CASES = [
     (1, 12, 24, (-1, 1, -1, 1), "random"),
     (3, 384, 96, (-1, 1, -0.5, 0.5), "clumps"),
     (3, 12, 12, (-1, 1, -1, 1), "random"),
+    # cubic and quartic splines (k = 4, 5)
+    (4, 64, 64, (-1, 1, -1, 1), "clumps"),
+    (5, 64, 64, (-1, 1, -1, 1), "clumps"),
+    (4, 128, 64, (-1, 1, -0.5, 0.5), "clumps"),
+    (5, 32, 128, (-1, 1, -2, 2), "random"),
+    (4, 4, 4, (-1, 1, -1, 1), "random"),
+    (5, 4, 4, (-1, 1, -1, 1), "random"),
+    (5, 8, 512, (-1, 1, -1, 1), "random"),
+    (4, 256, 256, (-1, 1, -1, 1), "clumps"),
+    (5, 96, 96, (-1, 1, -1, 1), "clumps"),
+    (4, 48, 192, (-1, 1, -1, 1), "random"),
+    (5, 384, 96, (-1, 1, -0.5, 0.5), "clumps"),
+    (4, 12, 12, (-1, 1, -1, 1), "random"),
 ]
 
 
@@ -124,7 +139,7 @@ def test_forces_fp64_and_fp32_match_oracle(k, M, N, dom, kind):
     assert e32 <= FP32_TOL, e32
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("n", [1024, 4096, 1536])
 def test_forces_full_size_sparse_impulses(k, n):
     """Full-size grids: C = a few seeded impulses (sigma = S C, Eq. (sigmaW)),
@@ -151,7 +166,9 @@ def test_forces_full_size_sparse_impulses(k, n):
 
 ANISO = [(k, M, N, dom) for k in (1, 2, 3)
          for (M, N, dom) in ((2048, 2048, (-2.0, 2.0, -1.0, 1.0)), (4096, 1024, (-1.0, 1.0, -1.0, 1.0)),
-                             (1536, 768, (-1.0, 1.0, -0.25, 0.25)))]
+                             (1536, 768, (-1.0, 1.0, -0.25, 0.25)))] + [
+    (4, 2048, 2048, (-2.0, 2.0, -1.0, 1.0)), (5, 1536, 768, (-1.0, 1.0, -0.25, 0.25)),
+    (5, 4096, 1024, (-1.0, 1.0, -1.0, 1.0))]
 
 
 @pytest.mark.parametrize("k,M,N,dom", ANISO, ids=[f"k{c[0]}-{c[1]}x{c[2]}-dx{(c[3][1]-c[3][0])/c[1]/((c[3][3]-c[3][2])/c[2]):g}dy"
