@@ -10,6 +10,9 @@
   the orders of Sec. 3.1 (k for D4; about 2.5 for k = 3 on D3, whose density
   is not smooth enough at the rim); the FP32-split error stays within
   1e-6 max|F| of the FP64 error (its rounding floor).
+* A smooth (Gaussian) disk with a closed-form force, k = 2 .. 5, N = 128 ..
+  512: the FP64 error falls as h^k, so the cubic and quartic splines show
+  their full orders (the disks of Sec. 3 cap every order near 2.5 or 3.5).
 * 1024^2 and 4096^2, k = 3, tapered Gaussian clumps: both paths against the
   oracle's direct sum on seeded sampled cells, and FP32-split against FP64
   over the whole field.
@@ -119,6 +122,35 @@ def test_convergence_sweep(k, n):
     else:
         # k = 3 on D3: limited by the rim, between 2 and 3
         assert all(2.0 < o < 3.2 for o in orders[1:]), orders
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5])
+def test_smooth_disk_orders(k):
+    """The Gaussian disk of tests/smooth_disk.py (a = 0.12, closed-form force):
+    the FP64 path's max error falls as h^k for every order, the cubic and
+    quartic splines included, and the FP32-split path stays within 1e-6
+    max|F| of FP64."""
+    import smooth_disk
+    sg = _sg()
+    a = 0.12
+    sizes = [128, 256, 512]
+    errs = []
+    for N in sizes:
+        xs, ys = oracle.sample_lattice(k, N, N)
+        X, Y = np.meshgrid(xs, ys)
+        sigma = smooth_disk.sigma(X, Y, a)
+        xc = oracle.cell_centres(N, -1.0, 1.0)
+        ax, ay = smooth_disk.force_xy(xc, xc, a)
+        fmax = max(np.abs(ax).max(), np.abs(ay).max())
+        grid = (N, N, -1.0, 1.0, -1.0, 1.0, k)
+        gx, gy = run_forces(grid, sg.SG_FP64, sigma)
+        fx, fy = run_forces(grid, sg.SG_FP32_SPLIT, sigma)
+        errs.append(max(np.abs(gx - ax).max(), np.abs(gy - ay).max()) / fmax)
+        dev = max(np.abs(fx - gx).max(), np.abs(fy - gy).max()) / fmax
+        assert dev <= 1e-6, (N, dev)
+    orders = [oracle.accuracy_order(errs[i], errs[i + 1]) for i in range(len(sizes) - 1)]
+    lo, hi = (k - 0.35, k + 0.35) if k < 5 else (4.7, 5.8)
+    assert all(lo < o < hi for o in orders), (errs, orders)
 
 
 @pytest.mark.parametrize("N,count", [(1024, 1024), (4096, 128)])

@@ -15,7 +15,9 @@
   integral Eq. (Fx_convolution) applied to the spline interpolant on 8x8
   grids, the momentum invariant, the adjoint identity;
 * the analytic disk forces of Sec. 3 against a brute-force quadrature of the
-  disk's force integral, continuity at the rim and the far field.
+  disk's force integral, continuity at the rim and the far field;
+* a smooth (Gaussian) disk's closed-form force against quadrature of its
+  Hankel integral, and the oracle's observed order k on it for k = 2..5.
 """
 import math
 import os
@@ -490,6 +492,42 @@ def _disk_force_brute(n, alpha, R):
 
     return integrate.quad(lambda th: math.cos(th) * inner_out(th), math.pi - tt, math.pi + tt,
                           epsabs=1e-14, epsrel=1e-12, limit=200)[0]
+
+
+def test_smooth_disk_closed_form_against_hankel_quadrature():
+    """The Gaussian disk's closed-form force (tests/smooth_disk.py) against
+    direct quadrature of its Hankel integral."""
+    from scipy.special import j1
+    import smooth_disk
+    a = 0.15
+    for R in (0.01, 0.1, 0.2, 0.35, 0.6, 1.3):
+        f = lambda k: k * a * a * math.exp(-k * k * a * a / 2) * j1(k * R)
+        ref = -2 * math.pi * integrate.quad(f, 0, 60 / a, limit=400, epsabs=1e-14, epsrel=1e-12)[0]
+        assert abs(smooth_disk.force_radial(R, a) - ref) < 1e-10 * max(1.0, abs(ref)), (R, ref)
+    # far field: a point mass 2 pi a^2 (G = 1)
+    R = 3.0
+    assert abs(smooth_disk.force_radial(R, a) / (-2 * math.pi * a * a / R ** 2) - 1) < 1e-2
+
+
+def test_oracle_orders_on_smooth_disk():
+    """On the smooth disk the method's only error is the interpolation of
+    sigma by order-k splines, so the force error falls as h^k: the observed
+    order between N = 64 and 128 is k (k = 2..5; k = 5 comes out a little
+    above 5 at these sizes).  Relative max errors at N = 128: 3.1e-3, 5.7e-5,
+    2.5e-6, 1.3e-7."""
+    import smooth_disk
+    a = 0.12
+    for k in (2, 3, 4, 5):
+        errs = []
+        for N in (32, 64, 128):
+            xs, ys = oracle.sample_lattice(k, N, N)
+            X, Y = np.meshgrid(xs, ys)
+            fx, fy = oracle.forces(smooth_disk.sigma(X, Y, a), k)
+            xc = oracle.cell_centres(N, -1.0, 1.0)
+            ax, ay = smooth_disk.force_xy(xc, xc, a)
+            errs.append(max(np.abs(fx - ax).max(), np.abs(fy - ay).max()))
+        order = oracle.accuracy_order(errs[1], errs[2])
+        assert (k - 0.35 < order < k + 0.35) if k < 5 else (4.7 < order < 5.8), (k, errs, order)
 
 
 @pytest.mark.parametrize("n", [3, 4])
