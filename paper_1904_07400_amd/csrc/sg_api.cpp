@@ -477,13 +477,15 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
     G.M = grids[i].nx;
     G.N = grids[i].ny;
     G.k = grids[i].order;
-    G.kind = (G.k % 2 == 0) ? 1 : 0;  // even k: splines centred on vertices, complex spectra
+    G.kind = (G.k % 2 == 0) ? 1 : 0;  // even k: splines centred on vertices, spectra with a bin phase
     G.hx = (grids[i].x1 - grids[i].x0) / G.M;
     G.hy = (grids[i].y1 - grids[i].y0) / G.N;
     G.off = off;
     off += (int64_t)G.M * G.N;
-    const size_t tab_el = G.kind == 0 ? 8 : 16;  // odd k: one real (FP64 or hi+lo FP32); even k: complex
-    const size_t tab_n = G.kind == 0 ? (size_t)(G.M + 1) * (G.N + 1) : (size_t)(G.M + 1) * 2 * G.N;
+    // one real per bin (FP64 or hi+lo FP32) on a quarter of the lattice; for
+    // even k the bin phase is applied in the column pass
+    const size_t tab_el = 8;
+    const size_t tab_n = (size_t)(G.M + 1) * (G.N + 1);
     // grids of equal size, order and cell shape share one pair of spectra
     const auto key = std::make_tuple(G.M, G.N, G.k, G.hx, G.hy);
     const bool fresh = !spectra.count(key);

@@ -551,26 +551,21 @@ template <typename R, typename TO>
 __device__ __forceinline__ cx<R> mul_iA(cx<R> z, const TO* tab, int idx, R sgn) {
   return apply_iA(z, tab[(unsigned)idx], sgn);
 }
-template <typename R, typename TC>
-__device__ __forceinline__ cx<R> mul_W(cx<R> z, const TC* tab, int idx, bool cj);
-template <>
-__device__ __forceinline__ cx<double> mul_W(cx<double> z, const double2* tab, int idx, bool cj) {
-  const double2 w = tab[(unsigned)idx];
-  return cmul(z, cx<double>{w.x, cj ? -w.y : w.y});
-}
-template <>
-__device__ __forceinline__ cx<float> mul_W(cx<float> z, const float4* tab, int idx, bool cj) {
-  float4 w = tab[(unsigned)idx];  // (re_hi, re_lo, im_hi, im_lo)
-  if (cj) {
-    w.z = -w.z;
-    w.w = -w.w;
-  }
-  return {(z.x * w.x - z.y * w.z) + (z.x * w.y - z.y * w.w), (z.x * w.z + z.y * w.x) + (z.x * w.w + z.y * w.y)};
+// Even k: the spline centres sit half a cell off the cell centres in both
+// directions, so W^d = ph(p, q) i A^d with ph = exp(-i pi (p / 2M + q / 2N))
+// and A^d real (R8); the tables store A^d like the odd-k tables.
+// exp(-i pi frac), from FP64:
+template <typename R>
+__device__ __forceinline__ cx<R> half_cell_phase(double frac) {
+  double sn, cs;
+  sincospi(-frac, &sn, &cs);
+  return cx<R>{(R)cs, (R)sn};
 }
 
 // Product of the column spectrum with W^d (or conj W^d, CJ) at column bin p.
 // half 0: bins q = 2q', half 1: q = 2q'+1.  eps: symmetry of the stored
-// table across q -> 2N - q (+1 for x, -1 for y) for odd k.
+// table across q -> 2N - q for odd k (+1 for x, -1 for y); even k has the
+// opposite one.  kind 1 (even k): ph is the phase of the bin.
 // Odd k: the stored entry of the real table for column bin p, row bin qq of
 // half `half` (row: the table row of bin p), and its sign (+1, or eps past
 // the reflection q -> 2N - q).
@@ -584,20 +579,21 @@ __device__ __forceinline__ R odd_sign(int qq, int half, R eps) {
   return (half == 0 ? qq <= N / 2 : qq < N / 2) ? (R)1 : eps;
 }
 
-template <typename R, typename TO, typename TC, int N, bool CJ = false>
-__device__ __forceinline__ cx<R> spec_mul(cx<R> z, int kind, const TO* to, const TC* tc, int p, int qq,
-                                          int half, R eps) {
-  if (kind == 0) {
-    const TO* row = to + (int64_t)p * (N + 1);
-    const R c = CJ ? (R)-1 : (R)1;  // conj(i A) = -i A
-    if (half == 0) {
-      const bool lo = qq <= N / 2;
-      return mul_iA(z, row, lo ? qq : N - qq, lo ? c : c * eps);
-    }
-    const bool lo = qq < N / 2;
-    return mul_iA(z, row + N / 2 + 1, lo ? qq : N - 1 - qq, lo ? c : c * eps);
+template <typename R, typename TO, int N, bool CJ = false>
+__device__ __forceinline__ cx<R> spec_mul(cx<R> z, int kind, const TO* to, int p, int qq, int half, R eps,
+                                          cx<R> ph) {
+  if (kind == 1) {
+    z = CJ ? cmulc(z, ph) : cmul(z, ph);
+    eps = -eps;
   }
-  return mul_W(z, tc + (int64_t)p * (2 * N), half * N + qq, CJ);
+  const TO* row = to + (int64_t)p * (N + 1);
+  const R c = CJ ? (R)-1 : (R)1;  // conj(i A) = -i A
+  if (half == 0) {
+    const bool lo = qq <= N / 2;
+    return mul_iA(z, row, lo ? qq : N - qq, lo ? c : c * eps);
+  }
+  const bool lo = qq < N / 2;
+  return mul_iA(z, row + N / 2 + 1, lo ? qq : N - 1 - qq, lo ? c : c * eps);
 }
 
 // Product of one half of the column spectrum with W^d of one component
@@ -605,14 +601,18 @@ __device__ __forceinline__ cx<R> spec_mul(cx<R> z, int kind, const TO* to, const
 // workgroup holds the packed column 0 (uniform over the workgroup); packed:
 // this slice is column 0, whose spectrum U carries bins p = 0 and p = M:
 // C_0 = (U(q) + conj U(-q))/2, C_M = (U(q) - conj U(-q))/(2i), and the
-// products are re-packed as G_0 + i G_M.
-template <typename R, typename TO, typename TC, int N, int E, int T>
+// products are re-packed as G_0 + i G_M.  Even k: w2n = exp(-i pi q'/N),
+// php = exp(-i pi c / 2M), rho = exp(-i pi / 2N) make the bin phases.
+template <typename R, typename TO, int N, int E, int T>
 __device__ __forceinline__ void col_product(const cx<R>* f, cx<R>* g, int half, bool exch, bool packed, cx<R>* lds,
-                                            int kind, const TO* to, const TC* tc, R eps, int c, int M, int t) {
+                                            int kind, const TO* to, R eps, int c, int M, int t, const cx<R>* w2n,
+                                            cx<R> php, cx<R> rho) {
+  const cx<R> phh = half ? cmul(php, rho) : php;  // column and half part of the phase
   if (!exch) {
     // no packed column in this workgroup: independent loads, no branches
 #pragma unroll
-    for (int e = 0; e < E; ++e) g[e] = spec_mul<R, TO, TC, N>(f[e], kind, to, tc, c, t + e * T, half, eps);
+    for (int e = 0; e < E; ++e)
+      g[e] = spec_mul<R, TO, N>(f[e], kind, to, c, t + e * T, half, eps, cmul(w2n[e], phh));
     return;
   }
 #pragma unroll
@@ -628,13 +628,16 @@ __device__ __forceinline__ void col_product(const cx<R>* f, cx<R>* g, int half, 
       const cx<R> u = f[e], um = conj(lds[pad(qm)]);
       const cx<R> c0v{(R)0.5 * (u.x + um.x), (R)0.5 * (u.y + um.y)};
       const cx<R> cmv{(R)0.5 * (u.y - um.y), (R)-0.5 * (u.x - um.x)};
-      const cx<R> w0 = spec_mul<R, TO, TC, N>(c0v, kind, to, tc, 0, qq, half, eps);
-      const cx<R> wm = spec_mul<R, TO, TC, N>(cmv, kind, to, tc, M, qq, half, eps);
+      // phases of bins p = 0 (1) and p = M (-i) times that of row bin q
+      const cx<R> ph0 = half ? cmul(w2n[e], rho) : w2n[e];
+      const cx<R> w0 = spec_mul<R, TO, N>(c0v, kind, to, 0, qq, half, eps, ph0);
+      const cx<R> wm = spec_mul<R, TO, N>(cmv, kind, to, M, qq, half, eps, cx<R>{ph0.y, -ph0.x});
       g[e] = cx<R>{w0.x - wm.y, w0.y + wm.x};
     }
   } else {
 #pragma unroll
-    for (int e = 0; e < E; ++e) g[e] = spec_mul<R, TO, TC, N>(f[e], kind, to, tc, c, t + e * T, half, eps);
+    for (int e = 0; e < E; ++e)
+      g[e] = spec_mul<R, TO, N>(f[e], kind, to, c, t + e * T, half, eps, cmul(w2n[e], phh));
   }
   __syncthreads();
 }
@@ -642,11 +645,11 @@ __device__ __forceinline__ void col_product(const cx<R>* f, cx<R>* g, int half, 
 // MODE: 0 = k 1 (real tables, no solve), 1 = k 2 (complex tables), 2 = k 3
 // (real tables, y-solve), 3 = k 4 (complex tables, y-solve), 4 = k 5 (real
 // tables, pentadiagonal y-solve)
-template <typename R, typename TO, typename TC, int N, int MODE>
+template <typename R, typename TO, int N, int MODE>
 __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     SG_WPE(R, COL) k_col(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
-          const TO* __restrict__ toy, const TC* __restrict__ tcx, const TC* __restrict__ tcy,
-          const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ tw, const sg_bgrid* __restrict__ bg) {
+          const TO* __restrict__ toy, const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ tw,
+          const sg_bgrid* __restrict__ bg) {
   constexpr int kind = (MODE == 1 || MODE == 3) ? 1 : 0;
   constexpr bool solve = MODE >= 2;
   constexpr int SYS = MODE == 2 ? 3 : (MODE == 3 ? 4 : 5);  // order of the y-solve
@@ -654,13 +657,8 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     const sg_bgrid d = grid_desc(bg);
     X = reinterpret_cast<const cx<R>*>(d.X);
     V = reinterpret_cast<cx<R>*>(d.V);
-    if (kind == 0) {
-      tox = reinterpret_cast<const TO*>(d.tabx);
-      toy = reinterpret_cast<const TO*>(d.taby);
-    } else {
-      tcx = reinterpret_cast<const TC*>(d.tabx);
-      tcy = reinterpret_cast<const TC*>(d.taby);
-    }
+    tox = reinterpret_cast<const TO*>(d.tabx);
+    toy = reinterpret_cast<const TO*>(d.taby);
   }
   using C = col_cfg<R, N>;
   constexpr int E = C::E, T = C::T, LL = C::SLOT, NBUF = C::NBUF;
@@ -677,11 +675,11 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
   cx<R> a[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) a[e] = col[(unsigned)(solve ? t * E + e : t + e * T)];
-  // Odd k with four exchange buffers: every table entry of the four products
-  // is loaded here, after the column (loads complete in order), so that
-  // their latency overlaps the solve and the forward transforms (in order
-  // x even, y even, x odd, y odd).
-  constexpr bool pre = (kind == 0) && (NBUF == 4);
+  // With four exchange buffers: every table entry of the four products is
+  // loaded here, after the column (loads complete in order), so that their
+  // latency overlaps the solve and the forward transforms (in order x even,
+  // y even, x odd, y odd).
+  constexpr bool pre = NBUF == 4;
   TO tv[pre ? 4 : 1][pre ? E : 1];
   if constexpr (pre) {
     // unconditional (unused by the packed workgroup), so that the waits
@@ -698,6 +696,12 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
   cx<R> w2n[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) w2n[e] = r2n[(unsigned)(t + e * T)];
+  // even k: phase of column bin c and the extra phase of the odd row bins
+  cx<R> php{(R)1, (R)0}, rho{(R)1, (R)0};
+  if constexpr (kind == 1) {
+    php = half_cell_phase<R>((double)c / (2.0 * M));
+    rho = half_cell_phase<R>(1.0 / (2.0 * N));
+  }
   // with four buffers the forward transforms alternate between buffers
   // {0, 1} and {2, 3} (one barrier per exchange)
   constexpr bool pp = (NBUF == 4) && SG_COL_PP;
@@ -762,20 +766,30 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     bool done = false;
     if constexpr (pre) {
       if (!exch) {
+        if constexpr (kind == 1) {
+          // even k: the bin phases, shared by both components
+          const cx<R> pho = cmul(php, rho);
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            fe[e] = cmul(fe[e], cmul(w2n[e], php));
+            fo[e] = cmul(fo[e], cmul(w2n[e], pho));
+          }
+        }
+        constexpr R ex = kind == 1 ? (R)-1 : (R)1;  // reflection sign of the x table
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int e = 0; e < E; ++e)
             g4[i][e] = apply_iA((i >> 1) ? fo[e] : fe[e], tv[i][e],
-                                odd_sign<R, N>(t + e * T, i >> 1, (i & 1) ? (R)-1 : (R)1));
+                                odd_sign<R, N>(t + e * T, i >> 1, (i & 1) ? -ex : ex));
         done = true;
       }
     }
     if (!done) {
-      col_product<R, TO, TC, N, E, T>(fe, g4[0], 0, exch, packed, lds, kind, tox, tcx, (R)1, c, M, t);
-      col_product<R, TO, TC, N, E, T>(fe, g4[1], 0, exch, packed, lds, kind, toy, tcy, (R)-1, c, M, t);
-      col_product<R, TO, TC, N, E, T>(fo, g4[2], 1, exch, packed, lds, kind, tox, tcx, (R)1, c, M, t);
-      col_product<R, TO, TC, N, E, T>(fo, g4[3], 1, exch, packed, lds, kind, toy, tcy, (R)-1, c, M, t);
+      col_product<R, TO, N, E, T>(fe, g4[0], 0, exch, packed, lds, kind, tox, (R)1, c, M, t, w2n, php, rho);
+      col_product<R, TO, N, E, T>(fe, g4[1], 0, exch, packed, lds, kind, toy, (R)-1, c, M, t, w2n, php, rho);
+      col_product<R, TO, N, E, T>(fo, g4[2], 1, exch, packed, lds, kind, tox, (R)1, c, M, t, w2n, php, rho);
+      col_product<R, TO, N, E, T>(fo, g4[3], 1, exch, packed, lds, kind, toy, (R)-1, c, M, t, w2n, php, rho);
     }
     fftn<true, N, T, 4>(g4, lds, LL, tw, t);
 #pragma unroll
@@ -792,8 +806,8 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     for (int half = 0; half < 2; ++half) {
       const cx<R>* f = half ? fo : fe;
       cx<R> gx[E], gy[E];
-      col_product<R, TO, TC, N, E, T>(f, gx, half, exch, packed, lds, kind, tox, tcx, (R)1, c, M, t);
-      col_product<R, TO, TC, N, E, T>(f, gy, half, exch, packed, lds, kind, toy, tcy, (R)-1, c, M, t);
+      col_product<R, TO, N, E, T>(f, gx, half, exch, packed, lds, kind, tox, (R)1, c, M, t, w2n, php, rho);
+      col_product<R, TO, N, E, T>(f, gy, half, exch, packed, lds, kind, toy, (R)-1, c, M, t, w2n, php, rho);
       fft2<true, N, T>(gx, gy, lds, lds2, tw, t);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -818,8 +832,8 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
 #pragma unroll
       for (int comp = 0; comp < 2; ++comp) {
         cx<R> g[E];
-        col_product<R, TO, TC, N, E, T>(f, g, half, exch, packed, lds, kind, comp ? toy : tox, comp ? tcy : tcx,
-                                        comp ? (R)-1 : (R)1, c, M, t);
+        col_product<R, TO, N, E, T>(f, g, half, exch, packed, lds, kind, comp ? toy : tox, comp ? (R)-1 : (R)1, c,
+                                    M, t, w2n, php, rho);
         fft<true, N, T>(g, lds, tw, t);
         cx<R>* acc = comp ? accy : accx;
 #pragma unroll
@@ -949,17 +963,20 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
 // the conjugate spectra, sums the two components, inverts cropped to N rows,
 // applies the y-solve and writes the packed row spectra of gC in tiles of
 // tj rows: bin p of row j at ((j/tj*2 + p%2)*(M/2) + p/2)*tj + j%tj.
-template <typename R, typename TO, typename TC, int N, int E, int T>
+// Even k: r2n = exp(-i pi q'/N), php and rho as in col_product.
+template <typename R, typename TO, int N, int E, int T>
 __device__ __forceinline__ void col_products_adj(const cx<R>* fx, const cx<R>* fy, cx<R>* h, int half, bool exch,
                                                  bool packed, cx<R>* lds, int kind, const TO* tox, const TO* toy,
-                                                 const TC* tcx, const TC* tcy, int c, int M, int t) {
+                                                 int c, int M, int t, const cx<R>* r2n, cx<R> php, cx<R> rho) {
+  const cx<R> phh = half ? cmul(php, rho) : php;
   if (!exch) {
     // no packed column in this workgroup: independent loads, no branches
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int qq = t + e * T;
-      h[e] = spec_mul<R, TO, TC, N, true>(fx[e], kind, tox, tcx, c, qq, half, (R)1) +
-             spec_mul<R, TO, TC, N, true>(fy[e], kind, toy, tcy, c, qq, half, (R)-1);
+      const cx<R> ph = kind == 1 ? cmul(r2n[(unsigned)qq], phh) : cx<R>{(R)1, (R)0};
+      h[e] = spec_mul<R, TO, N, true>(fx[e], kind, tox, c, qq, half, (R)1, ph) +
+             spec_mul<R, TO, N, true>(fy[e], kind, toy, c, qq, half, (R)-1, ph);
     }
     return;
   }
@@ -992,30 +1009,33 @@ __device__ __forceinline__ void col_products_adj(const cx<R>* fx, const cx<R>* f
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int qq = t + e * T;
+    const cx<R> w = kind == 1 ? r2n[(unsigned)qq] : cx<R>{(R)1, (R)0};
     if (packed) {
       const cx<R> ux = fx[e], uy = fy[e];
       const cx<R> x0v{(R)0.5 * (ux.x + umx[e].x), (R)0.5 * (ux.y + umx[e].y)};
       const cx<R> xmv{(R)0.5 * (ux.y - umx[e].y), (R)-0.5 * (ux.x - umx[e].x)};
       const cx<R> y0v{(R)0.5 * (uy.x + umy[e].x), (R)0.5 * (uy.y + umy[e].y)};
       const cx<R> ymv{(R)0.5 * (uy.y - umy[e].y), (R)-0.5 * (uy.x - umy[e].x)};
-      const cx<R> h0 = spec_mul<R, TO, TC, N, true>(x0v, kind, tox, tcx, 0, qq, half, (R)1) +
-                       spec_mul<R, TO, TC, N, true>(y0v, kind, toy, tcy, 0, qq, half, (R)-1);
-      const cx<R> hm = spec_mul<R, TO, TC, N, true>(xmv, kind, tox, tcx, M, qq, half, (R)1) +
-                       spec_mul<R, TO, TC, N, true>(ymv, kind, toy, tcy, M, qq, half, (R)-1);
+      const cx<R> ph0 = half ? cmul(w, rho) : w;  // bins p = 0 and p = M (-i ph0)
+      const cx<R> phm{ph0.y, -ph0.x};
+      const cx<R> h0 = spec_mul<R, TO, N, true>(x0v, kind, tox, 0, qq, half, (R)1, ph0) +
+                       spec_mul<R, TO, N, true>(y0v, kind, toy, 0, qq, half, (R)-1, ph0);
+      const cx<R> hm = spec_mul<R, TO, N, true>(xmv, kind, tox, M, qq, half, (R)1, phm) +
+                       spec_mul<R, TO, N, true>(ymv, kind, toy, M, qq, half, (R)-1, phm);
       h[e] = cx<R>{h0.x - hm.y, h0.y + hm.x};
     } else {
-      h[e] = spec_mul<R, TO, TC, N, true>(fx[e], kind, tox, tcx, c, qq, half, (R)1) +
-             spec_mul<R, TO, TC, N, true>(fy[e], kind, toy, tcy, c, qq, half, (R)-1);
+      const cx<R> ph = cmul(w, phh);
+      h[e] = spec_mul<R, TO, N, true>(fx[e], kind, tox, c, qq, half, (R)1, ph) +
+             spec_mul<R, TO, N, true>(fy[e], kind, toy, c, qq, half, (R)-1, ph);
     }
   }
 }
 
-template <typename R, typename TO, typename TC, int N, int MODE>
+template <typename R, typename TO, int N, int MODE>
 __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     k_col_adj(const cx<R>* __restrict__ Xx, const cx<R>* __restrict__ Xy, cx<R>* __restrict__ Y, int M, int tj,
-              const TO* __restrict__ tox, const TO* __restrict__ toy, const TC* __restrict__ tcx,
-              const TC* __restrict__ tcy, const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ tw,
-              const sg_bgrid* __restrict__ bg) {
+              const TO* __restrict__ tox, const TO* __restrict__ toy, const cx<R>* __restrict__ r2n,
+              const cx<R>* __restrict__ tw, const sg_bgrid* __restrict__ bg) {
   constexpr int kind = (MODE == 1 || MODE == 3) ? 1 : 0;
   constexpr bool solve = MODE >= 2;
   constexpr int SYS = MODE == 2 ? 3 : (MODE == 3 ? 4 : 5);  // order of the y-solve
@@ -1024,13 +1044,8 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     Xx = reinterpret_cast<const cx<R>*>(d.X);
     Xy = reinterpret_cast<const cx<R>*>(d.V);
     Y = reinterpret_cast<cx<R>*>(d.V) + (int64_t)M * N;
-    if (kind == 0) {
-      tox = reinterpret_cast<const TO*>(d.tabx);
-      toy = reinterpret_cast<const TO*>(d.taby);
-    } else {
-      tcx = reinterpret_cast<const TC*>(d.tabx);
-      tcy = reinterpret_cast<const TC*>(d.taby);
-    }
+    tox = reinterpret_cast<const TO*>(d.tabx);
+    toy = reinterpret_cast<const TO*>(d.taby);
   }
   using C = col_cfg<R, N>;
   constexpr int E = C::E, T = C::T, LL = C::SLOT;
@@ -1040,6 +1055,11 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
   const int c0 = xcd_tile(blockIdx.x, gridDim.x) * P, c = c0 + g;
   cx<R>* lds = smem + g * LL;
   const bool packed = (c == 0);
+  cx<R> php{(R)1, (R)0}, rho{(R)1, (R)0};  // even k: as in k_col
+  if constexpr (kind == 1) {
+    php = half_cell_phase<R>((double)c / (2.0 * M));
+    rho = half_cell_phase<R>(1.0 / (2.0 * N));
+  }
   cx<R> ax[E], ay[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -1059,7 +1079,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     fft<false, N, T>(fx, lds, tw, t);
     fft<false, N, T>(fy, lds, tw, t);
     cx<R> h[E];
-    col_products_adj<R, TO, TC, N, E, T>(fx, fy, h, half, c0 == 0, packed, lds, kind, tox, toy, tcx, tcy, c, M, t);
+    col_products_adj<R, TO, N, E, T>(fx, fy, h, half, c0 == 0, packed, lds, kind, tox, toy, c, M, t, r2n, php, rho);
     fft<true, N, T>(h, lds, tw, t);
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = half ? acc[e] + cmulc(h[e], r2n[(unsigned)(t + e * T)]) : h[e];
@@ -1199,15 +1219,6 @@ __device__ __forceinline__ void put_odd(void* tab, int fp32, int64_t idx, double
     reinterpret_cast<double*>(tab)[idx] = v;
   }
 }
-__device__ __forceinline__ void put_cplx(void* tab, int fp32, int64_t idx, cx<double> v) {
-  if (fp32) {
-    const float rh = (float)v.x, ih = (float)v.y;
-    reinterpret_cast<float4*>(tab)[idx] =
-        make_float4(rh, (float)(v.x - (double)rh), ih, (float)(v.y - (double)ih));
-  } else {
-    reinterpret_cast<double2*>(tab)[idx] = make_double2(v.x, v.y);
-  }
-}
 
 template <int N>
 __global__ void __launch_bounds__((spec_cfg<N>::T))
@@ -1253,12 +1264,16 @@ __global__ void __launch_bounds__((spec_cfg<N>::T))
       }
       for (int h = 0; h < nv; ++h) {
         const cx<double> w = vals[h] * scale;
-        if (kind == 0) {
-          if (half == 0 && qq <= N / 2) put_odd(tab, fp32, (int64_t)rows[h] * (N + 1) + qq, w.y);
-          if (half == 1 && qq < N / 2) put_odd(tab, fp32, (int64_t)rows[h] * (N + 1) + N / 2 + 1 + qq, w.y);
-        } else {
-          put_cplx(tab, fp32, (int64_t)rows[h] * (2 * N) + half * N + qq, w);
+        // odd k: W = i A; even k: W = ph i A with the phase of bin (p, q),
+        // ph = exp(-i pi (p / 2M + q / 2N)), so A = Im(W conj(ph))
+        double a = w.y;
+        if (kind == 1) {
+          double sn, cs;
+          sincospi((double)rows[h] / (2.0 * M) + (double)(2 * qq + half) / (2.0 * N), &sn, &cs);
+          a = w.y * cs + w.x * sn;
         }
+        if (half == 0 && qq <= N / 2) put_odd(tab, fp32, (int64_t)rows[h] * (N + 1) + qq, a);
+        if (half == 1 && qq < N / 2) put_odd(tab, fp32, (int64_t)rows[h] * (N + 1) + N / 2 + 1 + qq, a);
       }
     }
     __syncthreads();
@@ -1360,7 +1375,6 @@ __global__ void __launch_bounds__((coeffc_cfg<N>::P * coeffc_cfg<N>::T))
 template <typename R>
 struct tabs {
   using odd = typename std::conditional<sizeof(R) == 4, float2, double>::type;
-  using cplx = typename std::conditional<sizeof(R) == 4, float4, double2>::type;
 };
 
 #ifndef SG_SIZES
@@ -1398,28 +1412,25 @@ static hipError_t launch_col_t(const cx<R>* X, cx<R>* V, int M, int tj, const vo
                                int tile, hipStream_t st) {
   using C = col_cfg<R, N>;
   using TO = typename tabs<R>::odd;
-  using TC = typename tabs<R>::cplx;
   const int P = pow2_div(M, (tile > 0 && tile <= C::P) ? tile : C::P);
   const dim3 grid(M / P, bg ? ngrids : 1);
-  const TO* tox = kind == 0 ? (const TO*)tx : nullptr;
-  const TO* toy = kind == 0 ? (const TO*)ty : nullptr;
-  const TC* tcx = kind == 1 ? (const TC*)tx : nullptr;
-  const TC* tcy = kind == 1 ? (const TC*)ty : nullptr;
+  const TO* tox = (const TO*)tx;
+  const TO* toy = (const TO*)ty;
   // modes: 0 = k 1, 1 = k 2, 2 = k 3, 3 = k 4, 4 = k 5 (solve = k for k >= 3)
   if (solve == 4)
-    hipLaunchKernelGGL((k_col<R, TO, TC, N, 3>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy, r2n,
+    hipLaunchKernelGGL((k_col<R, TO, N, 3>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
                        tw, bg);
   else if (solve == 5)
-    hipLaunchKernelGGL((k_col<R, TO, TC, N, 4>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy, r2n,
+    hipLaunchKernelGGL((k_col<R, TO, N, 4>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
                        tw, bg);
   else if (kind == 1)
-    hipLaunchKernelGGL((k_col<R, TO, TC, N, 1>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy, r2n,
+    hipLaunchKernelGGL((k_col<R, TO, N, 1>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
                        tw, bg);
   else if (solve)
-    hipLaunchKernelGGL((k_col<R, TO, TC, N, 2>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy, r2n,
+    hipLaunchKernelGGL((k_col<R, TO, N, 2>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
                        tw, bg);
   else
-    hipLaunchKernelGGL((k_col<R, TO, TC, N, 0>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, tcx, tcy, r2n,
+    hipLaunchKernelGGL((k_col<R, TO, N, 0>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
                        tw, bg);
   return hipGetLastError();
 }
@@ -1707,28 +1718,25 @@ static hipError_t launch_col_adj_t(const cx<R>* Xx, const cx<R>* Xy, cx<R>* Y, i
                                    const sg_bgrid* bg, int ngrids, hipStream_t st) {
   using C = col_cfg<R, N>;
   using TO = typename tabs<R>::odd;
-  using TC = typename tabs<R>::cplx;
   const int P = pow2_div(M, C::P);
   const dim3 grid(M / P, bg ? ngrids : 1);
-  const TO* tox = kind == 0 ? (const TO*)tx : nullptr;
-  const TO* toy = kind == 0 ? (const TO*)ty : nullptr;
-  const TC* tcx = kind == 1 ? (const TC*)tx : nullptr;
-  const TC* tcy = kind == 1 ? (const TC*)ty : nullptr;
+  const TO* tox = (const TO*)tx;
+  const TO* toy = (const TO*)ty;
   // modes: 0 = k 1, 1 = k 2, 2 = k 3, 3 = k 4, 4 = k 5 (solve = k for k >= 3)
   if (solve == 4)
-    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 3>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy, tcx, tcy,
+    hipLaunchKernelGGL((k_col_adj<R, TO, N, 3>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy,
                        r2n, tw, bg);
   else if (solve == 5)
-    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 4>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy, tcx, tcy,
+    hipLaunchKernelGGL((k_col_adj<R, TO, N, 4>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy,
                        r2n, tw, bg);
   else if (kind == 1)
-    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 1>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy, tcx, tcy,
+    hipLaunchKernelGGL((k_col_adj<R, TO, N, 1>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy,
                        r2n, tw, bg);
   else if (solve)
-    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 2>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy, tcx, tcy,
+    hipLaunchKernelGGL((k_col_adj<R, TO, N, 2>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy,
                        r2n, tw, bg);
   else
-    hipLaunchKernelGGL((k_col_adj<R, TO, TC, N, 0>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy, tcx, tcy,
+    hipLaunchKernelGGL((k_col_adj<R, TO, N, 0>), grid, dim3(P * C::T), 0, st, Xx, Xy, Y, M, tj, tox, toy,
                        r2n, tw, bg);
   return hipGetLastError();
 }
