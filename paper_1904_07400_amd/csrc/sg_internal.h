@@ -31,7 +31,9 @@ hipError_t sg_launch_row_fwd(int prec, int M, const void* src, int64_t ld, void*
 // largest tile (rows or columns per workgroup) of a pass: 0 = A, 1 = B, 2 = C
 int sg_max_tile(int prec, int pass, int len);
 // X: column-major row spectra (bin p of row j at X[p*N + j]); V: tiles of
-// tj rows (sg_row_tile), the layout the inverse row pass reads
+// tj rows (sg_row_tile), the layout the inverse row pass reads.  kind: 0 for
+// odd k (tables of A, W = i A), 1 for even k (W = ph i A, ph the bin's
+// half-cell phase); tx, ty are the quarter tables of A in either case.
 hipError_t sg_launch_col(int prec, int N, const void* X, void* V, int M, int tj, const void* tx, const void* ty,
                          int kind, const void* r2n, int solve, const void* tw, const sg_bgrid* bg, int ngrids,
                          int tile, hipStream_t st);

@@ -536,7 +536,8 @@ struct col_cfg {
   static constexpr int P = P0 < PL ? P0 : PL;
 };
 
-// spectrum lookup helpers: odd k (real tables, W = i A) and k = 2 (complex)
+// spectrum lookup helpers: real tables A with W = i A (odd k) or W = ph i A
+// (even k, ph the bin's half-cell phase)
 // z * (i A sgn) with a table entry A (double, or a float hi+lo pair)
 __device__ __forceinline__ cx<double> apply_iA(cx<double> z, double a, double sgn) {
   a *= sgn;
@@ -642,9 +643,8 @@ __device__ __forceinline__ void col_product(const cx<R>* f, cx<R>* g, int half, 
   __syncthreads();
 }
 
-// MODE: 0 = k 1 (real tables, no solve), 1 = k 2 (complex tables), 2 = k 3
-// (real tables, y-solve), 3 = k 4 (complex tables, y-solve), 4 = k 5 (real
-// tables, pentadiagonal y-solve)
+// MODE: 0 = k 1 (no solve), 1 = k 2 (phased tables), 2 = k 3 (y-solve), 3 =
+// k 4 (phased tables, y-solve), 4 = k 5 (pentadiagonal y-solve)
 template <typename R, typename TO, int N, int MODE>
 __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     SG_WPE(R, COL) k_col(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
