@@ -268,6 +268,63 @@ def aniso_bench(sg, torch, k, steps, warmup):
             "rel_err_vs_fp64": err, "meets_1e-6": bool(err <= 1e-6)}
 
 
+def grad_bench(sg, torch, steps, warmup):
+    """Differentiation at scale: one plan of a 4096^2 grid (the largest
+    supported size) with four 2048^2 grids alongside, k = 3, 64 seeded clumps
+    per grid.  A step is the forward forces, the loss residual 2 (F - F_t) and
+    the adjoint (dL/dsigma for L = sum |F - F_t|^2, F_t from perturbed
+    clumps).  FP32-split timed; its gradient checked against the FP64 plan's
+    per grid."""
+    import workloads
+    grids = [(4096, 4096, -1.0, 1.0, -1.0, 1.0, 3)] + [(2048, 2048, -1.0, 1.0, -1.0, 1.0, 3)] * 4
+    out = {"workload": "4096^2 + 4 x 2048^2 in one plan, k=3, 64 seeded clumps each; forward + adjoint of "
+                       "L = sum |F - F_t|^2 (F_t from perturbed clumps)"}
+    grads = {}
+    for prec in (sg.SG_FP64, sg.SG_FP32_SPLIT):
+        plan = sg.Plan(grids, prec)
+        try:
+            sig = torch.empty(plan.total, dtype=plan.dtype, device="cuda")
+            tsig = torch.empty_like(sig)
+            for gi in range(len(grids)):
+                xs, ys = plan.sample_points(gi)
+                params = workloads.clump_params(5 + gi, 64)
+                a, b = plan.offsets[gi], plan.offsets[gi + 1]
+                sig[a:b] = workloads.clump_sigma_torch(params, xs, ys).ravel().to(plan.dtype)
+                tsig[a:b] = workloads.clump_sigma_torch(workloads.perturb_clumps(params, 55), xs, ys).ravel().to(
+                    plan.dtype)
+            tx, ty = (t.clone() for t in plan.forces(tsig))
+            fx, fy, g = plan.empty(), plan.empty(), plan.empty()
+
+            def step():
+                plan.forces(sig, fx, fy)
+                plan.adjoint(2 * (fx - tx), 2 * (fy - ty), g)
+
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            grads[prec] = g.double().cpu().numpy()
+            key = "fp64_ms_per_step" if prec == sg.SG_FP64 else "ms_per_step"
+            out[key] = round(ms, 4)
+            if prec == sg.SG_FP32_SPLIT:
+                out["value"] = plan.total / (ms * 1e-3)
+                out["unit"] = "cells/s (forward + adjoint)"
+                offs = plan.offsets
+        finally:
+            plan.close()
+    g64, g32 = grads[sg.SG_FP64], grads[sg.SG_FP32_SPLIT]
+    out["rel_err_vs_fp64_per_grid"] = [
+        float(abs(g32[offs[i]:offs[i + 1]] - g64[offs[i]:offs[i + 1]]).max() / abs(g64[offs[i]:offs[i + 1]]).max())
+        for i in range(len(grids))]
+    return out
+
+
 def orders_bench(sg, torch, n, steps, warmup):
     """The cubic and quartic splines (k = 4, 5) on the headline grid: n x n
     cells on [-1,1]^2, the same clump recipe, FP32-split timed and checked
@@ -341,6 +398,7 @@ def main():
     ap.add_argument("--batch-only", action="store_true", help="only the batched-disks measurement")
     ap.add_argument("--no-aniso", action="store_true", help="skip the anisotropic-cell measurement")
     ap.add_argument("--no-orders", action="store_true", help="skip the k = 4, 5 measurement")
+    ap.add_argument("--no-grad", action="store_true", help="skip the forward + adjoint measurement")
     ap.add_argument("--prec", choices=["both", "fp32", "fp64"], default="both",
                     help="both (default, the metric) or one path only (profiling)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -440,6 +498,8 @@ def main():
         line["anisotropic"] = aniso_bench(sg, torch, k, max(args.steps // 2, 3), 2)
     if not args.no_orders:
         line["higher_orders"] = orders_bench(sg, torch, n, max(args.steps // 2, 3), 2)
+    if not args.no_grad:
+        line["differentiation"] = grad_bench(sg, torch, max(args.steps // 2, 3), 2)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(n, k, sigma, args.cpu_sample)
     print(json.dumps(line), flush=True)
