@@ -1,10 +1,10 @@
 // Device kernels of the thin-disk self-gravity library (gfx950).
 //
 // Per-step path for one M x N grid (sigma row-major [N][M], x fastest):
-//   pass A (rows):    [k=3: x-solve, Eq. (C_system)] + real FFT of the row
+//   pass A (rows):    [k >= 3: x-solve, Eq. (C_system)] + real FFT of the row
 //                     zero-padded to 2M, written as M packed complex bins
 //                     (bin 0 carries the real bins 0 and M);
-//   pass B (columns): [k=3: y-solve, Eq. (z_system), on the row spectra] +
+//   pass B (columns): [k >= 3: y-solve, Eq. (z_system), on the row spectra] +
 //                     FFT of the column zero-padded to 2N, products with the
 //                     spectra of w^x and w^y (convolution theorem), two
 //                     inverse FFTs cropped to N outputs, written as the
@@ -1202,8 +1202,9 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, R, M>::G * rowfwd_cfg<R, R, M>:
 // the first radix-2 butterfly) of the row spectra of the padded weight
 // table, then the stored form of W^d(p, q) / (4MN):
 //   odd k : A = Im W (W is purely imaginary), q in [0, N], split by parity;
-//   k = 2 : W itself for every q in [0, 2N), split by parity.
-// Output element type: double / double2 (FP64 plans) or hi+lo floats.
+//   even k: A = Im(W conj(ph)), ph = exp(-i pi (p / 2M + q / 2N)) the
+//           half-cell phase, on the same quarter.
+// Output element type: double (FP64 plans) or a hi+lo float pair.
 template <int N>
 struct spec_cfg {
   static constexpr int E = elems_for(N, 8, SG_E3);
