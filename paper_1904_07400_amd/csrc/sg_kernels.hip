@@ -553,8 +553,11 @@ __device__ __forceinline__ cx<R> mul_iA(cx<R> z, const TO* tab, int idx, R sgn) 
   return apply_iA(z, tab[(unsigned)idx], sgn);
 }
 // Even k: the spline centres sit half a cell off the cell centres in both
-// directions, so W^d = ph(p, q) i A^d with ph = exp(-i pi (p / 2M + q / 2N))
-// and A^d real (R8); the tables store A^d like the odd-k tables.
+// directions.  The padded weight table is then odd (force direction) and
+// even (across) about that centre, over the whole period once its slots
+// m = M, n = N hold the mirrored values, so W^d = ph(p, q) i A^d with
+// ph = exp(-i pi (p / 2M + q / 2N)) and A^d real; the tables store A^d like
+// the odd-k tables.
 // exp(-i pi frac), from FP64:
 template <typename R>
 __device__ __forceinline__ cx<R> half_cell_phase(double frac) {
