@@ -479,7 +479,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32-split (fp64 solve, fp32 FFT, hi+lo spectra)",
+        "dtype": "f32",
+        "precision_form": "FP32-split: f32 FFTs and products with hi+lo f32 spectra, f64 coefficient solve",
         "data": "synthetic",
         "config": {"workload": f"{n}x{n} cells on [-1,1]^2, k={k}, sigma = 32 seeded Gaussian clumps x taper "
                                f"(clump recipe of the 1024^2 precision case, at {n}^2)",
