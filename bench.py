@@ -27,19 +27,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+# bytes per spectrum bin and component in FP32-split plans (float hi + lo)
+TABLE_BYTES_FP32 = 8
 
 
-def bytes_per_cell(prec_fp64: bool):
+def bytes_per_cell(prec_fp64: bool, table_bytes=None):
     """Algorithmic HBM bytes per output cell, per pass (A, B, C).
 
     A: read sigma, write the row spectra X (one complex per cell).
-    B: read X, read the two weight spectra (one real per (p, q) bin each,
-       a float hi+lo pair or a double), write V (two complex per cell).
-    C: read V, write Fx and Fy."""
+    B: read X, read the weight spectra, write V (two complex per cell).
+    C: read V, write Fx and Fy.
+    The spectra: one real per (p, q) bin for each of the two components,
+    ``table_bytes`` each (a double; a float; or a float hi + lo pair).  The
+    model of the path's byte budget takes 8 bytes per bin for both components
+    together (FP32: one float each; FP64: the budget of one double table)."""
     r = 8 if prec_fp64 else 4          # real
     c = 2 * r                          # complex
-    t = 8                              # spectrum entry: double, or float hi + lo
-    return {"A": r + c, "B": c + 2 * t + 2 * c, "C": 2 * c + 2 * r}
+    sw = 8 if table_bytes is None else 2 * table_bytes
+    return {"A": r + c, "B": c + sw + 2 * c, "C": 2 * c + 2 * r}
 
 
 def time_plan(sg, torch, grid, prec, sigma_np, steps, warmup):
@@ -375,6 +380,53 @@ def cpu_baseline(n, k, sigma_np, sample):
             "host_cpu": _cpu_model()}
 
 
+def cpu_fft_reference(sg, torch, n, k, sigma_np, ref_fx, ref_fy):
+    """CPU FFT reference (not the oracle): the same forces by FP64
+    zero-padded FFT convolution with scipy.fft on all host cores.  The
+    weights come from the library (sg_weights, FP64) and are transformed once
+    (excluded, like plan time); the timed part is the coefficient solve (banded
+    solves along both axes), one forward real 2-D FFT, the two spectral
+    products and the two inverse real 2-D FFTs, cropped.  k = 1, 2, 3."""
+    import numpy as np
+    import scipy.fft
+    import scipy.linalg
+    if k not in (1, 2, 3):
+        return None
+    workers = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    plan = sg.Plan([(n, n, -1.0, 1.0, -1.0, 1.0, k)], sg.SG_FP64)
+    try:
+        wx, wy = (w.cpu().numpy() for w in plan.weights(0))
+    finally:
+        plan.close()
+    P = 2 * n
+
+    def padded(w):
+        # w(m, n') at (m mod 2n, n' mod 2n); the slots m = n, n' = n stay 0 (odd k)
+        out = np.zeros((P, P))
+        idx = np.arange(-(n - 1), n) % P
+        out[np.ix_(idx, idx)] = w
+        return out
+
+    Wx = scipy.fft.rfft2(padded(wx), workers=workers)
+    Wy = scipy.fft.rfft2(padded(wy), workers=workers)
+    ab = np.array([[1.0], [6.0], [1.0]]) * np.ones((3, n)) / 8.0  # tridiag(1,6,1)/8, Eqs. (z_system), (C_system)
+    sig = np.asarray(sigma_np, dtype=np.float64)
+    t0 = time.perf_counter()
+    C = sig
+    if k == 3:
+        C = scipy.linalg.solve_banded((1, 1), ab, C.T).T       # along x (rows)
+        C = scipy.linalg.solve_banded((1, 1), ab, C)           # along y (columns)
+    Ch = scipy.fft.rfft2(C, s=(P, P), workers=workers)
+    fx = scipy.fft.irfft2(Ch * Wx, s=(P, P), workers=workers)[:n, :n]
+    fy = scipy.fft.irfft2(Ch * Wy, s=(P, P), workers=workers)[:n, :n]
+    dt = time.perf_counter() - t0
+    scale = max(np.abs(ref_fx).max(), np.abs(ref_fy).max())
+    diff = max(np.abs(fx - ref_fx).max(), np.abs(fy - ref_fy).max()) / scale
+    return {"value": n * n / dt, "unit": "cells/s", "cores": workers, "kind": "CPU FFT reference (not the oracle)",
+            "seconds": round(dt, 3), "library": f"scipy.fft {scipy.__version__} (pocketfft), FP64",
+            "rel_diff_vs_gpu_fp64": float(diff)}
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -458,15 +510,21 @@ def main():
     err32 = max(np.abs(fx - gx).max(), np.abs(fy - gy).max()) / scale
 
     cells = n * n
-    bpc = bytes_per_cell(False)
+    bpc = bytes_per_cell(False)                                 # the byte budget of the path
+    bpc_impl = bytes_per_cell(False, TABLE_BYTES_FP32)          # what this build's tables hold
     dom = max(range(3), key=lambda i: pass32[i])
     name = "ABC"[dom]
     achieved = bpc[name] * cells / (pass32[dom] * 1e-3) / 1e9
     kname = {"A": "k_row_fwd", "B": "k_col", "C": "k_row_inv"}[name]
+    step_gbs = sum(bpc.values()) * cells / (ms32 * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": kname,
                 "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(kname, n),
-                "bytes_per_cell": bpc[name], "kernel_ms": round(pass32[dom], 4)}
+                "bytes_per_cell": bpc[name], "kernel_ms": round(pass32[dom], 4),
+                "bytes_per_cell_impl": bpc_impl[name],
+                "frac_impl": round(bpc_impl[name] * cells / (pass32[dom] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                "step": {"bytes_per_cell": sum(bpc.values()), "achieved": round(step_gbs, 1),
+                         "frac": round(step_gbs / PEAK_HBM_GBS, 4), "ms": round(ms32, 4)}}
     total_bytes = sum(bpc.values()) * cells
     line = {
         "metric": "force cells/s (Fx+Fy, 3rd order, 4096²): FP32-split vs FP64 at ≤1e-6 rel",
@@ -503,6 +561,9 @@ def main():
         line["differentiation"] = grad_bench(sg, torch, max(args.steps // 2, 3), 2)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(n, k, sigma, args.cpu_sample)
+        ref = cpu_fft_reference(sg, torch, n, k, sigma, gx.reshape(n, n), gy.reshape(n, n))
+        if ref is not None:
+            line["cpu_fft_reference"] = ref
     print(json.dumps(line), flush=True)
 
 

@@ -204,6 +204,8 @@ class Plan:
         self.dtype = torch.float64 if prec == SG_FP64 else torch.float32
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        if isinstance(self.stream, int):
+            self.stream = torch.cuda.ExternalStream(self.stream)
         self.handle = sg_plan_create(self.grids, prec, self.stream, flags)
         self.offsets = sg_plan_layout(self.handle, len(self.grids))
 
@@ -237,28 +239,75 @@ class Plan:
         nx, ny = self.grids[g][0], self.grids[g][1]
         return xs0 + dx * np.arange(nx), ys0 + dy * np.arange(ny)
 
+    # -- argument checks: every tensor handed to the kernels must be a
+    # contiguous tensor of the plan's dtype on the plan's device holding
+    # exactly the packed length (a short or mistyped buffer would be read or
+    # written out of bounds by the kernels)
+    def _check_tensor(self, name, t, numel=None, dtype=None):
+        import torch
+        dtype = self.dtype if dtype is None else dtype
+        numel = self.total if numel is None else numel
+        if not isinstance(t, torch.Tensor):
+            raise SGError(1, f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+        if t.dtype != dtype:
+            raise SGError(1, f"{name}: dtype {t.dtype}, the plan needs {dtype}")
+        if t.device != self.device:
+            raise SGError(1, f"{name}: on {t.device}, the plan is on {self.device}")
+        if not t.is_contiguous():
+            raise SGError(1, f"{name}: not contiguous")
+        if t.numel() != numel:
+            raise SGError(1, f"{name}: {t.numel()} elements, the plan needs {numel}")
+
+    def _call(self, fn, ins, outs):
+        """Run one library call on the plan's stream.  When the caller's
+        current stream is another one, the plan's stream first waits for it
+        (the inputs may still be being written there) and the caller's stream
+        then waits for the plan's (the outputs are used there); every tensor
+        is recorded on the plan's stream so that the caching allocator does
+        not reuse its memory while the plan's kernels may still touch it."""
+        import torch
+        cur = torch.cuda.current_stream(self.device)
+        other = cur.cuda_stream != self.stream.cuda_stream
+        if other:
+            self.stream.wait_stream(cur)
+        fn()
+        if other:
+            for t in (*ins, *outs):
+                t.record_stream(self.stream)
+            cur.wait_stream(self.stream)
+
     def weights(self, g: int = 0):
         import torch
+        if not 0 <= g < len(self.grids):
+            raise SGError(1, f"grid index {g} out of range")
         nx, ny = self.grids[g][0], self.grids[g][1]
         wx = torch.empty((2 * ny - 1, 2 * nx - 1), dtype=torch.float64, device=self.device)
         wy = torch.empty_like(wx)
-        sg_weights(self.handle, g, wx, wy)
+        self._call(lambda: sg_weights(self.handle, g, wx, wy), (), (wx, wy))
         return wx, wy
 
     def coeffs(self, sigma, out=None):
         out = self.empty() if out is None else out
-        sg_bspline_coeffs(self.handle, sigma, out)
+        self._check_tensor("sigma", sigma)
+        self._check_tensor("out", out)
+        self._call(lambda: sg_bspline_coeffs(self.handle, sigma, out), (sigma,), (out,))
         return out
 
     def forces(self, sigma, fx=None, fy=None):
         fx = self.empty() if fx is None else fx
         fy = self.empty() if fy is None else fy
-        sg_forces(self.handle, sigma, fx, fy)
+        self._check_tensor("sigma", sigma)
+        self._check_tensor("fx", fx)
+        self._check_tensor("fy", fy)
+        self._call(lambda: sg_forces(self.handle, sigma, fx, fy), (sigma,), (fx, fy))
         return fx, fy
 
     def adjoint(self, gfx, gfy, out=None):
         out = self.empty() if out is None else out
-        sg_forces_adjoint(self.handle, gfx, gfy, out)
+        self._check_tensor("gfx", gfx)
+        self._check_tensor("gfy", gfy)
+        self._check_tensor("out", out)
+        self._call(lambda: sg_forces_adjoint(self.handle, gfx, gfy, out), (gfx, gfy), (out,))
         return out
 
 
@@ -272,6 +321,8 @@ def _autograd():
         def forward(ctx, sigma, plan):
             ctx.plan = plan
             s = sigma.contiguous()
+            if s.dtype != plan.dtype:
+                raise SGError(1, f"sigma: dtype {s.dtype}, the plan needs {plan.dtype}")
             return plan.forces(s)
 
         @staticmethod

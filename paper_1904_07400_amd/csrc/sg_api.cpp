@@ -154,9 +154,32 @@ struct sg_plan_s {
 
 namespace {
 
+// Fault injection for the error-path tests, read from the environment at
+// each call: SG_FAULT_INJECT=alloc refuses every device allocation of a plan,
+// alloc:N only the N-th one (1-based, counted from the start of
+// sg_plan_create on this thread), device makes the next per-step call fail as
+// if a HIP call had returned an error (the plan then turns sticky).
+thread_local int g_alloc_count = 0;
+
+bool inject_alloc_failure() {
+  const char* v = getenv("SG_FAULT_INJECT");
+  if (!v) return false;
+  if (strcmp(v, "alloc") == 0) return true;
+  if (strncmp(v, "alloc:", 6) == 0) return g_alloc_count == atoi(v + 6);
+  return false;
+}
+
+bool inject_device_failure() {
+  const char* v = getenv("SG_FAULT_INJECT");
+  return v && strcmp(v, "device") == 0;
+}
+
+// Device memory of the plan (released by sg_plan_destroy, or at once when
+// plan creation fails).
 sg_status dev_alloc(sg_plan p, void** out, size_t bytes) {
-  if (getenv("SG_FAULT_INJECT") && strcmp(getenv("SG_FAULT_INJECT"), "alloc") == 0)
-    return fail(SG_ERR_NOMEM, "allocation of %zu bytes refused (SG_FAULT_INJECT=alloc)", bytes);
+  ++g_alloc_count;
+  if (inject_alloc_failure())
+    return fail(SG_ERR_NOMEM, "allocation %d of %zu bytes refused (SG_FAULT_INJECT)", g_alloc_count, bytes);
   hipError_t e = hipMalloc(out, bytes ? bytes : 16);
   if (e != hipSuccess) {
     *out = nullptr;
@@ -233,6 +256,14 @@ sg_status check_plan(sg_plan p) {
   return SG_OK;
 }
 
+// Per-step entry: the plan check, then the injected device failure if asked.
+sg_status step_entry(sg_plan p) {
+  sg_status s = check_plan(p);
+  if (s != SG_OK) return s;
+  if (inject_device_failure()) return hip_check(p, hipErrorLaunchFailure, "injected (SG_FAULT_INJECT=device)");
+  return SG_OK;
+}
+
 // Weight spectra of one grid (plan time, FP64 throughout).
 sg_status build_spectra(sg_plan p, GridPlan& G, const void* r2m64, const void* r2n64) {
   const int M = G.M, N = G.N;
@@ -242,12 +273,15 @@ sg_status build_spectra(sg_plan p, GridPlan& G, const void* r2m64, const void* r
   if (ts != SG_OK) return ts;
   double* wp = nullptr;
   void* S = nullptr;
-  hipError_t e = hipMalloc((void**)&wp, sizeof(double) * 2 * (size_t)(2 * M) * (2 * N));
+  ++g_alloc_count;
+  hipError_t e = inject_alloc_failure() ? hipErrorOutOfMemory
+                                        : hipMalloc((void**)&wp, sizeof(double) * 2 * (size_t)(2 * M) * (2 * N));
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(SG_ERR_NOMEM, "plan-time weight table: %s", hipGetErrorString(e));
   }
-  e = hipMalloc(&S, 16 * (size_t)(2 * N) * M);
+  ++g_alloc_count;
+  e = inject_alloc_failure() ? hipErrorOutOfMemory : hipMalloc(&S, 16 * (size_t)(2 * N) * M);
   if (e != hipSuccess) {
     (void)hipFree(wp);
     (void)hipGetLastError();
@@ -428,6 +462,7 @@ const char* sg_last_error_message(void) { return g_msg.c_str(); }
 sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_precision prec, void* hip_stream,
                          uint32_t flags) {
   g_msg.clear();
+  g_alloc_count = 0;
   if (!out) return fail(SG_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!grids || ngrids < 1) return fail(SG_ERR_ARG, "need at least one grid (ngrids=%d)", ngrids);
@@ -651,7 +686,7 @@ sg_status sg_weights(sg_plan p, int32_t g, double* wx, double* wy) {
 
 sg_status sg_bspline_coeffs(sg_plan p, const void* sigma, void* coeffs) {
   g_msg.clear();
-  sg_status s = check_plan(p);
+  sg_status s = step_entry(p);
   if (s != SG_OK) return s;
   if (!sigma || !coeffs) return fail(SG_ERR_ARG, "sigma or coeffs is NULL");
   const int prec = p->prec == SG_FP64 ? 0 : 1;
@@ -673,7 +708,7 @@ sg_status sg_bspline_coeffs(sg_plan p, const void* sigma, void* coeffs) {
 
 sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy) {
   g_msg.clear();
-  sg_status s = check_plan(p);
+  sg_status s = step_entry(p);
   if (s != SG_OK) return s;
   if (!sigma || !fx || !fy) return fail(SG_ERR_ARG, "sigma, fx or fy is NULL");
   if (fx == fy || fx == sigma || fy == sigma) return fail(SG_ERR_ARG, "fx, fy and sigma must not alias");
@@ -809,7 +844,7 @@ sg_status sg_plan_pass_times(sg_plan p, double* ms, int64_t* calls) {
 
 sg_status sg_forces_adjoint(sg_plan p, const void* gfx, const void* gfy, void* gsigma) {
   g_msg.clear();
-  sg_status s = check_plan(p);
+  sg_status s = step_entry(p);
   if (s != SG_OK) return s;
   if (!gfx || !gfy || !gsigma) return fail(SG_ERR_ARG, "gfx, gfy or gsigma is NULL");
   if (gsigma == gfx || gsigma == gfy) return fail(SG_ERR_ARG, "gsigma must not alias gfx or gfy");
