@@ -75,6 +75,9 @@ typedef struct {
 #define SG_FLAG_CHECK_FINITE 0x1u /* sg_forces rejects non-finite sigma (SG_ERR_STATE); costs one extra read */
 #define SG_FLAG_GRAPH 0x2u        /* sg_forces replays a captured HIP graph of the whole step (see sg_forces) */
 #define SG_FLAG_AUTOTUNE 0x4u     /* sg_plan_create times the launch tiles of every class and keeps the best */
+#define SG_FLAG_SPECTRA_F32 0x8u  /* SG_FP32_SPLIT: kernel spectra of grids with ny = 4096 or 8192 stored as
+                                     single floats (4 B per bin) instead of hi + lo pairs: half the table
+                                     traffic of the column pass; ignored by SG_FP64 plans */
 
 /* Create a plan for ngrids grids (all of one precision) on the given HIP
  * stream (hipStream_t; NULL = the null stream).  Plan time does what the

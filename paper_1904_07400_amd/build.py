@@ -1,7 +1,8 @@
 """Compile the HIP library (libsg.so) for gfx950, in-tree.
 
 Sources: csrc/sg_kernels.hip (device kernels + launch dispatch, compiled as
-four objects in parallel) and csrc/sg_api.cpp (the C ABI of include/sg.h).
+four objects in parallel), csrc/sg_colfs.hip (the four-step column pass of
+the long columns) and csrc/sg_api.cpp (the C ABI of include/sg.h).
 Every call recompiles.
 """
 from __future__ import annotations
@@ -25,7 +26,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC, "--offload-
 # (source, extra flags, object name): the kernel file is compiled in four
 # parts (SG_PART, a bit mask of the parts) in parallel
 UNITS = [("sg_kernels.hip", ["-DSG_PART=%d" % (1 << i)], "sg_kernels_p%d.o" % i) for i in range(4)] + \
-        [("sg_api.cpp", [], "sg_api.o")]
+        [("sg_colfs.hip", [], "sg_colfs.o"), ("sg_api.cpp", [], "sg_api.o")]
 
 
 def _compile(unit, obj_dir: str) -> str:

@@ -31,8 +31,8 @@ sg_status fail(sg_status s, const char* fmt, ...) {
 }
 
 bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
-// Grid sizes with kernels: 2^a from 4 to 4096 and 3 * 2^a from 12 to 1536.
-bool size_ok(int v) { return pow2_in(v, 4, 4096) || (v % 3 == 0 && pow2_in(v / 3, 4, 512)); }
+// Grid sizes with kernels: 2^a from 4 to 8192 and 3 * 2^a from 12 to 1536.
+bool size_ok(int v) { return pow2_in(v, 4, 8192) || (v % 3 == 0 && pow2_in(v / 3, 4, 512)); }
 
 // Roots of unity exp(-2 pi i k / B), k = 0..B-1, from long double sin/cos of
 // the octant-reduced angle (one rounding to the stored precision).
@@ -107,6 +107,9 @@ struct GridPlan {
   void* twA = nullptr;  // stage twiddles: forward rows, columns, inverse rows
   void* twB = nullptr;
   void* twC = nullptr;
+  bool fs = false;          // columns by the four-step pass (long columns)
+  void* twfs = nullptr;     // its twiddle table
+  int tab_bytes = 8;        // bytes per spectrum entry: double, float hi + lo, or float
 };
 
 // Grids of one size and order: one launch per pass runs all of them
@@ -174,6 +177,22 @@ bool inject_device_failure() {
   return v && strcmp(v, "device") == 0;
 }
 
+// Temporary device memory of plan creation (freed by the caller before it
+// returns), counted for the fault injection like the plan's own.
+sg_status tmp_alloc(void** out, size_t bytes, const char* what) {
+  ++g_alloc_count;
+  *out = nullptr;
+  if (inject_alloc_failure())
+    return fail(SG_ERR_NOMEM, "%s: allocation %d of %zu bytes refused (SG_FAULT_INJECT)", what, g_alloc_count, bytes);
+  hipError_t e = hipMalloc(out, bytes ? bytes : 16);
+  if (e != hipSuccess) {
+    *out = nullptr;
+    (void)hipGetLastError();
+    return fail(SG_ERR_NOMEM, "%s: hipMalloc(%zu) failed: %s", what, bytes, hipGetErrorString(e));
+  }
+  return SG_OK;
+}
+
 // Device memory of the plan (released by sg_plan_destroy, or at once when
 // plan creation fails).
 sg_status dev_alloc(sg_plan p, void** out, size_t bytes) {
@@ -213,6 +232,29 @@ sg_status make_twiddles(sg_plan p, int prec, int pass, int len, const void* root
   if (s != SG_OK) return s;
   sg_twiddles(prec, pass, len, roots, *out, p->st);
   return hip_check(p, hipGetLastError(), "twiddle table");
+}
+
+// Twiddle table of the four-step column pass of length N (long double,
+// rounded once to the plan precision).
+sg_status upload_fs_twiddles(sg_plan p, int prec, int N, void** out) {
+  const int n = sg_colfs_twiddles(prec, N, nullptr, nullptr);
+  if (n <= 0) return fail(SG_ERR_UNSUPPORTED, "no four-step column pass for length %d", N);
+  std::vector<double> re(n), im(n);
+  sg_colfs_twiddles(prec, N, re.data(), im.data());
+  const size_t el = prec == 0 ? 8 : 4;
+  std::vector<unsigned char> h(2 * el * (size_t)n);
+  for (int i = 0; i < n; ++i) {
+    if (prec == 0) {
+      double v[2] = {re[i], im[i]};
+      memcpy(&h[16 * (size_t)i], v, 16);
+    } else {
+      float v[2] = {(float)re[i], (float)im[i]};
+      memcpy(&h[8 * (size_t)i], v, 8);
+    }
+  }
+  sg_status s = dev_alloc(p, out, h.size());
+  if (s != SG_OK) return s;
+  return hip_check(p, hipMemcpy(*out, h.data(), h.size(), hipMemcpyHostToDevice), "hipMemcpy four-step twiddles");
 }
 
 void drop_events(sg_plan p) {
@@ -273,30 +315,39 @@ sg_status build_spectra(sg_plan p, GridPlan& G, const void* r2m64, const void* r
   if (ts != SG_OK) return ts;
   double* wp = nullptr;
   void* S = nullptr;
-  ++g_alloc_count;
-  hipError_t e = inject_alloc_failure() ? hipErrorOutOfMemory
-                                        : hipMalloc((void**)&wp, sizeof(double) * 2 * (size_t)(2 * M) * (2 * N));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(SG_ERR_NOMEM, "plan-time weight table: %s", hipGetErrorString(e));
-  }
-  ++g_alloc_count;
-  e = inject_alloc_failure() ? hipErrorOutOfMemory : hipMalloc(&S, 16 * (size_t)(2 * N) * M);
-  if (e != hipSuccess) {
+  sg_status as = tmp_alloc((void**)&wp, sizeof(double) * 2 * (size_t)(2 * M) * (2 * N), "plan-time weight table");
+  if (as != SG_OK) return as;
+  as = tmp_alloc(&S, 16 * (size_t)(2 * N) * M, "plan-time spectrum workspace");
+  if (as != SG_OK) {
     (void)hipFree(wp);
-    (void)hipGetLastError();
-    return fail(SG_ERR_NOMEM, "plan-time spectrum workspace: %s", hipGetErrorString(e));
+    return as;
   }
+  hipError_t e = hipSuccess;
   double* wpx = wp;
   double* wpy = wp + (size_t)(2 * M) * (2 * N);
-  const int fp32 = p->prec == SG_FP32_SPLIT ? 1 : 0;
+  // stored form of the tables: double, float hi + lo, or float
+  const int fp32 = p->prec == SG_FP64 ? 0 : (G.tab_bytes == 8 ? 1 : 2);
   const double scale = 1.0 / (4.0 * (double)M * (double)N);
   sg_status st = SG_OK;
+  // columns of 8192: the four-step spectrum kernel (FP64 twiddles of that length)
+  void* twfs64 = nullptr;
+  if (N == 8192) {
+    sg_status ts2 = upload_fs_twiddles(p, 0, N, &twfs64);
+    if (ts2 != SG_OK) {
+      (void)hipFree(wp);
+      (void)hipFree(S);
+      return ts2;
+    }
+  }
+  auto spec = [&](void* tab) {
+    return N == 8192 ? sg_launch_specfs(N, S, M, tab, G.kind, fp32, scale, r2n64, twfs64, p->st)
+                     : sg_launch_spec_col(N, S, M, tab, G.kind, fp32, scale, r2n64, twS64, p->st);
+  };
   e = sg_launch_weights(G.k, G.hx, G.hy, M, N, wpx, wpy, 0, p->st);
   if (e == hipSuccess) e = sg_launch_row_fwd(0, M, wpx, 2 * M, S, 2 * N, r2m64, 0, 1, twA64, nullptr, 1, 0, p->st);
-  if (e == hipSuccess) e = sg_launch_spec_col(N, S, M, G.tabx, G.kind, fp32, scale, r2n64, twS64, p->st);
+  if (e == hipSuccess) e = spec(G.tabx);
   if (e == hipSuccess) e = sg_launch_row_fwd(0, M, wpy, 2 * M, S, 2 * N, r2m64, 0, 1, twA64, nullptr, 1, 0, p->st);
-  if (e == hipSuccess) e = sg_launch_spec_col(N, S, M, G.taby, G.kind, fp32, scale, r2n64, twS64, p->st);
+  if (e == hipSuccess) e = spec(G.taby);
   if (e == hipSuccess) e = hipStreamSynchronize(p->st);
   if (e != hipSuccess) st = hip_check(p, e, "plan-time spectrum");
   (void)hipFree(wp);
@@ -307,6 +358,21 @@ sg_status build_spectra(sg_plan p, GridPlan& G, const void* r2m64, const void* r
 constexpr size_t kMaxGraphs = 4;
 constexpr int kSideStreams = 4;
 
+// The column pass of one class: the four-step kernel for long columns, the
+// Stockham kernel otherwise.
+hipError_t launch_cols(sg_plan p, const GridClass& c, int tile, hipStream_t q) {
+  const int prec = p->prec == SG_FP64 ? 0 : 1;
+  const GridPlan& G = p->grids[c.members[0]];
+  const int solve = c.k >= 3 ? c.k : 0;
+  const int ng = (int)c.members.size();
+  const int tj = sg_row_tile(prec, c.M, c.N);
+  if (G.fs)
+    return sg_launch_colfs(prec, c.N, nullptr, nullptr, c.M, tj, nullptr, nullptr, G.kind, G.tab_bytes, G.r2n, solve,
+                           G.twfs, c.desc, ng, q);
+  return sg_launch_col(prec, c.N, nullptr, nullptr, c.M, tj, nullptr, nullptr, G.kind, G.r2n, solve, G.twB, c.desc, ng,
+                       tile, q);
+}
+
 // The three launches of every grid of one class on stream q.
 hipError_t issue_class(sg_plan p, const GridClass& c, const void* sigma, void* fx, void* fy, hipStream_t q,
                        const int* tile) {
@@ -316,9 +382,7 @@ hipError_t issue_class(sg_plan p, const GridClass& c, const void* sigma, void* f
   const int ng = (int)c.members.size();
   const int tj = sg_row_tile(prec, c.M, c.N);
   hipError_t e = sg_launch_row_fwd(prec, c.M, sigma, c.M, nullptr, c.N, G.r2m, solve, 0, G.twA, c.desc, ng, tile[0], q);
-  if (e == hipSuccess)
-    e = sg_launch_col(prec, c.N, nullptr, nullptr, c.M, tj, nullptr, nullptr, G.kind, G.r2n, solve, G.twB, c.desc, ng,
-                      tile[1], q);
+  if (e == hipSuccess) e = launch_cols(p, c, tile[1], q);
   if (e == hipSuccess)
     e = sg_launch_row_inv(prec, c.M, nullptr, fx, fy, c.N, tj, G.r2m, G.twC, c.desc, ng, tile[2], q);
   return e;
@@ -385,8 +449,7 @@ sg_status time_tile(sg_plan p, GridClass& c, int pass, int tile, const void* sig
     if (pass == 0)
       e = sg_launch_row_fwd(prec, c.M, sig, c.M, nullptr, c.N, G.r2m, solve, 0, G.twA, c.desc, ng, t3[0], p->st);
     else if (pass == 1)
-      e = sg_launch_col(prec, c.N, nullptr, nullptr, c.M, tj, nullptr, nullptr, G.kind, G.r2n, solve, G.twB, c.desc,
-                        ng, t3[1], p->st);
+      e = launch_cols(p, c, t3[1], p->st);
     else
       e = sg_launch_row_inv(prec, c.M, nullptr, fx, fy, c.N, tj, G.r2m, G.twC, c.desc, ng, t3[2], p->st);
     if (e == hipSuccess) e = hipEventRecord(b, p->st);
@@ -467,7 +530,7 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
   *out = nullptr;
   if (!grids || ngrids < 1) return fail(SG_ERR_ARG, "need at least one grid (ngrids=%d)", ngrids);
   if (prec != SG_FP64 && prec != SG_FP32_SPLIT) return fail(SG_ERR_ARG, "unknown precision %d", (int)prec);
-  if (flags & ~(SG_FLAG_CHECK_FINITE | SG_FLAG_GRAPH | SG_FLAG_AUTOTUNE))
+  if (flags & ~(SG_FLAG_CHECK_FINITE | SG_FLAG_GRAPH | SG_FLAG_AUTOTUNE | SG_FLAG_SPECTRA_F32))
     return fail(SG_ERR_ARG, "unknown flags 0x%x", flags);
   for (int i = 0; i < ngrids; ++i) {
     const sg_grid& g = grids[i];
@@ -503,7 +566,8 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
   const size_t cb = prec == SG_FP64 ? 16 : 8;  // complex element bytes
   std::map<int, void*> roots64;
   std::map<std::pair<int, int>, void*> tw;  // (pass, length) -> stage twiddles
-  std::map<std::tuple<int, int, int, double, double>, std::pair<void*, void*>> spectra;  // shared weight spectra
+  std::map<std::tuple<int, int, int, double, double, int>, std::pair<void*, void*>> spectra;  // shared weight spectra
+  std::map<int, void*> twfs;  // four-step twiddle tables by length
   sg_status s = SG_OK;
   int64_t off = 0;
   for (int i = 0; i < ngrids && s == SG_OK; ++i) {
@@ -517,12 +581,21 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
     G.hy = (grids[i].y1 - grids[i].y0) / G.N;
     G.off = off;
     off += (int64_t)G.M * G.N;
-    // one real per bin (FP64 or hi+lo FP32) on a quarter of the lattice; for
-    // even k the bin phase is applied in the column pass
-    const size_t tab_el = 8;
+    // the four-step column pass for the long columns (SG_COLFS=0 in the
+    // environment keeps the Stockham pass where it exists: a diagnostic)
+    {
+      const char* env = getenv("SG_COLFS");
+      const bool off = env && strcmp(env, "0") == 0 && G.N <= 4096;
+      G.fs = sg_colfs_supported(prec == SG_FP64 ? 0 : 1, G.N) && !off;
+    }
+    // one real per bin (FP64, hi+lo FP32, or with SG_FLAG_SPECTRA_F32 and the
+    // four-step pass, FP32) on a quarter of the lattice; for even k the bin
+    // phase is applied in the column pass
+    G.tab_bytes = (prec == SG_FP32_SPLIT && G.fs && (flags & SG_FLAG_SPECTRA_F32)) ? 4 : 8;
+    const size_t tab_el = (size_t)G.tab_bytes;
     const size_t tab_n = (size_t)(G.M + 1) * (G.N + 1);
-    // grids of equal size, order and cell shape share one pair of spectra
-    const auto key = std::make_tuple(G.M, G.N, G.k, G.hx, G.hy);
+    // grids of equal size, order, cell shape and table form share one pair of spectra
+    const auto key = std::make_tuple(G.M, G.N, G.k, G.hx, G.hy, G.tab_bytes);
     const bool fresh = !spectra.count(key);
     if (fresh) {
       if (s == SG_OK) s = dev_alloc(p, &G.tabx, tab_el * tab_n);
@@ -561,6 +634,14 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
           tw[tk] = d;
         }
         *slots[pass] = tw[tk];
+      }
+      if (s == SG_OK && G.fs) {
+        if (!twfs.count(G.N)) {
+          void* d = nullptr;
+          s = upload_fs_twiddles(p, pc, G.N, &d);
+          twfs[G.N] = d;
+        }
+        G.twfs = twfs[G.N];
       }
       if (s == SG_OK && fresh) s = build_spectra(p, G, roots64[2 * G.M], roots64[2 * G.N]);
     }
@@ -766,9 +847,7 @@ sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy) {
     if (e == hipSuccess)
       e = sg_launch_row_fwd(prec, c.M, sigma, c.M, nullptr, c.N, G.r2m, solve, 0, G.twA, c.desc, ng, c.tile[0], p->st);
     if (e == hipSuccess) e = mark(p);
-    if (e == hipSuccess)
-      e = sg_launch_col(prec, c.N, nullptr, nullptr, c.M, tj, nullptr, nullptr, G.kind, G.r2n, solve, G.twB, c.desc, ng,
-                        c.tile[1], p->st);
+    if (e == hipSuccess) e = launch_cols(p, c, c.tile[1], p->st);
     if (e == hipSuccess) e = mark(p);
     if (e == hipSuccess)
       e = sg_launch_row_inv(prec, c.M, nullptr, fx, fy, c.N, tj, G.r2m, G.twC, c.desc, ng, c.tile[2], p->st);
@@ -855,13 +934,20 @@ sg_status sg_forces_adjoint(sg_plan p, const void* gfx, const void* gfy, void* g
     const GridPlan& G = p->grids[c.members[0]];
     const int solve = c.k >= 3 ? c.k : 0;
     const int ng = (int)c.members.size();
+    const int tj = sg_row_tile(prec, c.M, c.N);
     hipError_t e =
         sg_launch_row_fwd(prec, c.M, gfx, c.M, nullptr, c.N, G.r2m, 0, 0, G.twA, c.desc, ng, c.tile[0], p->st);
     if (e == hipSuccess)
       e = sg_launch_row_fwd(prec, c.M, gfy, c.M, nullptr, c.N, G.r2m, 0, 0, G.twA, c.desc_y, ng, c.tile[0], p->st);
-    if (e == hipSuccess)
-      e = sg_launch_adjoint_tail(prec, c.M, c.N, nullptr, nullptr, nullptr, gsigma, sg_row_tile(prec, c.M, c.N),
-                                 nullptr, nullptr, G.kind, G.r2m, G.r2n, solve, G.twB, G.twA, c.desc, ng, p->st);
+    if (e == hipSuccess && G.fs) {
+      e = sg_launch_colfs_adj(prec, c.N, nullptr, nullptr, nullptr, c.M, tj, nullptr, nullptr, G.kind, G.tab_bytes, G.r2n,
+                              solve, G.twfs, c.desc, ng, p->st);
+      if (e == hipSuccess)
+        e = sg_launch_row_c2r(prec, c.M, c.N, nullptr, gsigma, tj, G.r2m, solve, G.twA, c.desc, ng, p->st);
+    } else if (e == hipSuccess) {
+      e = sg_launch_adjoint_tail(prec, c.M, c.N, nullptr, nullptr, nullptr, gsigma, tj, nullptr, nullptr, G.kind, G.r2m,
+                                 G.r2n, solve, G.twB, G.twA, c.desc, ng, p->st);
+    }
     if (e != hipSuccess) return hip_check(p, e, "adjoint launch");
   }
   return SG_OK;

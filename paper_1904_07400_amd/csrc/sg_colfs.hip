@@ -1,0 +1,208 @@
+// Launches of the four-step column pass (colfs.hpp) for the long columns:
+// N = 4096 (FP32, FP64) and N = 8192 (FP32).  One workgroup of N / E
+// threads per column; for a batch, blockIdx.y is the grid of the class.
+#include "colfs.hpp"
+
+#ifndef SG_COLFS_SPLIT_F4096
+#define SG_COLFS_SPLIT_F4096 0
+#endif
+#ifndef SG_COLFS_SPLIT_D4096
+#define SG_COLFS_SPLIT_D4096 0
+#endif
+
+namespace sg {
+
+// elements per thread, LDS slots and component split per precision and
+// length (chosen so that no kernel spills registers)
+template <typename R, int N>
+struct colfs_sel {
+  static constexpr bool ok = false;
+};
+template <>
+struct colfs_sel<float, 4096> {
+  static constexpr bool ok = true;
+  static constexpr int E = 8, SLOTS = 4, SPLIT = SG_COLFS_SPLIT_F4096;
+};
+template <>
+struct colfs_sel<float, 8192> {
+  static constexpr bool ok = true;
+  static constexpr int E = 16, SLOTS = 2, SPLIT = 1;
+};
+template <>
+struct colfs_sel<double, 4096> {
+  static constexpr bool ok = true;
+  static constexpr int E = 8, SLOTS = 2, SPLIT = SG_COLFS_SPLIT_D4096;
+};
+template <>
+struct colfs_sel<double, 8192> {
+  static constexpr bool ok = true;
+  static constexpr int E = 16, SLOTS = 1, SPLIT = 1;
+};
+
+template <typename R, typename TO, int N, int MODE, int COMP>
+static void launch_colfs_k(const cx<R>* X, cx<R>* V, int M, int tj, const TO* tox, const TO* toy, const cx<R>* r2n,
+                           const cx<R>* tw, const sg_bgrid* bg, int ngrids, hipStream_t st) {
+  using Sel = colfs_sel<R, N>;
+  hipLaunchKernelGGL((k_colfs<R, TO, N, MODE, Sel::E, Sel::SLOTS, COMP>), dim3(M, bg ? ngrids : 1),
+                     dim3(N / Sel::E), 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+}
+
+template <typename R, typename TO, int N, int MODE>
+static hipError_t launch_colfs_m(const cx<R>* X, cx<R>* V, int M, int tj, const TO* tox, const TO* toy,
+                                 const cx<R>* r2n, const cx<R>* tw, const sg_bgrid* bg, int ngrids, hipStream_t st) {
+  if constexpr (colfs_sel<R, N>::SPLIT) {
+    launch_colfs_k<R, TO, N, MODE, 1>(X, V, M, tj, tox, toy, r2n, tw, bg, ngrids, st);
+    launch_colfs_k<R, TO, N, MODE, 2>(X, V, M, tj, tox, toy, r2n, tw, bg, ngrids, st);
+  } else {
+    launch_colfs_k<R, TO, N, MODE, 0>(X, V, M, tj, tox, toy, r2n, tw, bg, ngrids, st);
+  }
+  return hipGetLastError();
+}
+
+template <typename R, typename TO, int N>
+static hipError_t launch_colfs_t(const cx<R>* X, cx<R>* V, int M, int tj, const void* tx, const void* ty, int kind,
+                                 const cx<R>* r2n, int solve, const cx<R>* tw, const sg_bgrid* bg, int ngrids,
+                                 hipStream_t st) {
+  const TO* tox = (const TO*)tx;
+  const TO* toy = (const TO*)ty;
+  // modes: 0 = k 1, 1 = k 2, 2 = k 3, 3 = k 4, 4 = k 5 (solve = k for k >= 3)
+  if (solve == 4) return launch_colfs_m<R, TO, N, 3>(X, V, M, tj, tox, toy, r2n, tw, bg, ngrids, st);
+  if (solve == 5) return launch_colfs_m<R, TO, N, 4>(X, V, M, tj, tox, toy, r2n, tw, bg, ngrids, st);
+  if (kind == 1) return launch_colfs_m<R, TO, N, 1>(X, V, M, tj, tox, toy, r2n, tw, bg, ngrids, st);
+  if (solve) return launch_colfs_m<R, TO, N, 2>(X, V, M, tj, tox, toy, r2n, tw, bg, ngrids, st);
+  return launch_colfs_m<R, TO, N, 0>(X, V, M, tj, tox, toy, r2n, tw, bg, ngrids, st);
+}
+
+template <typename R, int N>
+static int colfs_twiddles_t(double* re, double* im) {
+  using Sel = colfs_sel<R, N>;
+  using S = fs_shape<N, Sel::E>;
+  if (re && im)
+    fs_fill_twiddles<N, Sel::E>(
+        [](int m, int L, double* cr, double* ci) {
+          // exp(-2 pi i m / L) from long double, rounded once
+          const long double a = 6.283185307179586476925286766559005768L * (long double)m / (long double)L;
+          *cr = (double)cosl(a);
+          *ci = (double)-sinl(a);
+        },
+        re, im);
+  return S::TW_SIZE;
+}
+
+}  // namespace sg
+
+using namespace sg;
+
+int sg_colfs_supported(int prec, int N) {
+  (void)prec;
+  return (N == 4096 || N == 8192) ? 1 : 0;
+}
+
+int sg_colfs_twiddles(int prec, int N, double* re, double* im) {
+  if (!sg_colfs_supported(prec, N)) return -1;
+  if (prec == 0) return N == 4096 ? colfs_twiddles_t<double, 4096>(re, im) : colfs_twiddles_t<double, 8192>(re, im);
+  return N == 4096 ? colfs_twiddles_t<float, 4096>(re, im) : colfs_twiddles_t<float, 8192>(re, im);
+}
+
+hipError_t sg_launch_colfs(int prec, int N, const void* X, void* V, int M, int tj, const void* tx, const void* ty,
+                           int kind, int tab_bytes, const void* r2n, int solve, const void* tw, const sg_bgrid* bg,
+                           int ngrids, hipStream_t st) {
+  if (prec == 0) {
+    if (tab_bytes != 8) return hipErrorInvalidValue;
+    const cx<double>* Xd = (const cx<double>*)X;
+    cx<double>* Vd = (cx<double>*)V;
+    const cx<double>* rd = (const cx<double>*)r2n;
+    const cx<double>* td = (const cx<double>*)tw;
+    if (N == 4096) return launch_colfs_t<double, double, 4096>(Xd, Vd, M, tj, tx, ty, kind, rd, solve, td, bg, ngrids, st);
+    if (N == 8192) return launch_colfs_t<double, double, 8192>(Xd, Vd, M, tj, tx, ty, kind, rd, solve, td, bg, ngrids, st);
+    return hipErrorInvalidValue;
+  }
+  const cx<float>* Xf = (const cx<float>*)X;
+  cx<float>* Vf = (cx<float>*)V;
+  const cx<float>* rf = (const cx<float>*)r2n;
+  const cx<float>* tf = (const cx<float>*)tw;
+  if (N == 4096) {
+    if (tab_bytes == 8)
+      return launch_colfs_t<float, float2, 4096>(Xf, Vf, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
+    return launch_colfs_t<float, float, 4096>(Xf, Vf, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
+  }
+  if (N == 8192) {
+    if (tab_bytes == 8)
+      return launch_colfs_t<float, float2, 8192>(Xf, Vf, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
+    return launch_colfs_t<float, float, 8192>(Xf, Vf, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------- adjoint --
+namespace sg {
+template <typename R, int N>
+struct colfs_adj_sel {
+  static constexpr int E = N == 8192 ? 16 : 8;
+  static constexpr int SLOTS = (sizeof(R) == 8 && N == 8192) ? 1 : 2;
+};
+
+template <typename R, typename TO, int N, int MODE>
+static hipError_t launch_colfs_adj_m(const cx<R>* Xx, const cx<R>* Xy, cx<R>* Y, int M, int tj, const TO* tox,
+                                     const TO* toy, const cx<R>* r2n, const cx<R>* tw, const sg_bgrid* bg,
+                                     int ngrids, hipStream_t st) {
+  using Sel = colfs_adj_sel<R, N>;
+  hipLaunchKernelGGL((k_colfs_adj<R, TO, N, MODE, Sel::E, Sel::SLOTS>), dim3(M, bg ? ngrids : 1), dim3(N / Sel::E), 0,
+                     st, Xx, Xy, Y, M, tj, tox, toy, r2n, tw, bg);
+  return hipGetLastError();
+}
+
+template <typename R, typename TO, int N>
+static hipError_t launch_colfs_adj_t(const cx<R>* Xx, const cx<R>* Xy, cx<R>* Y, int M, int tj, const void* tx,
+                                     const void* ty, int kind, const cx<R>* r2n, int solve, const cx<R>* tw,
+                                     const sg_bgrid* bg, int ngrids, hipStream_t st) {
+  const TO* tox = (const TO*)tx;
+  const TO* toy = (const TO*)ty;
+  if (solve == 4) return launch_colfs_adj_m<R, TO, N, 3>(Xx, Xy, Y, M, tj, tox, toy, r2n, tw, bg, ngrids, st);
+  if (solve == 5) return launch_colfs_adj_m<R, TO, N, 4>(Xx, Xy, Y, M, tj, tox, toy, r2n, tw, bg, ngrids, st);
+  if (kind == 1) return launch_colfs_adj_m<R, TO, N, 1>(Xx, Xy, Y, M, tj, tox, toy, r2n, tw, bg, ngrids, st);
+  if (solve) return launch_colfs_adj_m<R, TO, N, 2>(Xx, Xy, Y, M, tj, tox, toy, r2n, tw, bg, ngrids, st);
+  return launch_colfs_adj_m<R, TO, N, 0>(Xx, Xy, Y, M, tj, tox, toy, r2n, tw, bg, ngrids, st);
+}
+}  // namespace sg
+
+hipError_t sg_launch_colfs_adj(int prec, int N, const void* Xx, const void* Xy, void* Y, int M, int tj, const void* tx,
+                               const void* ty, int kind, int tab_bytes, const void* r2n, int solve, const void* tw,
+                               const sg_bgrid* bg, int ngrids, hipStream_t st) {
+  if (prec == 0) {
+    if (tab_bytes != 8) return hipErrorInvalidValue;
+    const cx<double>* a = (const cx<double>*)Xx;
+    const cx<double>* b = (const cx<double>*)Xy;
+    cx<double>* y = (cx<double>*)Y;
+    const cx<double>* rd = (const cx<double>*)r2n;
+    const cx<double>* td = (const cx<double>*)tw;
+    if (N == 4096) return launch_colfs_adj_t<double, double, 4096>(a, b, y, M, tj, tx, ty, kind, rd, solve, td, bg, ngrids, st);
+    if (N == 8192) return launch_colfs_adj_t<double, double, 8192>(a, b, y, M, tj, tx, ty, kind, rd, solve, td, bg, ngrids, st);
+    return hipErrorInvalidValue;
+  }
+  const cx<float>* a = (const cx<float>*)Xx;
+  const cx<float>* b = (const cx<float>*)Xy;
+  cx<float>* y = (cx<float>*)Y;
+  const cx<float>* rf = (const cx<float>*)r2n;
+  const cx<float>* tf = (const cx<float>*)tw;
+  if (N == 4096) {
+    if (tab_bytes == 8)
+      return launch_colfs_adj_t<float, float2, 4096>(a, b, y, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
+    return launch_colfs_adj_t<float, float, 4096>(a, b, y, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
+  }
+  if (N == 8192) {
+    if (tab_bytes == 8)
+      return launch_colfs_adj_t<float, float2, 8192>(a, b, y, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
+    return launch_colfs_adj_t<float, float, 8192>(a, b, y, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------- spectrum (plan) --
+hipError_t sg_launch_specfs(int N, const void* rowspec, int M, void* tab, int kind, int fp32, double scale,
+                            const void* r2n, const void* tw, hipStream_t st) {
+  if (N != 8192) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_specfs<8192, 16>), dim3(M), dim3(512), 0, st, (const cx<double>*)rowspec, M, tab, kind, fp32,
+                     scale, (const cx<double>*)r2n, (const cx<double>*)tw);
+  return hipGetLastError();
+}

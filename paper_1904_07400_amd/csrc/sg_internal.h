@@ -59,3 +59,25 @@ hipError_t sg_launch_adjoint_tail(int prec, int M, int N, const void* Xx, const 
                                   int tj, const void* tx, const void* ty, int kind, const void* r2m, const void* r2n,
                                   int solve, const void* twB, const void* twA, const sg_bgrid* bg, int ngrids,
                                   hipStream_t st);
+// Four-step column pass for long columns (sg_colfs.hip): supported
+// (precision, N); its twiddle table (entry count, and filled from long double
+// when re and im are given); the launch (the arguments of sg_launch_col, plus
+// tab_bytes: 8 for double or float hi+lo tables, 4 for float tables).
+int sg_colfs_supported(int prec, int N);
+int sg_colfs_twiddles(int prec, int N, double* re, double* im);
+hipError_t sg_launch_colfs(int prec, int N, const void* X, void* V, int M, int tj, const void* tx, const void* ty,
+                           int kind, int tab_bytes, const void* r2n, int solve, const void* tw, const sg_bgrid* bg,
+                           int ngrids, hipStream_t st);
+// Adjoint column pass of the long columns (the arguments of the column
+// pass of sg_launch_adjoint_tail, plus tab_bytes).
+hipError_t sg_launch_colfs_adj(int prec, int N, const void* Xx, const void* Xy, void* Y, int M, int tj, const void* tx,
+                               const void* ty, int kind, int tab_bytes, const void* r2n, int solve, const void* tw,
+                               const sg_bgrid* bg, int ngrids, hipStream_t st);
+// Plan-time spectrum columns of length 8192 (FP64; tw: the FP64 four-step
+// twiddle table of that length; fp32: 0 double, 1 float hi + lo, 2 float).
+hipError_t sg_launch_specfs(int N, const void* rowspec, int M, void* tab, int kind, int fp32, double scale,
+                            const void* r2n, const void* tw, hipStream_t st);
+// The inverse real row pass of the adjoint alone (after a column pass that
+// wrote the packed gC spectra Y; batched: Y from the descriptors).
+hipError_t sg_launch_row_c2r(int prec, int M, int N, const void* Y, void* gsigma, int tj, const void* r2m, int solve,
+                             const void* twA, const sg_bgrid* bg, int ngrids, hipStream_t st);

@@ -17,6 +17,7 @@
 // Plan time: weights of Eq. (eqnwB) on the padded 2M x 2N lattice (FP64),
 // then the same row/column transforms in FP64 to get their spectra.
 #include "fft.hpp"
+#include "kcommon.hpp"
 #include "sg_internal.h"
 #include "tridiag.hpp"
 
@@ -312,41 +313,6 @@ __global__ void k_weights(int k, double hx, double hy, int M, int N, double* __r
 }
 
 #endif
-
-// --------------------------------------------------------- common bits --
-// Elements per thread for a transform of length L: E0 (a power of two) for
-// L = 2^a, E3 (a multiple of 3) for L = 3 * 2^a, never more than L.
-__host__ __device__ constexpr int elems_for(int L, int E0, int E3) {
-  return (L % 3 == 0) ? (E3 < L ? E3 : L) : (E0 < L ? E0 : L);
-}
-// Largest power of two that divides v, capped at cap (a power of two).
-__host__ __device__ constexpr int pow2_div(int v, int cap) {
-  return (v % 2 == 0 && cap > 1) ? 2 * pow2_div(v / 2, cap / 2) : 1;
-}
-
-// Map the launch index to a tile so that consecutive tiles land on the same
-// XCD (workgroups are dealt round-robin over the 8 XCDs).
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-  if (nb % 8 != 0) return b;
-  return (b % 8) * (nb / 8) + b / 8;
-}
-
-// The batch descriptor of grid blockIdx.y, read through the constant address
-// space: pointers loaded from constant memory are taken to be global, so
-// accesses through them compile to global instructions rather than flat ones
-// (flat accesses also count on the LDS wait counter, so every LDS wait would
-// wait for them too).  All of the library's buffers are device memory.
-__device__ __forceinline__ sg_bgrid grid_desc(const sg_bgrid* bg) {
-  using K = const __attribute__((address_space(4))) sg_bgrid;
-  const K* k = (const K*)bg + blockIdx.y;
-  sg_bgrid d;
-  d.off = k->off;
-  d.X = k->X;
-  d.V = k->V;
-  d.tabx = k->tabx;
-  d.taby = k->taby;
-  return d;
-}
 
 // ---------------------------------------------------------------- pass A --
 // Real FFT of length 2M of a row whose upper half is zero (or, with full,
@@ -1119,8 +1085,17 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
 // the half-length complex inverse FFT (z = x_even + i x_odd, its first M/2
 // outputs from the even and odd input bins: two inverse FFTs of length M/2),
 // then the transposed x-solve (Eq. (C_system) is symmetric).
+// Rows per workgroup: those of the forward row pass, but at most 512
+// threads for the banded x-solve of k = 4, 5 (HI), whose registers would
+// not fit 1024 threads without spilling.
+template <typename R, int M, bool HI>
+struct rowc2r_cfg {
+  using F = rowfwd_cfg<R, R, M>;
+  static constexpr int G = (HI && F::G * F::T > 512) ? (512 / F::T > 0 ? 512 / F::T : 1) : F::G;
+};
+
 template <typename R, typename Out, int M, bool HI = false>  // HI: as in k_row_fwd
-__global__ void __launch_bounds__((rowfwd_cfg<R, R, M>::G * rowfwd_cfg<R, R, M>::T))
+__global__ void __launch_bounds__((rowc2r_cfg<R, M, HI>::G * rowfwd_cfg<R, R, M>::T))
     k_row_c2r(const cx<R>* __restrict__ Y, Out* __restrict__ out, int nrows, int tj, const cx<R>* __restrict__ r2m,
               int solve, const cx<R>* __restrict__ tw, const sg_bgrid* __restrict__ bg) {
   if (bg) {  // batched: packed spectra in the second half of V
@@ -1130,7 +1105,7 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, R, M>::G * rowfwd_cfg<R, R, M>:
   }
   using C = rowfwd_cfg<R, R, M>;
   constexpr int L = C::L, E = C::E, T = C::T, SLOT = C::SLOT;
-  __shared__ cx<R> smem[C::G * SLOT];
+  __shared__ cx<R> smem[rowc2r_cfg<R, M, HI>::G * SLOT];
   const int G = blockDim.x / T;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int row = xcd_tile(blockIdx.x, gridDim.x) * G + g;
@@ -1215,10 +1190,13 @@ struct spec_cfg {
   static constexpr int LL = lds_len<N>::value;
 };
 
+// fp32: 0 double, 1 float hi + lo pair, 2 float
 __device__ __forceinline__ void put_odd(void* tab, int fp32, int64_t idx, double v) {
-  if (fp32) {
+  if (fp32 == 1) {
     const float h = (float)v;
     reinterpret_cast<float2*>(tab)[idx] = make_float2(h, (float)(v - (double)h));
+  } else if (fp32 == 2) {
+    reinterpret_cast<float*>(tab)[idx] = (float)v;
   } else {
     reinterpret_cast<double*>(tab)[idx] = v;
   }
@@ -1381,10 +1359,16 @@ struct tabs {
   using odd = typename std::conditional<sizeof(R) == 4, float2, double>::type;
 };
 
+// Transform lengths with kernels: SG_SIZES for the column passes of this
+// file (the four-step column pass of sg_colfs.hip takes 4096 and 8192 as
+// well), SG_ROW_SIZES for the row passes and the coefficient solves.
 #ifndef SG_SIZES
 #define SG_SIZES(X)                                                                                        \
   X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(12) X(24) X(48) X(96) X(192) X(384) \
       X(768) X(1536)
+#endif
+#ifndef SG_ROW_SIZES
+#define SG_ROW_SIZES(X) SG_SIZES(X) X(8192)
 #endif
 
 // rows (or columns) per workgroup: the requested tile if it is in [1, cap],
@@ -1490,7 +1474,7 @@ static hipError_t row_fwd_dispatch(int M, const In* src, int64_t ld, cx<R>* X, i
 #define CASE(SZ) \
   case SZ:       \
     return launch_row_fwd_t<R, In, SZ>(src, ld, X, nrows, r2m, solve, full, tw, bg, ngrids, tile, st);
-    SG_SIZES(CASE)
+    SG_ROW_SIZES(CASE)
 #undef CASE
     default:
       return hipErrorInvalidValue;
@@ -1525,7 +1509,7 @@ static hipError_t row_inv_dispatch(int M, const cx<R>* V, Out* fx, Out* fy, int 
 #define CASE(SZ) \
   case SZ:       \
     return launch_row_inv_t<R, Out, SZ>(V, fx, fy, nrows, tj, r2m, tw, bg, ngrids, tile, st);
-    SG_SIZES(CASE)
+    SG_ROW_SIZES(CASE)
 #undef CASE
     default:
       return hipErrorInvalidValue;
@@ -1585,9 +1569,9 @@ static int max_tile_t(int pass, int len) {
 #define CASE(SZ)                                         \
   case SZ:                                               \
     if (pass == 0) return rowfwd_cfg<R, R, SZ>::G;       \
-    if (pass == 1) return col_cfg<R, SZ>::P;             \
+    if (pass == 1) return SZ > 4096 ? 1 : col_cfg<R, SZ>::P; \
     return rowinv_cfg<R, SZ>::G;
-    SG_SIZES(CASE)
+    SG_ROW_SIZES(CASE)
 #undef CASE
     default:
       return 0;
@@ -1634,7 +1618,7 @@ static hipError_t coeff_rows_dispatch(int M, const R* src, R* dst, int nrows, in
                        dst, nrows, sys);                                                            \
     return hipGetLastError();                                                                       \
   }
-    SG_SIZES(CASE)
+    SG_ROW_SIZES(CASE)
 #undef CASE
     default:
       return hipErrorInvalidValue;
@@ -1651,7 +1635,7 @@ static hipError_t coeff_cols_dispatch(int N, R* data, int M, int sys, hipStream_
     hipLaunchKernelGGL((k_coeff_cols<R, SZ>), dim3(M / P), dim3(P * C::T), 0, st, data, M, sys);      \
     return hipGetLastError();                                                                        \
   }
-    SG_SIZES(CASE)
+    SG_ROW_SIZES(CASE)
 #undef CASE
     default:
       return hipErrorInvalidValue;
@@ -1702,6 +1686,10 @@ static int tw_dispatch(int pass, int len, const void* roots, void* out, hipStrea
     return -1;
     SG_SIZES(CASE)
 #undef CASE
+    case 8192:  // row passes only (the columns of this length take the four-step pass)
+      if (pass == 0) return tw_build<R, 4096, rowfwd_cfg<R, R, 8192>::E>(roots, 4, out, st);
+      if (pass == 2) return tw_build<R, 8192, rowinv_cfg<R, 8192>::E>(roots, 2, out, st);
+      return 0;
     default:
       return -1;
   }
@@ -1749,13 +1737,16 @@ template <typename R, int M>
 static hipError_t launch_row_c2r_t(const cx<R>* Y, R* out, int nrows, int tj, const cx<R>* r2m, int solve,
                                    const cx<R>* tw, const sg_bgrid* bg, int ngrids, hipStream_t st) {
   using C = rowfwd_cfg<R, R, M>;
-  const int G = C::G < nrows ? C::G : nrows;
-  if (solve >= 4)
+  if (solve >= 4) {
+    constexpr int GH = rowc2r_cfg<R, M, true>::G;
+    const int G = GH < nrows ? GH : nrows;
     hipLaunchKernelGGL((k_row_c2r<R, R, M, true>), dim3((nrows + G - 1) / G, bg ? ngrids : 1), dim3(G * C::T), 0, st,
                        Y, out, nrows, tj, r2m, solve, tw, bg);
-  else
+  } else {
+    const int G = C::G < nrows ? C::G : nrows;
     hipLaunchKernelGGL((k_row_c2r<R, R, M>), dim3((nrows + G - 1) / G, bg ? ngrids : 1), dim3(G * C::T), 0, st, Y,
                        out, nrows, tj, r2m, solve, tw, bg);
+  }
   return hipGetLastError();
 }
 
@@ -1780,11 +1771,34 @@ static hipError_t adj_dispatch(int M, int N, const cx<R>* Xx, const cx<R>* Xy, c
 #define CASE(SZ) \
   case SZ:       \
     return launch_row_c2r_t<R, SZ>(Y, out, N, tj, r2m, solve, twA, bg, ngrids, st);
-    SG_SIZES(CASE)
+    SG_ROW_SIZES(CASE)
 #undef CASE
     default:
       return hipErrorInvalidValue;
   }
+}
+
+template <typename R>
+static hipError_t c2r_dispatch(int M, int N, const cx<R>* Y, R* out, int tj, const cx<R>* r2m, int solve,
+                               const cx<R>* twA, const sg_bgrid* bg, int ngrids, hipStream_t st) {
+  switch (M) {
+#define CASE(SZ) \
+  case SZ:       \
+    return launch_row_c2r_t<R, SZ>(Y, out, N, tj, r2m, solve, twA, bg, ngrids, st);
+    SG_ROW_SIZES(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t sg_launch_row_c2r(int prec, int M, int N, const void* Y, void* gsigma, int tj, const void* r2m, int solve,
+                             const void* twA, const sg_bgrid* bg, int ngrids, hipStream_t st) {
+  if (prec == 0)
+    return c2r_dispatch<double>(M, N, (const cx<double>*)Y, (double*)gsigma, tj, (const cx<double>*)r2m, solve,
+                                (const cx<double>*)twA, bg, ngrids, st);
+  return c2r_dispatch<float>(M, N, (const cx<float>*)Y, (float*)gsigma, tj, (const cx<float>*)r2m, solve,
+                             (const cx<float>*)twA, bg, ngrids, st);
 }
 
 hipError_t sg_launch_adjoint_tail(int prec, int M, int N, const void* Xx, const void* Xy, void* Y, void* gsigma,

@@ -47,10 +47,11 @@ def test_status_strings_and_arg_errors():
         (sg.sg_grid(100, 64, -1, 1, -1, 1, 3), 0, 0, 2),
         (sg.sg_grid(96, 6, -1, 1, -1, 1, 3), 0, 0, 2),
         (sg.sg_grid(3072, 64, -1, 1, -1, 1, 3), 0, 0, 2),
-        (sg.sg_grid(8192, 64, -1, 1, -1, 1, 3), 0, 0, 2),
-        (sg.sg_grid(64, 8192, -1, 1, -1, 1, 3), 1, 0, 2),
+        (sg.sg_grid(16384, 64, -1, 1, -1, 1, 3), 0, 0, 2),
+        (sg.sg_grid(64, 16384, -1, 1, -1, 1, 3), 1, 0, 2),
         (sg.sg_grid(64, 64, -1, 1, -1, 1, 3), 7, 0, 1),
         (sg.sg_grid(64, 64, -1, 1, -1, 1, 3), 0, 0x80, 1),
+        (sg.sg_grid(3072, 64, -1, 1, -1, 1, 3), 1, 0, 2),
     ]
     for g, prec, flags, want in bad:
         arr = (sg.sg_grid * 1)(g)

@@ -12,9 +12,11 @@ adjoint's own rounding).
 * autograd gradient of L = sum |F - F_target|^2 against the oracle at 256^2;
 * central finite differences of L on the FP64 path at 256 x 128 (L is
   quadratic in sigma, so the differences are exact up to rounding);
-* 4096^2 plus four 2048^2 grids in one plan: FP32-split gradient against the
-  FP64 gradient, and finite differences at 64 seeded cells of the 4096^2
-  grid (the 8192^2 form of this case is skipped: the library refuses 8192).
+* 8192^2 (and 4096^2) plus four 2048^2 grids in one plan: FP32-split
+  gradient against the FP64 gradient, and finite differences at 64 seeded
+  cells of the large grid;
+* the FP32-split adjoint of the cubic and quartic splines (k = 4, 5) at
+  1024^2 and 4096^2 against the FP64 adjoint of the same gradients.
 """
 import numpy as np
 import pytest
@@ -112,13 +114,6 @@ def test_autograd_gradient_against_oracle_256():
             plan.close()
         err = np.abs(got - ref).max() / np.abs(ref).max()
         assert err <= tol, (prec, err)
-
-
-# The 8192^2 case below ran in a GPU command that faulted the device; its
-# 8192 kernels needed 2.2 KB/lane of scratch, above what the build now
-# allows, and the library refuses 8192 grids, so it stays skipped.
-_FAULT_SKIP = pytest.mark.skip(reason="needs 8192^2 grids: their kernels spilled 2.2 KB/lane of scratch and "
-                               "faulted the device; the library refuses 8192 until they are rebuilt without spills")
 
 
 def _fd_check(plan, sigma_t, target, grad, cells, delta):
@@ -220,12 +215,10 @@ def _at_scale(grids):
 
 
 def test_differentiation_at_scale_multigrid_4096():
-    """4096^2 (the largest supported size) with four 2048^2 grids alongside,
-    in one plan (packed buffers)."""
+    """4096^2 with four 2048^2 grids alongside, in one plan (packed buffers)."""
     _at_scale([(4096, 4096, -1.0, 1.0, -1.0, 1.0, 3)] + [(2048, 2048, -1.0, 1.0, -1.0, 1.0, 3)] * 4)
 
 
-@_FAULT_SKIP
 def test_differentiation_at_scale_multigrid():
     """8192^2 with four 2048^2 grids alongside, in one plan (packed buffers)."""
     _at_scale([(8192, 8192, -1.0, 1.0, -1.0, 1.0, 3)] + [(2048, 2048, -1.0, 1.0, -1.0, 1.0, 3)] * 4)
@@ -267,3 +260,29 @@ def test_autograd_multigrid_plan_equals_single_plans():
                 assert torch.equal(s1.grad, batched[offs[gi]:offs[gi + 1]]), (prec, gi)
             finally:
                 p1.close()
+
+
+@pytest.mark.parametrize("n,k", [(1024, 4), (1024, 5), (4096, 4), (4096, 5)])
+def test_adjoint_fp32_higher_orders_full_size(n, k):
+    """The FP32-split adjoint of k = 4, 5 at full size (its row pass carries
+    the banded x-solve of those orders) against the FP64 adjoint."""
+    sg = _sg()
+    import torch
+    grid = (n, n, -1.0, 1.0, -1.0, 1.0, k)
+    g = torch.Generator(device="cuda").manual_seed(n + k)
+    gx = torch.randn(n * n, dtype=torch.float64, device="cuda", generator=g)
+    gy = torch.randn(n * n, dtype=torch.float64, device="cuda", generator=g)
+    plan = sg.Plan([grid], sg.SG_FP64)
+    try:
+        ref = plan.adjoint(gx, gy)
+    finally:
+        plan.close()
+    p32 = sg.Plan([grid], sg.SG_FP32_SPLIT)
+    try:
+        got = p32.adjoint(gx.float(), gy.float())
+        torch.cuda.synchronize()
+        err = ((got.double() - ref).abs().max() / ref.abs().max()).item()
+    finally:
+        p32.close()
+    # random gradients: FP32 transform rounding and input rounding, relative to max|g_sigma|
+    assert err <= 2e-6, err
