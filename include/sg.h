@@ -59,11 +59,12 @@ typedef enum {
 typedef enum {
   SG_FP64 = 0,       /* every per-step array double; FFT and products in FP64 */
   SG_FP32_SPLIT = 1  /* float arrays; coefficient solve in FP64, FFT in FP32 with
-                        FP64-derived twiddles, kernel spectrum carried as hi+lo floats */
+                        FP64-derived twiddles; kernel spectra as hi+lo float pairs (as single floats
+                        for ny = 4096, 8192 unless SG_FLAG_SPECTRA_SPLIT) */
 } sg_precision;
 
 /* One grid.  Cell sizes are dx = (x1-x0)/nx, dy = (y1-y0)/ny (Sec. 2, grid
- * points x_{i+1/2} = x0 + i dx).  nx, ny: each 2^a from 4 to 4096 or
+ * points x_{i+1/2} = x0 + i dx).  nx, ny: each 2^a from 4 to 8192 or
  * 3 * 2^a from 12 to 1536 (other sizes: SG_ERR_UNSUPPORTED). */
 typedef struct {
   int32_t nx, ny;
@@ -75,9 +76,11 @@ typedef struct {
 #define SG_FLAG_CHECK_FINITE 0x1u /* sg_forces rejects non-finite sigma (SG_ERR_STATE); costs one extra read */
 #define SG_FLAG_GRAPH 0x2u        /* sg_forces replays a captured HIP graph of the whole step (see sg_forces) */
 #define SG_FLAG_AUTOTUNE 0x4u     /* sg_plan_create times the launch tiles of every class and keeps the best */
-#define SG_FLAG_SPECTRA_F32 0x8u  /* SG_FP32_SPLIT: kernel spectra of grids with ny = 4096 or 8192 stored as
-                                     single floats (4 B per bin) instead of hi + lo pairs: half the table
-                                     traffic of the column pass; ignored by SG_FP64 plans */
+#define SG_FLAG_SPECTRA_SPLIT 0x8u /* SG_FP32_SPLIT: keep the kernel spectra of grids with ny = 4096 or 8192
+                                      as hi + lo float pairs (8 B per bin).  Without it those grids' spectra are
+                                      single floats (4 B per bin; the lo part moves the error by about 10 %, well
+                                      inside 1e-6, and costs 8 B per cell of column-pass traffic); smaller grids
+                                      always keep hi + lo.  Ignored by SG_FP64 plans. */
 
 /* Create a plan for ngrids grids (all of one precision) on the given HIP
  * stream (hipStream_t; NULL = the null stream).  Plan time does what the

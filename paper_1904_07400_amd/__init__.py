@@ -18,7 +18,7 @@ import os
 import threading
 
 __all__ = [
-    "SG_FP64", "SG_FP32_SPLIT", "SG_FLAG_CHECK_FINITE", "SG_FLAG_GRAPH", "SG_FLAG_AUTOTUNE", "SG_FLAG_SPECTRA_F32", "SGError",
+    "SG_FP64", "SG_FP32_SPLIT", "SG_FLAG_CHECK_FINITE", "SG_FLAG_GRAPH", "SG_FLAG_AUTOTUNE", "SG_FLAG_SPECTRA_SPLIT", "SGError",
     "sg_grid", "lib", "sg_plan_classes",
     "sg_plan_create", "sg_plan_destroy", "sg_plan_layout", "sg_plan_info", "sg_sample_points",
     "sg_weights", "sg_bspline_coeffs", "sg_forces", "sg_forces_adjoint", "sg_status_string",
@@ -30,7 +30,7 @@ SG_FP32_SPLIT = 1
 SG_FLAG_CHECK_FINITE = 0x1
 SG_FLAG_GRAPH = 0x2
 SG_FLAG_AUTOTUNE = 0x4
-SG_FLAG_SPECTRA_F32 = 0x8
+SG_FLAG_SPECTRA_SPLIT = 0x8
 STATUS = {0: "SG_OK", 1: "SG_ERR_ARG", 2: "SG_ERR_UNSUPPORTED", 3: "SG_ERR_NOMEM",
           4: "SG_ERR_DEVICE", 5: "SG_ERR_STATE"}
 

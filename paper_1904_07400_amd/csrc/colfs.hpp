@@ -79,7 +79,12 @@ struct colfs_cfg {
 // COMP: 0 both force components; 1 the x component only, Yx left in V(p);
 // 2 the y component, combined with the Yx of a COMP = 1 launch into V(p),
 // V(2M - p) (two launches, half the registers of one).
-template <typename R, typename TO, int N, int MODE, int E, int SLOTS, int COMP>
+// PF: a workgroup loops over columns b, b + gridDim.x, ... (in the order
+// that keeps an XCD's columns together) and loads the next column and its
+// table entries while it transforms the current one; the phases w_2N^j stay
+// in registers, so that no load in the loop body waits behind the prefetch
+// (loads complete in order).  Needs the table entries in registers (KEEP).
+template <typename R, typename TO, int N, int MODE, int E, int SLOTS, int COMP, bool PF = false>
 __global__ void __launch_bounds__(N / E)
     k_colfs(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
             const TO* __restrict__ toy, const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ twfs,
@@ -104,33 +109,66 @@ __global__ void __launch_bounds__(N / E)
   cx<R>* A0 = smem;
   cx<R>* A1 = SLOTS == 4 ? smem + 2 * SL : smem;
   constexpr bool cautious = SLOTS < 4;
-  const int t = threadIdx.x;
-  const int c = xcd_tile(blockIdx.x, gridDim.x);
-  const bool packed = (c == 0);
-  const cx<R>* col = X + (int64_t)c * N;
-
-  // ---- loads: the column (chunk of E per thread for the solve, else D1),
-  // the spectrum-table entries of this thread's D3 bins, the twiddles
-  cx<R> a[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) a[e] = col[(unsigned)(solve ? t * E + e : S::d1_index(t, e))];
+  const int t0 = threadIdx.x;
   constexpr bool pre = C::KEEP;
+  static_assert(!PF || (pre && COMP == 0), "the prefetching loop keeps the table entries in registers");
   constexpr int NT = COMP == 0 ? 4 : 2;  // tables used: (x even, y even, x odd, y odd) or one component's halves
-  TO tv[pre ? NT : 1][pre ? E : 1];
-  const TO* rowx = tox + (int64_t)c * (N + 1);
-  const TO* rowy = toy + (int64_t)c * (N + 1);
   // table of product i: component (COMP 0: i & 1; else COMP - 1), half (COMP 0: i >> 1; else i)
   auto comp_of = [](int i) { return COMP == 0 ? (i & 1) : COMP - 1; };
   auto half_of = [](int i) { return COMP == 0 ? (i >> 1) : i; };
-  if constexpr (pre) {
+  // ---- loads of a column: the column (chunk of E per thread for the solve,
+  // else D1); the spectrum-table entries of this thread's D3 bins
+  auto load_col = [&](int t, int cc, cx<R> (&aa)[E]) {
+    const cx<R>* col = X + (int64_t)cc * N;
 #pragma unroll
-    for (int i = 0; i < NT; ++i)
+    for (int e = 0; e < E; ++e) aa[e] = col[(unsigned)(solve ? t * E + e : S::d1_index(t, e))];
+  };
+  auto load_tab = [&](int t, int cc, TO (&tt)[pre ? NT : 1][pre ? E : 1]) {
+    if constexpr (pre) {
+      const TO* rx = tox + (int64_t)cc * (N + 1);
+      const TO* ry = toy + (int64_t)cc * (N + 1);
 #pragma unroll
-      for (int r = 0; r < E; ++r)
-        tv[i][r] = (comp_of(i) ? rowy : rowx)[(unsigned)fs_tab_index<TO, N>(S::d3_index(t, r), half_of(i))];
-  }
+      for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int r = 0; r < E; ++r)
+          tt[i][r] = (comp_of(i) ? ry : rx)[(unsigned)fs_tab_index<TO, N>(S::d3_index(t, r), half_of(i))];
+    }
+  };
   fs_tw<N, E, R, C::KEEP> tw;
-  tw.init(twfs, t);
+  tw.init(twfs, t0);
+  cx<R> w2k[PF ? E : 1];  // w_2N^j of this thread's D1 elements, kept by the loop
+  if constexpr (PF) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) w2k[e] = r2n[(unsigned)S::d1_index(t0, e)];
+  }
+  cx<R> a[E];
+  int it = blockIdx.x;
+  load_col(t0, xcd_tile(it, M), a);
+  for (;;) {
+  // the thread index through opaque(): the per-thread index arithmetic of
+  // the loop body stays in the body instead of being hoisted out of the loop
+  // and held in registers across it
+  const int t = PF ? opaque(t0) : t0;
+  auto w2n_at = [&](int e) -> cx<R> {
+    if constexpr (PF) return w2k[e];
+    else return r2n[(unsigned)opaque(S::d1_index(t, e))];
+  };
+  const int c = xcd_tile(it, M);
+  const bool packed = (c == 0);
+  const TO* rowx = tox + (int64_t)c * (N + 1);
+  const TO* rowy = toy + (int64_t)c * (N + 1);
+  const int itn = it + (int)gridDim.x;
+  // this column's table entries first, then (PF) the next column: loads
+  // complete in order, so waiting for the entries leaves the prefetch in
+  // flight
+  TO tv[pre ? NT : 1][pre ? E : 1];
+  load_tab(t, c, tv);
+  cx<R> an[PF ? E : 1];
+  if constexpr (PF) {
+    // unconditional (the last column reloads itself), so that the loads
+    // issue together without a branch
+    load_col(t, xcd_tile(itn < M ? itn : it, M), an);
+  }
 
   // ---- y-solve (FP64, chunks), then into D1 through slot 0
   if constexpr (solve) {
@@ -159,7 +197,7 @@ __global__ void __launch_bounds__(N / E)
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     f[0][e] = a[e];
-    f[1][e] = cmul(a[e], r2n[(unsigned)S::d1_index(t, e)]);
+    f[1][e] = cmul(a[e], w2n_at(e));
   }
   if constexpr (SLOTS == 1) {
 #pragma unroll
@@ -330,7 +368,7 @@ __global__ void __launch_bounds__(N / E)
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int j = S::d1_index(t, e);
-    const cx<R> w = r2n[(unsigned)opaque(j)];
+    const cx<R> w = w2n_at(e);
     const int64_t o = (int64_t)(j / tj) * jstride + (j % tj);
     if constexpr (COMP == 1) {
       va[o] = g[0][e] + cmulc(g[1][e], w);  // Yx, kept for the y launch
@@ -348,6 +386,16 @@ __global__ void __launch_bounds__(N / E)
       va[o] = v1;
       vb[o] = v2;
     }
+  }
+  if constexpr (!PF) {
+    break;
+  } else {
+    if (itn >= M) break;
+    it = itn;
+#pragma unroll
+    for (int e = 0; e < E; ++e) a[e] = an[e];
+    __syncthreads();  // this column's last LDS reads come before the next column's writes
+  }
   }
 }
 

@@ -530,7 +530,7 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
   *out = nullptr;
   if (!grids || ngrids < 1) return fail(SG_ERR_ARG, "need at least one grid (ngrids=%d)", ngrids);
   if (prec != SG_FP64 && prec != SG_FP32_SPLIT) return fail(SG_ERR_ARG, "unknown precision %d", (int)prec);
-  if (flags & ~(SG_FLAG_CHECK_FINITE | SG_FLAG_GRAPH | SG_FLAG_AUTOTUNE | SG_FLAG_SPECTRA_F32))
+  if (flags & ~(SG_FLAG_CHECK_FINITE | SG_FLAG_GRAPH | SG_FLAG_AUTOTUNE | SG_FLAG_SPECTRA_SPLIT))
     return fail(SG_ERR_ARG, "unknown flags 0x%x", flags);
   for (int i = 0; i < ngrids; ++i) {
     const sg_grid& g = grids[i];
@@ -588,10 +588,10 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
       const bool off = env && strcmp(env, "0") == 0 && G.N <= 4096;
       G.fs = sg_colfs_supported(prec == SG_FP64 ? 0 : 1, G.N) && !off;
     }
-    // one real per bin (FP64, hi+lo FP32, or with SG_FLAG_SPECTRA_F32 and the
-    // four-step pass, FP32) on a quarter of the lattice; for even k the bin
-    // phase is applied in the column pass
-    G.tab_bytes = (prec == SG_FP32_SPLIT && G.fs && (flags & SG_FLAG_SPECTRA_F32)) ? 4 : 8;
+    // one real per bin on a quarter of the lattice: FP64; hi+lo FP32; or, for
+    // the four-step pass of FP32-split plans without SG_FLAG_SPECTRA_SPLIT,
+    // FP32.  For even k the bin phase is applied in the column pass.
+    G.tab_bytes = (prec == SG_FP32_SPLIT && G.fs && !(flags & SG_FLAG_SPECTRA_SPLIT)) ? 4 : 8;
     const size_t tab_el = (size_t)G.tab_bytes;
     const size_t tab_n = (size_t)(G.M + 1) * (G.N + 1);
     // grids of equal size, order, cell shape and table form share one pair of spectra

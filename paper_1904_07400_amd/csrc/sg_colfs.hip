@@ -9,6 +9,10 @@
 #ifndef SG_COLFS_SPLIT_D4096
 #define SG_COLFS_SPLIT_D4096 0
 #endif
+// the prefetching persistent loop (FP32, 4096, single-float tables)
+#ifndef SG_COLFS_PF
+#define SG_COLFS_PF 1
+#endif
 
 namespace sg {
 
@@ -39,12 +43,35 @@ struct colfs_sel<double, 8192> {
   static constexpr int E = 16, SLOTS = 1, SPLIT = 1;
 };
 
+// Compute units of the current device (the persistent launches' width).
+static int device_cus() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 256;
+  return n > 0 ? n : 256;
+}
+
+// The prefetching loop for FP32 columns of 4096 with single-float tables
+// (its registers fit only then): one workgroup per compute unit.
+template <typename R, typename TO, int N, int MODE>
+struct colfs_pf {
+  // odd orders only: the even orders' bin phases leave no registers for it
+  static constexpr bool on = SG_COLFS_PF && sizeof(R) == 4 && N == 4096 && sizeof(TO) == 4 && (MODE % 2 == 0);
+};
+
 template <typename R, typename TO, int N, int MODE, int COMP>
 static void launch_colfs_k(const cx<R>* X, cx<R>* V, int M, int tj, const TO* tox, const TO* toy, const cx<R>* r2n,
                            const cx<R>* tw, const sg_bgrid* bg, int ngrids, hipStream_t st) {
   using Sel = colfs_sel<R, N>;
-  hipLaunchKernelGGL((k_colfs<R, TO, N, MODE, Sel::E, Sel::SLOTS, COMP>), dim3(M, bg ? ngrids : 1),
-                     dim3(N / Sel::E), 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+  if constexpr (colfs_pf<R, TO, N, MODE>::on && COMP == 0) {
+    static const int cus = device_cus();
+    const int nb = M < cus ? M : cus;
+    hipLaunchKernelGGL((k_colfs<R, TO, N, MODE, Sel::E, Sel::SLOTS, COMP, true>), dim3(nb, bg ? ngrids : 1),
+                       dim3(N / Sel::E), 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+  } else {
+    hipLaunchKernelGGL((k_colfs<R, TO, N, MODE, Sel::E, Sel::SLOTS, COMP>), dim3(M, bg ? ngrids : 1),
+                       dim3(N / Sel::E), 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+  }
 }
 
 template <typename R, typename TO, int N, int MODE>

@@ -34,12 +34,17 @@ static void rd(FILE* f, std::vector<T>& v, size_t n) {
 #define EMU_KERNEL 0
 #endif
 
+#ifndef EMU_PF
+#define EMU_PF 0
+#endif
+
 template <int CP>
 static void run_one(int M, int tj, std::vector<cx<R>>& X, std::vector<cx<R>>& V, std::vector<TO>& tx,
                     std::vector<TO>& ty, std::vector<cx<R>>& r2n, std::vector<cx<R>>& tw) {
-  emu::launch(dim3(M), dim3(N / E), [&] {
-    k_colfs<R, TO, N, MODE, E, SLOTS, CP>(X.data(), V.data(), M, tj, tx.data(), ty.data(), r2n.data(), tw.data(),
-                                          nullptr);
+  // EMU_PF: the prefetching loop with two workgroups, each taking several columns
+  emu::launch(dim3(EMU_PF ? 2 : M), dim3(N / E), [&] {
+    k_colfs<R, TO, N, MODE, E, SLOTS, CP, (bool)EMU_PF>(X.data(), V.data(), M, tj, tx.data(), ty.data(), r2n.data(),
+                                                        tw.data(), nullptr);
   });
 }
 

@@ -25,13 +25,13 @@ pytestmark = pytest.mark.slow
 GXX = shutil.which("g++")
 
 
-def _build(tmp, kernel, prec, N, E, slots, k, to, split):
+def _build(tmp, kernel, prec, N, E, slots, k, to, split, pf=0):
     R = "float" if prec == 32 else "double"
-    exe = os.path.join(tmp, f"emu_{kernel}_{prec}_{N}_{E}_{slots}_{k}_{to}_{split}")
+    exe = os.path.join(tmp, f"emu_{kernel}_{prec}_{N}_{E}_{slots}_{k}_{to}_{split}_{pf}")
     cmd = [GXX, "-std=c++20", "-O1", "-g", "-fsanitize=thread", "-I" + os.path.join(HERE, "emu"),
            "-I" + os.path.join(ROOT, "paper_1904_07400_amd", "csrc"), "-I" + os.path.join(ROOT, "include"),
            f"-DEMU_KERNEL={kernel}", f"-DEMU_R={R}", f"-DEMU_TO={to}", f"-DEMU_N={N}", f"-DEMU_E={E}",
-           f"-DEMU_SLOTS={slots}", f"-DEMU_MODE={k - 1}", f"-DEMU_SPLIT={split}",
+           f"-DEMU_SLOTS={slots}", f"-DEMU_MODE={k - 1}", f"-DEMU_SPLIT={split}", f"-DEMU_PF={pf}",
            os.path.join(HERE, "emu", "colfs_driver.cpp"), "-o", exe, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
@@ -62,16 +62,17 @@ def _run(exe, M, path_in, path_out):
     return races
 
 
-FWD = [(32, 4096, 8, 4, 3, "float2", 0), (32, 4096, 8, 4, 2, "float", 0), (32, 4096, 8, 4, 5, "float2", 0),
-       (32, 8192, 16, 2, 4, "float", 1), (64, 4096, 8, 2, 3, "double", 1), (64, 8192, 16, 1, 2, "double", 1)]
+FWD = [(32, 4096, 8, 4, 3, "float2", 0, 0), (32, 4096, 8, 4, 2, "float", 0, 0), (32, 4096, 8, 4, 5, "float2", 0, 0),
+       (32, 8192, 16, 2, 4, "float", 1, 0), (64, 4096, 8, 2, 3, "double", 1, 0), (64, 8192, 16, 1, 2, "double", 1, 0),
+       (32, 4096, 8, 4, 3, "float", 0, 1), (32, 4096, 8, 4, 1, "float", 0, 1)]
 
 
 @pytest.mark.skipif(GXX is None, reason="g++ not found")
-@pytest.mark.parametrize("prec,N,E,slots,k,to,split", FWD, ids=[f"fp{c[0]}-{c[1]}-s{c[3]}-k{c[4]}-{c[5]}-split{c[6]}"
-                                                                 for c in FWD])
-def test_column_pass(tmp_path, prec, N, E, slots, k, to, split):
-    M = 4
-    exe = _build(str(tmp_path), 0, prec, N, E, slots, k, to, split)
+@pytest.mark.parametrize("prec,N,E,slots,k,to,split,pf", FWD,
+                         ids=[f"fp{c[0]}-{c[1]}-s{c[3]}-k{c[4]}-{c[5]}-split{c[6]}-pf{c[7]}" for c in FWD])
+def test_column_pass(tmp_path, prec, N, E, slots, k, to, split, pf):
+    M = 5 if pf else 4  # the prefetching loop: two workgroups over five columns
+    exe = _build(str(tmp_path), 0, prec, N, E, slots, k, to, split, pf)
     rng = np.random.default_rng(k * 11 + N)
     X = rng.standard_normal((M, N)) + 1j * rng.standard_normal((M, N))
     tx, ty, stored = _tables(rng, M, N, to)
