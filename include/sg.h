@@ -139,6 +139,22 @@ sg_status sg_bspline_coeffs(sg_plan p, const void* sigma, void* coeffs);
  * later work on it.  Per-pass timing is not recorded for graph plans. */
 sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy);
 
+/* sg_forces for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same launches,
+ * results and arguments as sg_forces, with the per-step workspace (row
+ * spectra X and combined spectra V of every grid) in a fixed 64 MiB device
+ * array of the library instead of the plan's own.  Nothing is allocated,
+ * freed, cleared or synchronised; the launches are eager (no graph) and
+ * SG_FLAG_CHECK_FINITE is not applied.  The array is set up once per device
+ * at plan creation and held until the process ends.  Limit: the workspace of
+ * the plan's grids, 24 B per cell in FP32-split and 48 B per cell in FP64
+ * plus 256-byte alignment per array (e.g. one 1024^2 grid), must fit in 64
+ * MiB, else SG_ERR_ARG.  Every call on a GPU shares that GPU's array: calls
+ * that overlap in time on one GPU (other streams, other plans, other host
+ * threads) race and give wrong forces; the array keeps the last call's
+ * contents, which the next call overwrites before reading. */
+sg_status sg_forces_noalloc(sg_plan p, const void* sigma, void* fx, void* fy);
+
 /* The plan's grid classes: *nclasses (HOST) and, for the first cap classes,
  * 8 HOST int32 each in info: nx, ny, order, number of grids, then the rows
  * per workgroup of the row passes and the columns per workgroup of the

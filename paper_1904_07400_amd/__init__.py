@@ -21,7 +21,7 @@ __all__ = [
     "SG_FP64", "SG_FP32_SPLIT", "SG_FLAG_CHECK_FINITE", "SG_FLAG_GRAPH", "SG_FLAG_AUTOTUNE", "SG_FLAG_SPECTRA_SPLIT", "SGError",
     "sg_grid", "lib", "sg_plan_classes",
     "sg_plan_create", "sg_plan_destroy", "sg_plan_layout", "sg_plan_info", "sg_sample_points",
-    "sg_weights", "sg_bspline_coeffs", "sg_forces", "sg_forces_adjoint", "sg_status_string",
+    "sg_weights", "sg_bspline_coeffs", "sg_forces", "sg_forces_noalloc", "sg_forces_adjoint", "sg_status_string",
     "sg_last_error_message", "sg_plan_set_timing", "sg_plan_pass_times", "Plan", "ThinDiskForces",
 ]
 
@@ -73,6 +73,7 @@ def lib() -> ctypes.CDLL:
             L.sg_bspline_coeffs.argtypes = [vp, vp, vp]
             L.sg_forces.argtypes = [vp, vp, vp, vp]
             L.sg_forces_adjoint.argtypes = [vp, vp, vp, vp]
+            L.sg_forces_noalloc.argtypes = [vp, vp, vp, vp]
             L.sg_plan_set_timing.argtypes = [vp, i32]
             L.sg_plan_classes.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), i32]
             L.sg_plan_pass_times.argtypes = [vp, dp, ctypes.POINTER(i64)]
@@ -81,7 +82,7 @@ def lib() -> ctypes.CDLL:
             L.sg_last_error_message.argtypes = []
             L.sg_last_error_message.restype = ctypes.c_char_p
             for f in ("sg_plan_create", "sg_plan_destroy", "sg_plan_layout", "sg_plan_info",
-                      "sg_sample_points", "sg_weights", "sg_bspline_coeffs", "sg_forces",
+                      "sg_sample_points", "sg_weights", "sg_bspline_coeffs", "sg_forces", "sg_forces_noalloc",
                       "sg_forces_adjoint", "sg_plan_set_timing", "sg_plan_pass_times", "sg_plan_classes"):
                 getattr(L, f).restype = ctypes.c_int
             _lib = L
@@ -183,6 +184,10 @@ def sg_bspline_coeffs(plan: int, sigma, coeffs) -> None:
 
 def sg_forces(plan: int, sigma, fx, fy) -> None:
     _check(lib().sg_forces(plan, _ptr(sigma), _ptr(fx), _ptr(fy)))
+
+
+def sg_forces_noalloc(plan: int, sigma, fx, fy) -> None:
+    _check(lib().sg_forces_noalloc(plan, _ptr(sigma), _ptr(fx), _ptr(fy)))
 
 
 def sg_forces_adjoint(plan: int, gfx, gfy, gsigma) -> None:

@@ -9,12 +9,21 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
 
 #include "sg.h"
 #include "sg_internal.h"
+
+// Workspace of sg_forces_noalloc: a file-scope device array, one per GPU the
+// library runs on, held until the process ends.  Host code never uses the
+// array's name as an address (it is a host-side stand-in): each device's
+// address comes from hipGetSymbolAddress at plan creation, with that device
+// current, and is kept per device.
+#define SG_NOALLOC_BYTES (64ull << 20)
+static __device__ __align__(256) unsigned char scratch[SG_NOALLOC_BYTES];
 
 namespace {
 
@@ -28,6 +37,24 @@ sg_status fail(sg_status s, const char* fmt, ...) {
   va_end(ap);
   g_msg = buf;
   return s;
+}
+
+// Device address of scratch on the current device (once per device).
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+hipError_t scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = ptr;
+  *out = ptr;
+  return hipSuccess;
 }
 
 bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
@@ -119,6 +146,7 @@ struct GridClass {
   std::vector<int> members;
   sg_bgrid* desc = nullptr;
   sg_bgrid* desc_y = nullptr;  // the same with X = V (adjoint: row spectra of gy)
+  sg_bgrid* desc_s = nullptr;  // the same with X and V in the no-allocation scratch
   int tile[3] = {0, 0, 0};  // rows / columns per workgroup of passes A, B, C (0 = compiled maximum)
 };
 
@@ -153,6 +181,8 @@ struct sg_plan_s {
   bool timing = false;         // per-pass event timing (sg_plan_set_timing)
   std::vector<hipEvent_t> ev;  // 4 events per grid and call while timing
   int64_t timed_calls = 0;
+  int64_t noalloc_bytes = 0;   // X and V of every grid laid out in scratch
+  bool noalloc_ok = false;     // they fit (sg_forces_noalloc usable)
 };
 
 namespace {
@@ -360,16 +390,17 @@ constexpr int kSideStreams = 4;
 
 // The column pass of one class: the four-step kernel for long columns, the
 // Stockham kernel otherwise.
-hipError_t launch_cols(sg_plan p, const GridClass& c, int tile, hipStream_t q) {
+hipError_t launch_cols(sg_plan p, const GridClass& c, int tile, hipStream_t q, const sg_bgrid* desc = nullptr) {
   const int prec = p->prec == SG_FP64 ? 0 : 1;
   const GridPlan& G = p->grids[c.members[0]];
   const int solve = c.k >= 3 ? c.k : 0;
   const int ng = (int)c.members.size();
   const int tj = sg_row_tile(prec, c.M, c.N);
+  const sg_bgrid* d = desc ? desc : c.desc;
   if (G.fs)
     return sg_launch_colfs(prec, c.N, nullptr, nullptr, c.M, tj, nullptr, nullptr, G.kind, G.tab_bytes, G.r2n, solve,
-                           G.twfs, c.desc, ng, q);
-  return sg_launch_col(prec, c.N, nullptr, nullptr, c.M, tj, nullptr, nullptr, G.kind, G.r2n, solve, G.twB, c.desc, ng,
+                           G.twfs, d, ng, q);
+  return sg_launch_col(prec, c.N, nullptr, nullptr, c.M, tj, nullptr, nullptr, G.kind, G.r2n, solve, G.twB, d, ng,
                        tile, q);
 }
 
@@ -656,7 +687,7 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
     for (GridClass& x : p->classes)
       if (x.M == G.M && x.N == G.N && x.k == G.k) c = &x;
     if (!c) {
-      p->classes.push_back(GridClass{G.M, G.N, G.k, {}, nullptr, nullptr, {0, 0, 0}});
+      p->classes.push_back(GridClass{G.M, G.N, G.k, {}, nullptr, nullptr, nullptr, {0, 0, 0}});
       c = &p->classes.back();
     }
     c->members.push_back(i);
@@ -677,6 +708,40 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
     if (s == SG_OK)
       s = hip_check(p, hipMemcpy(c.desc_y, h.data(), h.size() * sizeof(sg_bgrid), hipMemcpyHostToDevice),
                     "descriptor upload");
+  }
+  // the no-allocation variant: every grid's X and V laid out in scratch
+  // (256-byte aligned), with descriptors of their own
+  if (s == SG_OK) {
+    const size_t cb = prec == SG_FP64 ? 16 : 8;
+    std::vector<int64_t> xo(p->grids.size()), vo(p->grids.size());
+    int64_t at = 0;
+    for (size_t i = 0; i < p->grids.size(); ++i) {
+      const GridPlan& G = p->grids[i];
+      xo[i] = at;
+      at += ((int64_t)(cb * (size_t)G.M * G.N) + 255) / 256 * 256;
+      vo[i] = at;
+      at += ((int64_t)(cb * 2 * (size_t)G.M * G.N) + 255) / 256 * 256;
+    }
+    p->noalloc_bytes = at;
+    p->noalloc_ok = at <= (int64_t)SG_NOALLOC_BYTES;
+    void* base = nullptr;
+    if (p->noalloc_ok) {
+      hipError_t e = scratch_address(p->device, &base);
+      if (e != hipSuccess) s = hip_check(p, e, "hipGetSymbolAddress(scratch)");
+    }
+    for (GridClass& c : p->classes) {
+      if (s != SG_OK || !p->noalloc_ok) break;
+      std::vector<sg_bgrid> h(c.members.size());
+      for (size_t j = 0; j < c.members.size(); ++j) {
+        const int gi = c.members[j];
+        const GridPlan& G = p->grids[gi];
+        h[j] = sg_bgrid{G.off, (char*)base + xo[gi], (char*)base + vo[gi], G.tabx, G.taby};
+      }
+      s = dev_alloc(p, (void**)&c.desc_s, h.size() * sizeof(sg_bgrid));
+      if (s == SG_OK)
+        s = hip_check(p, hipMemcpy(c.desc_s, h.data(), h.size() * sizeof(sg_bgrid), hipMemcpyHostToDevice),
+                      "descriptor upload");
+    }
   }
   if (s == SG_OK && (flags & SG_FLAG_GRAPH)) {
     const int nside = std::min<int>(kSideStreams, (int)p->classes.size());
@@ -855,6 +920,33 @@ sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy) {
     if (e != hipSuccess) return hip_check(p, e, "force launch");
   }
   if (p->timing) ++p->timed_calls;
+  return SG_OK;
+}
+
+sg_status sg_forces_noalloc(sg_plan p, const void* sigma, void* fx, void* fy) {
+  g_msg.clear();
+  sg_status s = step_entry(p);
+  if (s != SG_OK) return s;
+  if (!sigma || !fx || !fy) return fail(SG_ERR_ARG, "sigma, fx or fy is NULL");
+  if (fx == fy || fx == sigma || fy == sigma) return fail(SG_ERR_ARG, "fx, fy and sigma must not alias");
+  if (!p->noalloc_ok)
+    return fail(SG_ERR_ARG, "the plan's workspace (%lld bytes) exceeds the %llu-byte no-allocation scratch",
+                (long long)p->noalloc_bytes, (unsigned long long)SG_NOALLOC_BYTES);
+  const int prec = p->prec == SG_FP64 ? 0 : 1;
+  // the same launches as sg_forces (eager, on the plan's stream), with X and
+  // V in scratch; nothing is allocated, cleared or synchronised
+  for (const GridClass& c : p->classes) {
+    const GridPlan& G = p->grids[c.members[0]];
+    const int solve = c.k >= 3 ? c.k : 0;
+    const int ng = (int)c.members.size();
+    const int tj = sg_row_tile(prec, c.M, c.N);
+    hipError_t e = sg_launch_row_fwd(prec, c.M, sigma, c.M, nullptr, c.N, G.r2m, solve, 0, G.twA, c.desc_s, ng,
+                                     c.tile[0], p->st);
+    if (e == hipSuccess) e = launch_cols(p, c, c.tile[1], p->st, c.desc_s);
+    if (e == hipSuccess)
+      e = sg_launch_row_inv(prec, c.M, nullptr, fx, fy, c.N, tj, G.r2m, G.twC, c.desc_s, ng, c.tile[2], p->st);
+    if (e != hipSuccess) return hip_check(p, e, "force launch (no allocation)");
+  }
   return SG_OK;
 }
 
