@@ -75,9 +75,14 @@ def time_plan(sg, torch, grid, prec, sigma_np, steps, warmup, flags=0):
     return ms, [p / calls for p in pass_ms], plan_s, out
 
 
-KERNEL_SOURCES = ["paper_1904_07400_amd/csrc/sg_kernels.hip", "paper_1904_07400_amd/csrc/fft.hpp",
+KERNEL_SOURCES = ["paper_1904_07400_amd/csrc/sg_kernels.hip", "paper_1904_07400_amd/csrc/sg_colfs.hip",
+                  "paper_1904_07400_amd/csrc/fft.hpp", "paper_1904_07400_amd/csrc/fft4.hpp",
+                  "paper_1904_07400_amd/csrc/colfs.hpp", "paper_1904_07400_amd/csrc/kcommon.hpp",
                   "paper_1904_07400_amd/csrc/tridiag.hpp", "paper_1904_07400_amd/csrc/sg_internal.h",
                   "paper_1904_07400_amd/build.py"]
+# per-step kernels of the three passes (pass B: the four-step column kernel
+# for columns of 4096 and 8192, the radix kernel otherwise)
+PASS_KERNELS = r"k_(row_fwd|colfs|col|row_inv)<"
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "forces_4096_k3_fp32_traffic.md")
 
 
@@ -128,13 +133,35 @@ def pmc_summary(fetch_csv, write_csv, mib, cells):
     w_scale = known / max(write[cal[0]])
     rows = []
     for name in fetch:
-        if not re.search(r"k_(row_fwd|col|row_inv)<", name) or name not in write:
+        if not re.search(PASS_KERNELS, name) or name not in write:
             continue
         f = sum(fetch[name]) / len(fetch[name]) * f_scale
         w = sum(write[name]) / len(write[name]) * w_scale
         short = re.sub(r"\(.*", "", name).replace("sg::", "").replace("void ", "")
         rows.append((short, len(fetch[name]), f, w, (f + w) / cells))
     return f_scale, w_scale, rows
+
+
+def sq_summary(csvs):
+    """Per-kernel averages (per dispatch) of the instruction counters of one
+    or more rocprofv3 --pmc runs, for the per-step kernels."""
+    import csv
+    import re
+    per = {}
+    for path in csvs:
+        for row in csv.DictReader(open(path)):
+            name = row["Kernel_Name"]
+            if not re.search(PASS_KERNELS, name):
+                continue
+            per.setdefault(name, {}).setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
+    names = sorted({c for d in per.values() for c in d})
+    out = ["| kernel | " + " | ".join(names) + " |", "|---|" + "---|" * len(names)]
+    for name, d in per.items():
+        short = re.sub(r"HIP_vector_type<(\w+), (\d)u>", r"\1\2", name).replace("sg::", "").replace("void ", "")
+        short = re.sub(r"\(.*", "", short)
+        vals = [f"{sum(d[c]) / len(d[c]):.4g}" if c in d else "" for c in names]
+        out.append(f"| `{short}` | " + " | ".join(vals) + " |")
+    return "\n".join(out)
 
 
 def trace_summary(stats_csv, trace_csv):
@@ -304,19 +331,28 @@ def grad_bench(sg, torch, steps, warmup, big=8192):
                 plan.forces(sig, fx, fy)
                 plan.adjoint(2 * (fx - tx), 2 * (fy - ty), g)
 
-            for _ in range(warmup):
-                step()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(steps):
-                step()
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / steps
+            def timed(fn):
+                for _ in range(warmup):
+                    fn()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(steps):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                return e0.elapsed_time(e1) / steps
+
+            ms = timed(step)
             grads[prec] = g.double().cpu().numpy()
-            key = "fp64_ms_per_step" if prec == sg.SG_FP64 else "ms_per_step"
-            out[key] = round(ms, 4)
+            # the two halves alone: the forward pass, and the adjoint of fixed residuals
+            rx, ry = 2 * (fx - tx), 2 * (fy - ty)
+            ms_fwd = timed(lambda: plan.forces(sig, fx, fy))
+            ms_adj = timed(lambda: plan.adjoint(rx, ry, g))
+            pre = "fp64_" if prec == sg.SG_FP64 else ""
+            out[pre + "ms_per_step"] = round(ms, 4)
+            out[pre + "forward_ms"] = round(ms_fwd, 4)
+            out[pre + "adjoint_ms"] = round(ms_adj, 4)
             if prec == sg.SG_FP32_SPLIT:
                 out["value"] = plan.total / (ms * 1e-3)
                 out["unit"] = "cells/s (forward + adjoint)"
@@ -459,9 +495,15 @@ def main():
                     help="print per-kernel HBM traffic from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--trace-summary", nargs=2, metavar=("STATS_CSV", "TRACE_CSV"),
                     help="print a table of a rocprofv3 --kernel-trace --stats run and exit")
+    ap.add_argument("--sq-summary", nargs="+", metavar="PMC_CSV",
+                    help="print per-kernel instruction counters of rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
     if args.trace_summary:
         print(trace_summary(*args.trace_summary))
+        return
+    if args.sq_summary:
+        print(f"source hash: {kernel_source_hash()}")
+        print(sq_summary(args.sq_summary))
         return
     if args.pmc_summary:
         mib = args.copy_calibration_mib or 256
@@ -519,7 +561,7 @@ def main():
     dom = max(range(3), key=lambda i: pass32[i])
     name = "ABC"[dom]
     achieved = bpc[name] * cells / (pass32[dom] * 1e-3) / 1e9
-    kname = {"A": "k_row_fwd", "B": "k_col", "C": "k_row_inv"}[name]
+    kname = {"A": "k_row_fwd", "B": "k_colfs" if n in (4096, 8192) else "k_col", "C": "k_row_inv"}[name]
     step_gbs = sum(bpc.values()) * cells / (ms32 * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": kname,
                 "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",

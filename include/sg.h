@@ -60,7 +60,7 @@ typedef enum {
   SG_FP64 = 0,       /* every per-step array double; FFT and products in FP64 */
   SG_FP32_SPLIT = 1  /* float arrays; coefficient solve in FP64, FFT in FP32 with
                         FP64-derived twiddles; kernel spectra as hi+lo float pairs (as single floats
-                        for ny = 4096, 8192 unless SG_FLAG_SPECTRA_SPLIT) */
+                        for ny = 2048, 4096, 8192 unless SG_FLAG_SPECTRA_SPLIT) */
 } sg_precision;
 
 /* One grid.  Cell sizes are dx = (x1-x0)/nx, dy = (y1-y0)/ny (Sec. 2, grid
@@ -76,7 +76,7 @@ typedef struct {
 #define SG_FLAG_CHECK_FINITE 0x1u /* sg_forces rejects non-finite sigma (SG_ERR_STATE); costs one extra read */
 #define SG_FLAG_GRAPH 0x2u        /* sg_forces replays a captured HIP graph of the whole step (see sg_forces) */
 #define SG_FLAG_AUTOTUNE 0x4u     /* sg_plan_create times the launch tiles of every class and keeps the best */
-#define SG_FLAG_SPECTRA_SPLIT 0x8u /* SG_FP32_SPLIT: keep the kernel spectra of grids with ny = 4096 or 8192
+#define SG_FLAG_SPECTRA_SPLIT 0x8u /* SG_FP32_SPLIT: keep the kernel spectra of grids with ny = 2048, 4096 or 8192
                                       as hi + lo float pairs (8 B per bin).  Without it those grids' spectra are
                                       single floats (4 B per bin; the lo part moves the error by about 10 %, well
                                       inside 1e-6, and costs 8 B per cell of column-pass traffic); smaller grids

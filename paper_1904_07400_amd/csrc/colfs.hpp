@@ -1,4 +1,4 @@
-// Column pass for long columns (N = 4096, 8192) on the four-step transform
+// Column pass for long columns (N = 2048, 4096, 8192) on the four-step transform
 // of fft4.hpp: one column of the row spectra per workgroup of N / E threads.
 //
 // Per column p (a bin of the row transforms; column 0 carries the real bins
@@ -84,8 +84,19 @@ struct colfs_cfg {
 // table entries while it transforms the current one; the phases w_2N^j stay
 // in registers, so that no load in the loop body waits behind the prefetch
 // (loads complete in order).  Needs the table entries in registers (KEEP).
+// Minimum waves per SIMD the registers of k_colfs must allow: 2 for FP64
+// columns of 2048 (two workgroups of four waves per compute unit; left
+// alone it takes more than 256 registers, one wave per SIMD), else no cap.
+#ifndef SG_COLFS_WPE_D2048
+#define SG_COLFS_WPE_D2048 2
+#endif
+template <typename R, int N>
+struct colfs_wpe {
+  static constexpr int value = (sizeof(R) == 8 && N == 2048) ? SG_COLFS_WPE_D2048 : 1;
+};
+
 template <typename R, typename TO, int N, int MODE, int E, int SLOTS, int COMP, bool PF = false>
-__global__ void __launch_bounds__(N / E)
+__global__ void __launch_bounds__(N / E) SG_WAVES_PER_EU(colfs_wpe<R, N>::value)
     k_colfs(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
             const TO* __restrict__ toy, const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ twfs,
             const sg_bgrid* __restrict__ bg) {

@@ -13,6 +13,11 @@
 #define SG_OPAQUE(v) __asm__ volatile("" : "+v"(v))
 #endif
 
+// Minimum waves per SIMD a kernel's register allocation must allow.
+#ifndef SG_WAVES_PER_EU
+#define SG_WAVES_PER_EU(...) __attribute__((amdgpu_waves_per_eu(__VA_ARGS__)))
+#endif
+
 namespace sg {
 
 __device__ __forceinline__ int opaque(int i) {

@@ -1,6 +1,8 @@
 // Launches of the four-step column pass (colfs.hpp) for the long columns:
-// N = 4096 (FP32, FP64) and N = 8192 (FP32).  One workgroup of N / E
-// threads per column; for a batch, blockIdx.y is the grid of the class.
+// N = 2048, 4096 and 8192, FP32 and FP64.  One workgroup of N / E threads
+// per column; for a batch, blockIdx.y is the grid of the class.
+#include <type_traits>
+
 #include "colfs.hpp"
 
 #ifndef SG_COLFS_SPLIT_F4096
@@ -13,6 +15,10 @@
 #ifndef SG_COLFS_PF
 #define SG_COLFS_PF 1
 #endif
+// ... and for columns of 2048 (two workgroups per compute unit)
+#ifndef SG_COLFS_PF2048
+#define SG_COLFS_PF2048 0
+#endif
 
 namespace sg {
 
@@ -21,6 +27,16 @@ namespace sg {
 template <typename R, int N>
 struct colfs_sel {
   static constexpr bool ok = false;
+};
+template <>
+struct colfs_sel<float, 2048> {
+  static constexpr bool ok = true;
+  static constexpr int E = 8, SLOTS = 4, SPLIT = 0;
+};
+template <>
+struct colfs_sel<double, 2048> {
+  static constexpr bool ok = true;
+  static constexpr int E = 8, SLOTS = 2, SPLIT = 0;
 };
 template <>
 struct colfs_sel<float, 4096> {
@@ -56,7 +72,9 @@ static int device_cus() {
 template <typename R, typename TO, int N, int MODE>
 struct colfs_pf {
   // odd orders only: the even orders' bin phases leave no registers for it
-  static constexpr bool on = SG_COLFS_PF && sizeof(R) == 4 && N == 4096 && sizeof(TO) == 4 && (MODE % 2 == 0);
+  static constexpr bool on = sizeof(R) == 4 && sizeof(TO) == 4 && (MODE % 2 == 0) &&
+                             ((N == 4096 && SG_COLFS_PF) || (N == 2048 && SG_COLFS_PF2048));
+  static constexpr int per_cu = N == 2048 ? 2 : 1;  // resident workgroups per compute unit
 };
 
 template <typename R, typename TO, int N, int MODE, int COMP>
@@ -65,7 +83,8 @@ static void launch_colfs_k(const cx<R>* X, cx<R>* V, int M, int tj, const TO* to
   using Sel = colfs_sel<R, N>;
   if constexpr (colfs_pf<R, TO, N, MODE>::on && COMP == 0) {
     static const int cus = device_cus();
-    const int nb = M < cus ? M : cus;
+    const int slots = cus * colfs_pf<R, TO, N, MODE>::per_cu;
+    const int nb = M < slots ? M : slots;
     hipLaunchKernelGGL((k_colfs<R, TO, N, MODE, Sel::E, Sel::SLOTS, COMP, true>), dim3(nb, bg ? ngrids : 1),
                        dim3(N / Sel::E), 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
   } else {
@@ -122,14 +141,28 @@ using namespace sg;
 
 int sg_colfs_supported(int prec, int N) {
   (void)prec;
-  return (N == 4096 || N == 8192) ? 1 : 0;
+  return (N == 2048 || N == 4096 || N == 8192) ? 1 : 0;
 }
 
 int sg_colfs_twiddles(int prec, int N, double* re, double* im) {
   if (!sg_colfs_supported(prec, N)) return -1;
-  if (prec == 0) return N == 4096 ? colfs_twiddles_t<double, 4096>(re, im) : colfs_twiddles_t<double, 8192>(re, im);
-  return N == 4096 ? colfs_twiddles_t<float, 4096>(re, im) : colfs_twiddles_t<float, 8192>(re, im);
+  if (prec == 0)
+    return N == 2048 ? colfs_twiddles_t<double, 2048>(re, im)
+                     : (N == 4096 ? colfs_twiddles_t<double, 4096>(re, im) : colfs_twiddles_t<double, 8192>(re, im));
+  return N == 2048 ? colfs_twiddles_t<float, 2048>(re, im)
+                   : (N == 4096 ? colfs_twiddles_t<float, 4096>(re, im) : colfs_twiddles_t<float, 8192>(re, im));
 }
+
+namespace sg {
+// f(integral_constant<N>) for the supported lengths
+template <typename F>
+static hipError_t colfs_len(int N, F f) {
+  if (N == 2048) return f(std::integral_constant<int, 2048>{});
+  if (N == 4096) return f(std::integral_constant<int, 4096>{});
+  if (N == 8192) return f(std::integral_constant<int, 8192>{});
+  return hipErrorInvalidValue;
+}
+}  // namespace sg
 
 hipError_t sg_launch_colfs(int prec, int N, const void* X, void* V, int M, int tj, const void* tx, const void* ty,
                            int kind, int tab_bytes, const void* r2n, int solve, const void* tw, const sg_bgrid* bg,
@@ -140,25 +173,21 @@ hipError_t sg_launch_colfs(int prec, int N, const void* X, void* V, int M, int t
     cx<double>* Vd = (cx<double>*)V;
     const cx<double>* rd = (const cx<double>*)r2n;
     const cx<double>* td = (const cx<double>*)tw;
-    if (N == 4096) return launch_colfs_t<double, double, 4096>(Xd, Vd, M, tj, tx, ty, kind, rd, solve, td, bg, ngrids, st);
-    if (N == 8192) return launch_colfs_t<double, double, 8192>(Xd, Vd, M, tj, tx, ty, kind, rd, solve, td, bg, ngrids, st);
-    return hipErrorInvalidValue;
+    return colfs_len(N, [&](auto n) {
+      return launch_colfs_t<double, double, decltype(n)::value>(Xd, Vd, M, tj, tx, ty, kind, rd, solve, td, bg, ngrids,
+                                                                st);
+    });
   }
   const cx<float>* Xf = (const cx<float>*)X;
   cx<float>* Vf = (cx<float>*)V;
   const cx<float>* rf = (const cx<float>*)r2n;
   const cx<float>* tf = (const cx<float>*)tw;
-  if (N == 4096) {
+  return colfs_len(N, [&](auto n) {
+    constexpr int NN = decltype(n)::value;
     if (tab_bytes == 8)
-      return launch_colfs_t<float, float2, 4096>(Xf, Vf, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
-    return launch_colfs_t<float, float, 4096>(Xf, Vf, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
-  }
-  if (N == 8192) {
-    if (tab_bytes == 8)
-      return launch_colfs_t<float, float2, 8192>(Xf, Vf, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
-    return launch_colfs_t<float, float, 8192>(Xf, Vf, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
-  }
-  return hipErrorInvalidValue;
+      return launch_colfs_t<float, float2, NN>(Xf, Vf, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
+    return launch_colfs_t<float, float, NN>(Xf, Vf, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
+  });
 }
 
 // ---------------------------------------------------------------- adjoint --
@@ -203,26 +232,22 @@ hipError_t sg_launch_colfs_adj(int prec, int N, const void* Xx, const void* Xy, 
     cx<double>* y = (cx<double>*)Y;
     const cx<double>* rd = (const cx<double>*)r2n;
     const cx<double>* td = (const cx<double>*)tw;
-    if (N == 4096) return launch_colfs_adj_t<double, double, 4096>(a, b, y, M, tj, tx, ty, kind, rd, solve, td, bg, ngrids, st);
-    if (N == 8192) return launch_colfs_adj_t<double, double, 8192>(a, b, y, M, tj, tx, ty, kind, rd, solve, td, bg, ngrids, st);
-    return hipErrorInvalidValue;
+    return colfs_len(N, [&](auto n) {
+      return launch_colfs_adj_t<double, double, decltype(n)::value>(a, b, y, M, tj, tx, ty, kind, rd, solve, td, bg,
+                                                                    ngrids, st);
+    });
   }
   const cx<float>* a = (const cx<float>*)Xx;
   const cx<float>* b = (const cx<float>*)Xy;
   cx<float>* y = (cx<float>*)Y;
   const cx<float>* rf = (const cx<float>*)r2n;
   const cx<float>* tf = (const cx<float>*)tw;
-  if (N == 4096) {
+  return colfs_len(N, [&](auto n) {
+    constexpr int NN = decltype(n)::value;
     if (tab_bytes == 8)
-      return launch_colfs_adj_t<float, float2, 4096>(a, b, y, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
-    return launch_colfs_adj_t<float, float, 4096>(a, b, y, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
-  }
-  if (N == 8192) {
-    if (tab_bytes == 8)
-      return launch_colfs_adj_t<float, float2, 8192>(a, b, y, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
-    return launch_colfs_adj_t<float, float, 8192>(a, b, y, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
-  }
-  return hipErrorInvalidValue;
+      return launch_colfs_adj_t<float, float2, NN>(a, b, y, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
+    return launch_colfs_adj_t<float, float, NN>(a, b, y, M, tj, tx, ty, kind, rf, solve, tf, bg, ngrids, st);
+  });
 }
 
 // ------------------------------------------------------- spectrum (plan) --

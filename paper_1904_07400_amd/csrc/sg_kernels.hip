@@ -38,6 +38,24 @@
 #ifndef SG_RI_E32
 #define SG_RI_E32 8
 #endif
+// FP32 inverse rows from this length on: SG_RI_BIG_E elements per thread,
+// SG_RI_BIG_NB exchange buffers per row, SG_RI_BIG_WG threads per workgroup
+#ifndef SG_RI_BIG32
+#define SG_RI_BIG32 2048
+#endif
+#ifndef SG_RI_BIG_E
+#define SG_RI_BIG_E 16
+#endif
+#ifndef SG_RI_BIG_NB
+#define SG_RI_BIG_NB 1
+#endif
+#ifndef SG_RI_BIG_WG
+#define SG_RI_BIG_WG 512
+#endif
+// 1: those rows load both halves before the transforms
+#ifndef SG_RI_PRE
+#define SG_RI_PRE 1
+#endif
 #ifndef SG_RI_E64
 #define SG_RI_E64 16
 #endif
@@ -853,13 +871,21 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
 template <typename R, int M>
 struct rowinv_cfg {
   static constexpr int L = M;
-  static constexpr int E = elems_for(L, sizeof(R) == 4 ? SG_RI_E32 : SG_RI_E64, SG_E3);
+  // FP32 rows of at least SG_RI_BIG32 bins: 16 elements per thread, the two
+  // half-length inverses one after the other (one exchange buffer per row),
+  // so that four rows share a workgroup and the loads of a tile row quad
+  // leave as 32-byte segments
+  static constexpr bool BIG = sizeof(R) == 4 && M >= SG_RI_BIG32;
+  static constexpr int E = elems_for(L, sizeof(R) == 4 ? (BIG ? SG_RI_BIG_E : SG_RI_E32) : SG_RI_E64, SG_E3);
   static constexpr int T = L / E;
   static constexpr int LL = lds_len<L>::value;
-  static constexpr int NB = sizeof(R) == 4 ? SG_RI_NBUF32 : 1;  // exchange buffers per row
-  static constexpr int WG = sizeof(R) == 4 ? SG_RI_THREADS32 : SG_RI_THREADS64;
+  static constexpr int NB = sizeof(R) == 4 ? (BIG ? SG_RI_BIG_NB : SG_RI_NBUF32) : 1;  // exchange buffers per row
+  // LDS of one row: its buffers plus a shift of 8 elements, so that the
+  // rows' buffers start in different banks
+  static constexpr int RS = NB * LL + 8;
+  static constexpr int WG = sizeof(R) == 4 ? (BIG ? SG_RI_BIG_WG : SG_RI_THREADS32) : SG_RI_THREADS64;
   static constexpr int G0 = WG / T < 1 ? 1 : (WG / T < 16 ? WG / T : 16);
-  static constexpr int GL = kLdsBudget / (NB * LL * (int)sizeof(cx<R>));
+  static constexpr int GL = kLdsBudget / (RS * (int)sizeof(cx<R>));
   static constexpr int G = (G0 < GL ? G0 : GL) < 1 ? 1 : (G0 < GL ? G0 : GL);
 };
 
@@ -876,48 +902,45 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
   }
   using C = rowinv_cfg<R, M>;
   constexpr int E = C::E, T = C::T, LL = C::LL, NB = C::NB;
-  __shared__ cx<R> smem[C::G * LL * NB];
-  const int G = blockDim.x / T;  // rows per workgroup
-  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  __shared__ cx<R> smem[C::G * C::RS];
+  // G rows per workgroup, interleaved lane by lane (thread t of row g is
+  // thread t G + g), so that the G rows' elements of one bin, adjacent in a
+  // tile, are read by adjacent lanes
+  const int G = blockDim.x / T;
+  const int g = threadIdx.x % G, t = threadIdx.x / G;
   const int row = xcd_tile(blockIdx.x, gridDim.x) * G + g;
   const bool active = row < nrows;
-  cx<R>* lds = smem + g * LL * NB;
+  cx<R>* lds = smem + g * C::RS;
   const int jb = (active ? row : 0) / tj, jj = (active ? row : 0) % tj;
-  cx<R> ve[E], vo[E], wr[E];
+  // NB == 2 and the FP32 rows of four per workgroup: both halves loaded
+  // before any transform, so that all loads are in flight together; other
+  // FP64 rows load the odd half after the even half's transform (registers)
+  constexpr bool PRE = NB == 2 || (C::BIG && SG_RI_PRE);
+  cx<R> v2[2][E], wr[NB == 2 ? E : 1];
+  auto load_half = [&](int half) {
+    const cx<R>* base = V + ((int64_t)jb * 2 + half) * M * tj + jj;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v2[half][e] = base[(int64_t)(t + e * T) * tj];
+  };
+  load_half(0);
+  if constexpr (PRE) load_half(1);
   if constexpr (NB == 2) {
-    // both half-length inverses through the same stages
-    cx<R> v2[2][E];
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      const cx<R>* base = V + ((int64_t)jb * 2 + half) * M * tj + jj;
-#pragma unroll
-      for (int e = 0; e < E; ++e) v2[half][e] = base[(int64_t)(t + e * T) * tj];
-    }
-    // phases of the odd half, loaded now so that their latency hides behind
-    // the transforms
+    // phases of the odd half, loaded now so that their latency hides
+    // behind the transforms
 #pragma unroll
     for (int e = 0; e < E; ++e) wr[e] = r2m[t + e * T];
+    // both half-length inverses through the same stages
     fftn<true, M, T, 2>(v2, lds, LL, tw, t);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      ve[e] = v2[0][e];
-      vo[e] = v2[1][e];
-    }
   } else {
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      const cx<R>* base = V + ((int64_t)jb * 2 + half) * M * tj + jj;
-      cx<R>* v = half ? vo : ve;
-#pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = base[(int64_t)(t + e * T) * tj];
-      fft<true, M, T>(v, lds, tw, t);
-    }
+    fft<true, M, T>(v2[0], lds, tw, t);
+    if constexpr (!PRE) load_half(1);
+    fft<true, M, T>(v2[1], lds, tw, t);
   }
   if (active) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int n = t + e * T;
-      const cx<R> r = ve[e] + cmulc(vo[e], NB == 2 ? wr[e] : r2m[n]);
+      const cx<R> r = v2[0][e] + cmulc(v2[1][e], NB == 2 ? wr[e] : r2m[n]);
       fx[(int64_t)row * M + n] = (Out)r.x;
       fy[(int64_t)row * M + n] = (Out)r.y;
     }
@@ -1360,8 +1383,8 @@ struct tabs {
 };
 
 // Transform lengths with kernels: SG_SIZES for the column passes of this
-// file (the four-step column pass of sg_colfs.hip takes 4096 and 8192 as
-// well), SG_ROW_SIZES for the row passes and the coefficient solves.
+// file (the four-step column pass of sg_colfs.hip takes 2048, 4096 and 8192,
+// the last only there), SG_ROW_SIZES for the row passes and the coefficient solves.
 #ifndef SG_SIZES
 #define SG_SIZES(X)                                                                                        \
   X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(12) X(24) X(48) X(96) X(192) X(384) \

@@ -23,6 +23,7 @@
 #define __forceinline__ inline
 #define __shared__ static
 #define __launch_bounds__(...)
+#define SG_WAVES_PER_EU(...)
 #define __constant__
 #define SG_OPAQUE(v) __asm__ volatile("" : "+r"(v))
 

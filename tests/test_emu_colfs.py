@@ -5,8 +5,8 @@ case checks the kernel's output against the column pass written from its
 definition in numpy (tests/emu/colpass_ref.py), and that ThreadSanitizer
 reports no data race on the LDS (an access that no barrier orders against
 another thread's access to the same element).  Covers the shapes the GPU
-runs (N = 4096 and 8192, FP32 and FP64, every LDS plan and the component
-split) on a few columns each."""
+runs (N = 2048, 4096 and 8192, FP32 and FP64, every LDS plan and the
+component split) on a few columns each."""
 import os
 import shutil
 import subprocess
@@ -64,7 +64,8 @@ def _run(exe, M, path_in, path_out):
 
 FWD = [(32, 4096, 8, 4, 3, "float2", 0, 0), (32, 4096, 8, 4, 2, "float", 0, 0), (32, 4096, 8, 4, 5, "float2", 0, 0),
        (32, 8192, 16, 2, 4, "float", 1, 0), (64, 4096, 8, 2, 3, "double", 1, 0), (64, 8192, 16, 1, 2, "double", 1, 0),
-       (32, 4096, 8, 4, 3, "float", 0, 1), (32, 4096, 8, 4, 1, "float", 0, 1)]
+       (32, 4096, 8, 4, 3, "float", 0, 1), (32, 4096, 8, 4, 1, "float", 0, 1),
+       (32, 2048, 8, 4, 3, "float", 0, 0), (32, 2048, 8, 4, 2, "float2", 0, 0), (64, 2048, 8, 2, 5, "double", 0, 0)]
 
 
 @pytest.mark.skipif(GXX is None, reason="g++ not found")
@@ -93,7 +94,8 @@ def test_column_pass(tmp_path, prec, N, E, slots, k, to, split, pf):
 
 
 ADJ = [(32, 4096, 8, 2, 3, "float2"), (32, 4096, 8, 2, 2, "float"), (32, 8192, 16, 2, 5, "float2"),
-       (64, 8192, 16, 1, 3, "double"), (64, 4096, 8, 2, 4, "double")]
+       (64, 8192, 16, 1, 3, "double"), (64, 4096, 8, 2, 4, "double"), (32, 2048, 8, 2, 3, "float"),
+       (64, 2048, 8, 2, 2, "double")]
 
 
 @pytest.mark.skipif(GXX is None, reason="g++ not found")
