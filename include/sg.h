@@ -75,7 +75,8 @@ typedef struct {
 /* plan flags */
 #define SG_FLAG_CHECK_FINITE 0x1u /* sg_forces rejects non-finite sigma (SG_ERR_STATE); costs one extra read */
 #define SG_FLAG_GRAPH 0x2u        /* sg_forces replays a captured HIP graph of the whole step (see sg_forces) */
-#define SG_FLAG_AUTOTUNE 0x4u     /* sg_plan_create times the launch tiles of every class and keeps the best */
+#define SG_FLAG_AUTOTUNE 0x4u     /* sg_plan_create times the launch variants and tiles of every class not
+                                     in the tuning store and keeps the best (see sg_plan_tuning) */
 #define SG_FLAG_SPECTRA_SPLIT 0x8u /* SG_FP32_SPLIT: keep the kernel spectra of grids with ny = 2048, 4096 or 8192
                                       as hi + lo float pairs (8 B per bin).  Without it those grids' spectra are
                                       single floats (4 B per bin; the lo part moves the error by about 10 %, well
@@ -159,8 +160,30 @@ sg_status sg_forces_noalloc(sg_plan p, const void* sigma, void* fx, void* fy);
  * 8 HOST int32 each in info: nx, ny, order, number of grids, then the rows
  * per workgroup of the row passes and the columns per workgroup of the
  * column pass in use (A, B, C; chosen by the autotuner with
- * SG_FLAG_AUTOTUNE), then 0.  info may be NULL. */
+ * SG_FLAG_AUTOTUNE), then how they were chosen (as sg_plan_tuning).  info
+ * may be NULL. */
 sg_status sg_plan_classes(sg_plan p, int32_t* nclasses, int32_t* info, int32_t cap);
+
+/* Launch choices of class cls (0-based, as sg_plan_classes), 8 HOST int32
+ * in out: the launch variant of passes A, B, C (kernels of the same
+ * transforms with other buffering or elements per thread; variant
+ * choices that change the elements per thread change rounding, within the
+ * precision of the plan), the tile of each pass (0 = compiled maximum), how
+ * they were chosen (0 defaults, 1 timed at this plan's creation, 2 taken
+ * from the tuning store), then 0.
+ *
+ * Tuning (plan time only): the choices live in a process-wide store; every
+ * plan takes the variants recorded for its device, precision, size and
+ * order (so that plans of one process compute identical results), and the
+ * tiles recorded for its class size.  Missing entries are timed on zero
+ * input when the plan has SG_FLAG_AUTOTUNE (variants, then tiles) and
+ * recorded.  Environment: SG_TUNE=off (defaults only, the store ignored),
+ * quick (time tiles only, for every plan), full (time variants and tiles,
+ * for every plan); SG_TUNE_CACHE=path keeps the store in a JSON file, read
+ * on first use and rewritten (merged, via a temporary file and a rename)
+ * after new timings.  Entries carry the library build, so a rebuilt library
+ * ignores older ones. */
+sg_status sg_plan_tuning(sg_plan p, int32_t cls, int32_t* out);
 
 /* Adjoint of sg_forces: gsigma = d<gfx,Fx> + <gfy,Fy> / d sigma, i.e. the
  * transposed convolutions (correlation with the weights) followed by the

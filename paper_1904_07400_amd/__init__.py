@@ -19,7 +19,7 @@ import threading
 
 __all__ = [
     "SG_FP64", "SG_FP32_SPLIT", "SG_FLAG_CHECK_FINITE", "SG_FLAG_GRAPH", "SG_FLAG_AUTOTUNE", "SG_FLAG_SPECTRA_SPLIT", "SGError",
-    "sg_grid", "lib", "sg_plan_classes",
+    "sg_grid", "lib", "sg_plan_classes", "sg_plan_tuning",
     "sg_plan_create", "sg_plan_destroy", "sg_plan_layout", "sg_plan_info", "sg_sample_points",
     "sg_weights", "sg_bspline_coeffs", "sg_forces", "sg_forces_noalloc", "sg_forces_adjoint", "sg_status_string",
     "sg_last_error_message", "sg_plan_set_timing", "sg_plan_pass_times", "Plan", "ThinDiskForces",
@@ -76,6 +76,7 @@ def lib() -> ctypes.CDLL:
             L.sg_forces_noalloc.argtypes = [vp, vp, vp, vp]
             L.sg_plan_set_timing.argtypes = [vp, i32]
             L.sg_plan_classes.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), i32]
+            L.sg_plan_tuning.argtypes = [vp, i32, ctypes.POINTER(i32)]
             L.sg_plan_pass_times.argtypes = [vp, dp, ctypes.POINTER(i64)]
             L.sg_status_string.argtypes = [ctypes.c_int]
             L.sg_status_string.restype = ctypes.c_char_p
@@ -83,7 +84,8 @@ def lib() -> ctypes.CDLL:
             L.sg_last_error_message.restype = ctypes.c_char_p
             for f in ("sg_plan_create", "sg_plan_destroy", "sg_plan_layout", "sg_plan_info",
                       "sg_sample_points", "sg_weights", "sg_bspline_coeffs", "sg_forces", "sg_forces_noalloc",
-                      "sg_forces_adjoint", "sg_plan_set_timing", "sg_plan_pass_times", "sg_plan_classes"):
+                      "sg_forces_adjoint", "sg_plan_set_timing", "sg_plan_pass_times", "sg_plan_classes",
+                      "sg_plan_tuning"):
                 getattr(L, f).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -166,6 +168,14 @@ def sg_plan_classes(plan: int):
     info = (ctypes.c_int32 * (8 * max(n.value, 1)))()
     _check(lib().sg_plan_classes(plan, ctypes.byref(n), info, n.value))
     return [tuple(info[8 * i:8 * i + 7]) for i in range(n.value)]
+
+
+def sg_plan_tuning(plan: int, cls: int):
+    """(variants (A, B, C), tiles (A, B, C), source) of class cls: source 0 =
+    defaults, 1 = timed at the plan's creation, 2 = from the tuning store."""
+    out = (ctypes.c_int32 * 8)()
+    _check(lib().sg_plan_tuning(plan, cls, out))
+    return tuple(out[0:3]), tuple(out[3:6]), out[6]
 
 
 def sg_sample_points(plan: int, g: int):

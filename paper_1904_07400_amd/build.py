@@ -93,12 +93,30 @@ def check_resources(obj: str) -> None:
         raise RuntimeError(f"kernels above the {SCRATCH_LIMIT} B/lane scratch limit:\n{lines}")
 
 
+def build_id() -> str:
+    """Hash of the library sources and compile flags: the build tag of the
+    tuning store's entries (a rebuilt library with other kernels ignores
+    entries of the old one)."""
+    import hashlib
+    h = hashlib.sha256(" ".join(COMMON).encode())
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp", ".h", ".cpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    with open(os.path.join(INCLUDE, "sg.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:12]
+
+
 def build(verbose: bool = False) -> str:
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(UNITS)) as ex:
-        objs = list(ex.map(lambda u: _compile(u, obj_dir), UNITS))
-    for o, u in zip(objs, UNITS):
+    bid = build_id()
+    units = [(src, extra + (['-DSG_BUILD_ID="%s"' % bid] if src == "sg_api.cpp" else []), name)
+             for src, extra, name in UNITS]
+    with ThreadPoolExecutor(max_workers=len(units)) as ex:
+        objs = list(ex.map(lambda u: _compile(u, obj_dir), units))
+    for o, u in zip(objs, units):
         if u[0].endswith(".hip"):
             check_resources(o)
     tmp = LIB + ".tmp%d" % os.getpid()

@@ -6,8 +6,10 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <unistd.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <mutex>
 #include <string>
@@ -134,6 +136,7 @@ struct GridPlan {
   void* twA = nullptr;  // stage twiddles: forward rows, columns, inverse rows
   void* twB = nullptr;
   void* twC = nullptr;
+  void* twC1 = nullptr;     // inverse rows in launch variant 1 (FP32, where it exists)
   bool fs = false;          // columns by the four-step pass (long columns)
   void* twfs = nullptr;     // its twiddle table
   int tab_bytes = 8;        // bytes per spectrum entry: double, float hi + lo, or float
@@ -148,6 +151,8 @@ struct GridClass {
   sg_bgrid* desc_y = nullptr;  // the same with X = V (adjoint: row spectra of gy)
   sg_bgrid* desc_s = nullptr;  // the same with X and V in the no-allocation scratch
   int tile[3] = {0, 0, 0};  // rows / columns per workgroup of passes A, B, C (0 = compiled maximum)
+  int var[3] = {0, 0, 0};   // launch variant of passes A, B, C (sg_variants)
+  int src = 0;              // how var and tile were chosen: 0 defaults, 1 timed here, 2 the tuning store
 };
 
 // One captured step: the graph of every class's three launches for a given
@@ -401,7 +406,18 @@ hipError_t launch_cols(sg_plan p, const GridClass& c, int tile, hipStream_t q, c
     return sg_launch_colfs(prec, c.N, nullptr, nullptr, c.M, tj, nullptr, nullptr, G.kind, G.tab_bytes, G.r2n, solve,
                            G.twfs, d, ng, q);
   return sg_launch_col(prec, c.N, nullptr, nullptr, c.M, tj, nullptr, nullptr, G.kind, G.r2n, solve, G.twB, d, ng,
-                       tile, q);
+                       tile, c.var[1], q);
+}
+
+// The inverse row pass of one class (its launch variant and that variant's
+// twiddle table).
+hipError_t launch_rows_inv(sg_plan p, const GridClass& c, void* fx, void* fy, int tile, hipStream_t q,
+                           const sg_bgrid* desc) {
+  const int prec = p->prec == SG_FP64 ? 0 : 1;
+  const GridPlan& G = p->grids[c.members[0]];
+  const int tj = sg_row_tile(prec, c.M, c.N);
+  return sg_launch_row_inv(prec, c.M, nullptr, fx, fy, c.N, tj, G.r2m, c.var[2] ? G.twC1 : G.twC, desc,
+                           (int)c.members.size(), tile, c.var[2], q);
 }
 
 // The three launches of every grid of one class on stream q.
@@ -411,11 +427,9 @@ hipError_t issue_class(sg_plan p, const GridClass& c, const void* sigma, void* f
   const GridPlan& G = p->grids[c.members[0]];
   const int solve = c.k >= 3 ? c.k : 0;
   const int ng = (int)c.members.size();
-  const int tj = sg_row_tile(prec, c.M, c.N);
   hipError_t e = sg_launch_row_fwd(prec, c.M, sigma, c.M, nullptr, c.N, G.r2m, solve, 0, G.twA, c.desc, ng, tile[0], q);
   if (e == hipSuccess) e = launch_cols(p, c, tile[1], q);
-  if (e == hipSuccess)
-    e = sg_launch_row_inv(prec, c.M, nullptr, fx, fy, c.N, tj, G.r2m, G.twC, c.desc, ng, tile[2], q);
+  if (e == hipSuccess) e = launch_rows_inv(p, c, fx, fy, tile[2], q, c.desc);
   return e;
 }
 
@@ -464,7 +478,6 @@ sg_status time_tile(sg_plan p, GridClass& c, int pass, int tile, const void* sig
   const GridPlan& G = p->grids[c.members[0]];
   const int solve = c.k >= 3 ? c.k : 0;
   const int ng = (int)c.members.size();
-  const int tj = sg_row_tile(prec, c.M, c.N);
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess) return fail(SG_ERR_DEVICE, "hipEventCreate");
   if (hipEventCreate(&b) != hipSuccess) {
@@ -482,7 +495,7 @@ sg_status time_tile(sg_plan p, GridClass& c, int pass, int tile, const void* sig
     else if (pass == 1)
       e = launch_cols(p, c, t3[1], p->st);
     else
-      e = sg_launch_row_inv(prec, c.M, nullptr, fx, fy, c.N, tj, G.r2m, G.twC, c.desc, ng, t3[2], p->st);
+      e = launch_rows_inv(p, c, fx, fy, t3[2], p->st, c.desc);
     if (e == hipSuccess) e = hipEventRecord(b, p->st);
     if (e == hipSuccess) e = hipEventSynchronize(b);
     float t = 0.0f;
@@ -496,42 +509,230 @@ sg_status time_tile(sg_plan p, GridClass& c, int pass, int tile, const void* sig
   return SG_OK;
 }
 
-// Autotuner: per class and pass, the tile (rows or columns per workgroup,
-// powers of two up to the compiled maximum) with the shortest time, the
-// passes tuned in order A, B, C.
-sg_status autotune(sg_plan p) {
+// ------------------------------------------------------------- tuning --
+// Launch choices per class: the variant of each pass (sg_variants: kernels
+// of the same transform with other buffering or elements per thread) and
+// its tile (rows or columns per workgroup).  Choices live in a process-wide
+// store, like FFT wisdom: every plan created afterwards takes the variants
+// recorded for its (device, precision, size, order), tuned or not, so that
+// plans of one process compute identical results; tiles (which never change
+// results) are recorded per class size (number of grids) as well.  With
+// SG_TUNE_CACHE=path the store is read from that file on first use and
+// written back (whole, through a temporary file and a rename) after new
+// choices are timed.  SG_TUNE: off = defaults only, the store ignored;
+// quick = time tiles only; full = variants, then tiles.  Unset: full for
+// plans created with SG_FLAG_AUTOTUNE, the store alone for other plans.
+#ifndef SG_BUILD_ID
+#define SG_BUILD_ID "dev"
+#endif
+
+enum TuneMode { TUNE_UNSET, TUNE_OFF, TUNE_QUICK, TUNE_FULL };
+
+TuneMode tune_mode() {
+  const char* v = getenv("SG_TUNE");
+  if (!v || !*v) return TUNE_UNSET;
+  if (strcmp(v, "off") == 0 || strcmp(v, "0") == 0) return TUNE_OFF;
+  if (strcmp(v, "quick") == 0) return TUNE_QUICK;
+  return TUNE_FULL;
+}
+
+struct TuneStore {
+  std::mutex mu;
+  std::map<std::string, std::array<int, 3>> var;   // device/prec/size/order -> variants
+  std::map<std::string, std::array<int, 3>> tile;  // ... /grids -> tiles
+  std::string loaded;                              // cache file read into the store
+};
+TuneStore g_tune;
+
+// Entries of a cache file: lines  "key": [a, b, c]  after a line naming the
+// section ("variants" or "tiles").  Malformed lines are skipped.
+void read_cache(const std::string& path, std::map<std::string, std::array<int, 3>>& var,
+                std::map<std::string, std::array<int, 3>>& tile) {
+  FILE* f = fopen(path.c_str(), "r");
+  if (!f) return;
+  char line[1024];
+  int section = 0;  // 1 variants, 2 tiles
+  while (fgets(line, sizeof line, f)) {
+    if (strstr(line, "\"variants\"")) section = 1;
+    else if (strstr(line, "\"tiles\"")) section = 2;
+    const char* q0 = strchr(line, '"');
+    const char* q1 = q0 ? strchr(q0 + 1, '"') : nullptr;
+    const char* br = q1 ? strchr(q1, '[') : nullptr;
+    std::array<int, 3> v{};
+    if (!section || !br || sscanf(br, "[%d , %d , %d]", &v[0], &v[1], &v[2]) != 3) continue;
+    const std::string key(q0 + 1, q1);
+    if (key.find('/') == std::string::npos) continue;
+    (section == 1 ? var : tile)[key] = v;
+  }
+  fclose(f);
+}
+
+bool write_cache(const std::string& path, const std::map<std::string, std::array<int, 3>>& var,
+                 const std::map<std::string, std::array<int, 3>>& tile) {
+  const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  fprintf(f, "{\"sg_tune_cache\": 1,\n");
+  for (int sec = 0; sec < 2; ++sec) {
+    const auto& m = sec ? tile : var;
+    fprintf(f, " \"%s\": {\n", sec ? "tiles" : "variants");
+    size_t i = 0;
+    for (const auto& kv : m)
+      fprintf(f, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second[0], kv.second[1], kv.second[2],
+              ++i < m.size() ? "," : "");
+    fprintf(f, " }%s\n", sec ? "" : ",");
+  }
+  fprintf(f, "}\n");
+  const bool ok = fclose(f) == 0;
+  return ok && rename(tmp.c_str(), path.c_str()) == 0;
+}
+
+std::string device_tag(int dev) {
+  hipDeviceProp_t pr;
+  if (hipGetDeviceProperties(&pr, dev) != hipSuccess) return "unknown";
+  std::string arch = pr.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch.resize(colon);
+  return arch + "/" + std::to_string(pr.multiProcessorCount) + "cu/" SG_BUILD_ID;
+}
+
+std::string var_key(const std::string& dev, int prec, const GridClass& c) {
+  char b[160];
+  snprintf(b, sizeof b, "%s/%s/%dx%d/k%d", dev.c_str(), prec == 0 ? "fp64" : "fp32", c.M, c.N, c.k);
+  return b;
+}
+std::string tile_key(const std::string& dev, int prec, const GridClass& c) {
+  return var_key(dev, prec, c) + "/g" + std::to_string(c.members.size());
+}
+
+// Time every tile (powers of two up to the compiled maximum) of one pass in
+// the class's variant; the best goes into c.tile.
+sg_status tune_tiles(sg_plan p, GridClass& c, int pass, const void* sig, void* fx, void* fy, float* best_ms) {
+  const int prec = p->prec == SG_FP64 ? 0 : 1;
+  const int cap = sg_max_tile(prec, pass, pass == 1 ? c.N : c.M, c.var[pass]);
+  int best_tile = 0;
+  float best = 1e30f;
+  sg_status s = SG_OK;
+  for (int t = 1; t <= cap && s == SG_OK; t *= 2) {
+    float ms = 0.0f;
+    s = time_tile(p, c, pass, t, sig, fx, fy, &ms);
+    if (s == SG_OK && ms < best) {
+      best = ms;
+      best_tile = t;
+    }
+  }
+  if (s == SG_OK) c.tile[pass] = best_tile;
+  if (best_ms) *best_ms = best;
+  return s;
+}
+
+// Apply the store's choices to every class; time what is missing when asked
+// to (full: variants and tiles; quick: tiles), record it and write the
+// cache file.
+sg_status tune(sg_plan p) {
+  const TuneMode mode = tune_mode();
+  if (mode == TUNE_OFF) return SG_OK;
+  const bool timing = mode == TUNE_FULL || mode == TUNE_QUICK || (mode == TUNE_UNSET && (p->flags & SG_FLAG_AUTOTUNE));
+  const bool variants = mode == TUNE_FULL || (mode == TUNE_UNSET && (p->flags & SG_FLAG_AUTOTUNE));
+  const int prec = p->prec == SG_FP64 ? 0 : 1;
+  const std::string dev = device_tag(p->device);
+  const char* cache_env = getenv("SG_TUNE_CACHE");
+  const std::string cache = cache_env ? cache_env : "";
+  std::lock_guard<std::mutex> lk(g_tune.mu);
+  if (!cache.empty() && g_tune.loaded != cache) {
+    read_cache(cache, g_tune.var, g_tune.tile);
+    g_tune.loaded = cache;
+  }
+  // a stored choice is used only if this build has it
+  auto valid_var = [&](const GridClass& c, const std::array<int, 3>& v) {
+    for (int pass = 0; pass < 3; ++pass) {
+      const int n = (pass == 1 && p->grids[c.members[0]].fs) ? 1 : sg_variants(prec, pass, pass == 1 ? c.N : c.M);
+      if (v[pass] < 0 || v[pass] >= n) return false;
+    }
+    return true;
+  };
+  auto valid_tile = [&](const GridClass& c, const std::array<int, 3>& t) {
+    for (int pass = 0; pass < 3; ++pass)
+      if (t[pass] < 0 || t[pass] > sg_max_tile(prec, pass, pass == 1 ? c.N : c.M, c.var[pass])) return false;
+    return true;
+  };
+  std::vector<int> todo;  // classes with something to time
+  for (int i = 0; i < (int)p->classes.size(); ++i) {
+    GridClass& c = p->classes[i];
+    bool have_var = false, have_tile = false;
+    auto iv = g_tune.var.find(var_key(dev, prec, c));
+    if (iv != g_tune.var.end() && valid_var(c, iv->second)) {
+      for (int pass = 0; pass < 3; ++pass) c.var[pass] = iv->second[pass];
+      have_var = true;
+    }
+    auto it = g_tune.tile.find(tile_key(dev, prec, c));
+    if (have_var || !variants) {
+      if (it != g_tune.tile.end() && valid_tile(c, it->second)) {
+        for (int pass = 0; pass < 3; ++pass) c.tile[pass] = it->second[pass];
+        have_tile = true;
+      }
+    }
+    if (have_var || have_tile) c.src = 2;
+    if (timing && !((have_var || !variants) && have_tile)) todo.push_back(i);
+  }
+  if (todo.empty()) return SG_OK;
+  // scratch buffers for the timing runs (zero input)
   const size_t el = p->prec == SG_FP64 ? 8 : 4;
   void *sig = nullptr, *fx = nullptr, *fy = nullptr;
-  sg_status s = SG_OK;
-  hipError_t e = hipMalloc(&sig, el * (size_t)p->total);
-  if (e == hipSuccess) e = hipMalloc(&fx, el * (size_t)p->total);
-  if (e == hipSuccess) e = hipMalloc(&fy, el * (size_t)p->total);
-  if (e == hipSuccess) e = hipMemsetAsync(sig, 0, el * (size_t)p->total, p->st);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    s = fail(SG_ERR_NOMEM, "autotune buffers: %s", hipGetErrorString(e));
-  }
-  const int prec = p->prec == SG_FP64 ? 0 : 1;
-  for (GridClass& c : p->classes) {
-    for (int pass = 0; pass < 3 && s == SG_OK; ++pass) {
-      const int cap = sg_max_tile(prec, pass, pass == 1 ? c.N : c.M);
-      int best_tile = 0;
-      float best = 1e30f;
-      for (int t = 1; t <= cap && s == SG_OK; t *= 2) {
-        float ms = 0.0f;
-        s = time_tile(p, c, pass, t, sig, fx, fy, &ms);
-        if (s == SG_OK && ms < best) {
-          best = ms;
-          best_tile = t;
+  sg_status s = tmp_alloc(&sig, el * (size_t)p->total, "tuning buffers");
+  if (s == SG_OK) s = tmp_alloc(&fx, el * (size_t)p->total, "tuning buffers");
+  if (s == SG_OK) s = tmp_alloc(&fy, el * (size_t)p->total, "tuning buffers");
+  if (s == SG_OK) s = hip_check(p, hipMemsetAsync(sig, 0, el * (size_t)p->total, p->st), "tuning buffers");
+  for (int i : todo) {
+    if (s != SG_OK) break;
+    GridClass& c = p->classes[i];
+    bool tiled[3] = {false, false, false};
+    if (variants && g_tune.var.find(var_key(dev, prec, c)) == g_tune.var.end()) {
+      // each variant with its best tile; the fastest stays, with that tile
+      for (int pass = 0; pass < 3 && s == SG_OK; ++pass) {
+        const bool fixed = pass == 1 && p->grids[c.members[0]].fs;
+        const int n = fixed ? 1 : sg_variants(prec, pass, pass == 1 ? c.N : c.M);
+        if (n < 2) continue;
+        int best_v = c.var[pass], best_t = c.tile[pass];
+        float best = 1e30f;
+        for (int v = 0; v < n && s == SG_OK; ++v) {
+          c.var[pass] = v;
+          float ms = 0.0f;
+          s = tune_tiles(p, c, pass, sig, fx, fy, &ms);
+          if (s == SG_OK && ms < best) {
+            best = ms;
+            best_v = v;
+            best_t = c.tile[pass];
+          }
         }
+        c.var[pass] = best_v;
+        c.tile[pass] = best_t;
+        tiled[pass] = true;
       }
-      if (s == SG_OK) c.tile[pass] = best_tile;
+      if (s == SG_OK) g_tune.var[var_key(dev, prec, c)] = {c.var[0], c.var[1], c.var[2]};
+    }
+    for (int pass = 0; pass < 3 && s == SG_OK; ++pass)
+      if (!tiled[pass]) s = tune_tiles(p, c, pass, sig, fx, fy, nullptr);
+    if (s == SG_OK) {
+      g_tune.tile[tile_key(dev, prec, c)] = {c.tile[0], c.tile[1], c.tile[2]};
+      c.src = 1;
     }
   }
   (void)hipStreamSynchronize(p->st);
   if (sig) (void)hipFree(sig);
   if (fx) (void)hipFree(fx);
   if (fy) (void)hipFree(fy);
+  if (s == SG_OK && !cache.empty()) {
+    // merge with what other processes may have written meanwhile; ours wins
+    std::map<std::string, std::array<int, 3>> v2, t2;
+    read_cache(cache, v2, t2);
+    for (const auto& kv : g_tune.var) v2[kv.first] = kv.second;
+    for (const auto& kv : g_tune.tile) t2[kv.first] = kv.second;
+    g_tune.var = v2;
+    g_tune.tile = t2;
+    if (!write_cache(cache, g_tune.var, g_tune.tile))
+      fprintf(stderr, "sg: could not write the tuning cache %s\n", cache.c_str());
+  }
   return s;
 }
 
@@ -666,6 +867,16 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
         }
         *slots[pass] = tw[tk];
       }
+      // inverse rows in launch variant 1 (pass code 4), where it exists
+      if (s == SG_OK && sg_variants(pc, 2, G.M) > 1) {
+        const auto tk = std::make_pair(4, G.M);
+        if (!tw.count(tk)) {
+          void* d = nullptr;
+          s = make_twiddles(p, pc, 4, G.M, G.r2m, &d);
+          tw[tk] = d;
+        }
+        G.twC1 = tw[tk];
+      }
       if (s == SG_OK && G.fs) {
         if (!twfs.count(G.N)) {
           void* d = nullptr;
@@ -687,7 +898,15 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
     for (GridClass& x : p->classes)
       if (x.M == G.M && x.N == G.N && x.k == G.k) c = &x;
     if (!c) {
-      p->classes.push_back(GridClass{G.M, G.N, G.k, {}, nullptr, nullptr, nullptr, {0, 0, 0}});
+      GridClass nc;
+      nc.M = G.M;
+      nc.N = G.N;
+      nc.k = G.k;
+      const int pc = prec == SG_FP64 ? 0 : 1;
+      // the Stockham column pass has variants; the four-step one has none
+      nc.var[1] = G.fs ? 0 : sg_default_variant(pc, 1, G.N);
+      nc.var[2] = sg_default_variant(pc, 2, G.M);
+      p->classes.push_back(nc);
       c = &p->classes.back();
     }
     c->members.push_back(i);
@@ -766,7 +985,7 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
         p->sync_ev.push_back(ev);
     }
   }
-  if (s == SG_OK && (flags & SG_FLAG_AUTOTUNE)) s = autotune(p);
+  if (s == SG_OK) s = tune(p);
   if (s == SG_OK) s = dev_alloc(p, (void**)&p->flag, sizeof(int));
   if (s != SG_OK) {
     std::string keep = g_msg;
@@ -914,8 +1133,7 @@ sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy) {
     if (e == hipSuccess) e = mark(p);
     if (e == hipSuccess) e = launch_cols(p, c, c.tile[1], p->st);
     if (e == hipSuccess) e = mark(p);
-    if (e == hipSuccess)
-      e = sg_launch_row_inv(prec, c.M, nullptr, fx, fy, c.N, tj, G.r2m, G.twC, c.desc, ng, c.tile[2], p->st);
+    if (e == hipSuccess) e = launch_rows_inv(p, c, fx, fy, c.tile[2], p->st, c.desc);
     if (e == hipSuccess) e = mark(p);
     if (e != hipSuccess) return hip_check(p, e, "force launch");
   }
@@ -943,8 +1161,7 @@ sg_status sg_forces_noalloc(sg_plan p, const void* sigma, void* fx, void* fy) {
     hipError_t e = sg_launch_row_fwd(prec, c.M, sigma, c.M, nullptr, c.N, G.r2m, solve, 0, G.twA, c.desc_s, ng,
                                      c.tile[0], p->st);
     if (e == hipSuccess) e = launch_cols(p, c, c.tile[1], p->st, c.desc_s);
-    if (e == hipSuccess)
-      e = sg_launch_row_inv(prec, c.M, nullptr, fx, fy, c.N, tj, G.r2m, G.twC, c.desc_s, ng, c.tile[2], p->st);
+    if (e == hipSuccess) e = launch_rows_inv(p, c, fx, fy, c.tile[2], p->st, c.desc_s);
     if (e != hipSuccess) return hip_check(p, e, "force launch (no allocation)");
   }
   return SG_OK;
@@ -966,7 +1183,7 @@ sg_status sg_plan_classes(sg_plan p, int32_t* nclasses, int32_t* info, int32_t c
       for (int pass = 0; pass < 3; ++pass) {
         // the tile the launch uses: rows capped by the row count; columns the
         // largest power of two that divides nx
-        int t = c.tile[pass] > 0 ? c.tile[pass] : sg_max_tile(prec, pass, pass == 1 ? c.N : c.M);
+        int t = c.tile[pass] > 0 ? c.tile[pass] : sg_max_tile(prec, pass, pass == 1 ? c.N : c.M, c.var[pass]);
         if (pass == 1) {
           int d = 1;
           while (d < t && c.M % (2 * d) == 0) d *= 2;
@@ -976,9 +1193,24 @@ sg_status sg_plan_classes(sg_plan p, int32_t* nclasses, int32_t* info, int32_t c
         }
         o[4 + pass] = t;
       }
-      o[7] = 0;
+      o[7] = c.src;
     }
   }
+  return SG_OK;
+}
+
+sg_status sg_plan_tuning(sg_plan p, int32_t cls, int32_t* out) {
+  g_msg.clear();
+  if (!p) return fail(SG_ERR_ARG, "plan is NULL");
+  if (!out) return fail(SG_ERR_ARG, "out is NULL");
+  if (cls < 0 || cls >= (int32_t)p->classes.size()) return fail(SG_ERR_ARG, "class %d out of range", (int)cls);
+  const GridClass& c = p->classes[cls];
+  for (int pass = 0; pass < 3; ++pass) {
+    out[pass] = c.var[pass];
+    out[3 + pass] = c.tile[pass];
+  }
+  out[6] = c.src;
+  out[7] = 0;
   return SG_OK;
 }
 

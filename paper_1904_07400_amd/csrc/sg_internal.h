@@ -28,22 +28,28 @@ hipError_t sg_launch_weights(int k, double hx, double hy, int M, int N, double* 
 hipError_t sg_launch_row_fwd(int prec, int M, const void* src, int64_t ld, void* X, int nrows, const void* r2m,
                              int solve, int full, const void* tw, const sg_bgrid* bg, int ngrids, int tile,
                              hipStream_t st);
-// largest tile (rows or columns per workgroup) of a pass: 0 = A, 1 = B, 2 = C
-int sg_max_tile(int prec, int pass, int len);
+// Launch variants of a pass (0 = A, 1 = B, 2 = C) for a transform length
+// (kernels of the same result with other buffering or elements per
+// thread): their number (0 for an unsupported length) and the default.
+int sg_variants(int prec, int pass, int len);
+int sg_default_variant(int prec, int pass, int len);
+// largest tile (rows or columns per workgroup) of a pass in a variant
+int sg_max_tile(int prec, int pass, int len, int variant);
 // X: column-major row spectra (bin p of row j at X[p*N + j]); V: tiles of
 // tj rows (sg_row_tile), the layout the inverse row pass reads.  kind: 0 for
 // odd k (tables of A, W = i A), 1 for even k (W = ph i A, ph the bin's
 // half-cell phase); tx, ty are the quarter tables of A in either case.
 hipError_t sg_launch_col(int prec, int N, const void* X, void* V, int M, int tj, const void* tx, const void* ty,
                          int kind, const void* r2n, int solve, const void* tw, const sg_bgrid* bg, int ngrids,
-                         int tile, hipStream_t st);
+                         int tile, int variant, hipStream_t st);
 int sg_row_tile(int prec, int M, int N);
 hipError_t sg_launch_row_inv(int prec, int M, const void* V, void* fx, void* fy, int nrows, int tj, const void* r2m,
-                             const void* tw, const sg_bgrid* bg, int ngrids, int tile, hipStream_t st);
+                             const void* tw, const sg_bgrid* bg, int ngrids, int tile, int variant, hipStream_t st);
 hipError_t sg_launch_spec_col(int N, const void* S, int M, void* tab, int kind, int fp32, double scale,
                               const void* r2n, const void* tw, hipStream_t st);
 // Stage twiddle tables of a pass's FFT (pass 0: forward rows, 1: columns,
-// 2: inverse rows, 3: spectrum columns, FP64 only); len = M or N; roots =
+// 2: inverse rows, 3: spectrum columns, FP64 only, 4: inverse rows in
+// launch variant 1, FP32 only); len = M or N; roots =
 // the 2*len-th roots in the pass precision.  Returns the entry count (out ==
 // NULL) or fills out on st; -1 for an unsupported size.
 int sg_twiddles(int prec, int pass, int len, const void* roots, void* out, hipStream_t st);

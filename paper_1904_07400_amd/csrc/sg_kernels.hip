@@ -500,7 +500,21 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
 }
 
 // ---------------------------------------------------------------- pass B --
-template <typename R, int N>
+// Lengths with a second launch variant (FP32): the Stockham column pass
+// from 64 to 1536 (2048 and up take the four-step pass), the inverse row
+// pass from 512 on.
+template <int N>
+constexpr bool col_variants() {
+  return N >= 64 && N <= 1536;
+}
+template <int M>
+constexpr bool rowinv_variants() {
+  return M >= 512;
+}
+
+// V: launch variant (FP32 only): 0 = SG_COL_NBUF32 exchange buffers per
+// column, 1 = two (more columns per workgroup; the same arithmetic)
+template <typename R, int N, int V = 0>
 struct col_cfg {
   static constexpr int E0 = sizeof(R) == 4 ? SG_COL_E32 : SG_COL_E64;
   static constexpr int E = elems_for(N, E0, SG_E3);
@@ -510,7 +524,7 @@ struct col_cfg {
   static constexpr int SLOT = LL > TRI ? LL : TRI;  // per-column LDS slot (complex elements)
   // exchange buffers per column: 2 or 4 let as many transforms share their
   // barriers
-  static constexpr int NBUF = sizeof(R) == 4 ? SG_COL_NBUF32 : 1;
+  static constexpr int NBUF = sizeof(R) == 4 ? (V == 1 ? 2 : SG_COL_NBUF32) : 1;
   static constexpr int BYTES = NBUF * SLOT * (int)sizeof(cx<R>);
   // columns per workgroup: up to SG_COL_WG threads, within the LDS budget
   static constexpr int WG = sizeof(R) == 4 ? SG_COL_WG32 : 256;
@@ -632,8 +646,8 @@ __device__ __forceinline__ void col_product(const cx<R>* f, cx<R>* g, int half, 
 
 // MODE: 0 = k 1 (no solve), 1 = k 2 (phased tables), 2 = k 3 (y-solve), 3 =
 // k 4 (phased tables, y-solve), 4 = k 5 (pentadiagonal y-solve)
-template <typename R, typename TO, int N, int MODE>
-__global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
+template <typename R, typename TO, int N, int MODE, int VA = 0>
+__global__ void __launch_bounds__((col_cfg<R, N, VA>::P * col_cfg<R, N, VA>::T))
     SG_WPE(R, COL) k_col(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
           const TO* __restrict__ toy, const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ tw,
           const sg_bgrid* __restrict__ bg) {
@@ -647,7 +661,7 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
     tox = reinterpret_cast<const TO*>(d.tabx);
     toy = reinterpret_cast<const TO*>(d.taby);
   }
-  using C = col_cfg<R, N>;
+  using C = col_cfg<R, N, VA>;
   constexpr int E = C::E, T = C::T, LL = C::SLOT, NBUF = C::NBUF;
   __shared__ cx<R> smem[C::P * LL * NBUF];
   const int P = blockDim.x / T;  // columns per workgroup (<= C::P, divides M)
@@ -868,14 +882,16 @@ __global__ void __launch_bounds__((col_cfg<R, N>::P * col_cfg<R, N>::T))
 // p/2)*tj + j%tj); each row loads its elements straight from the tile, and
 // the rows of one tile go to workgroups on the same XCD so that the tile's
 // cache lines are shared in its L2.
-template <typename R, int M>
+// V: launch variant (FP32 only): 0 = SG_RI_E32 elements per thread, both
+// half-length inverses through the same stages (SG_RI_NBUF32 buffers); 1 =
+// SG_RI_BIG_E elements per thread, the halves one after the other (one
+// exchange buffer per row), so that more rows share a workgroup and the
+// loads of adjacent tile rows leave together (the default from SG_RI_BIG32
+// bins on)
+template <typename R, int M, int V = 0>
 struct rowinv_cfg {
   static constexpr int L = M;
-  // FP32 rows of at least SG_RI_BIG32 bins: 16 elements per thread, the two
-  // half-length inverses one after the other (one exchange buffer per row),
-  // so that four rows share a workgroup and the loads of a tile row quad
-  // leave as 32-byte segments
-  static constexpr bool BIG = sizeof(R) == 4 && M >= SG_RI_BIG32;
+  static constexpr bool BIG = sizeof(R) == 4 && V == 1;
   static constexpr int E = elems_for(L, sizeof(R) == 4 ? (BIG ? SG_RI_BIG_E : SG_RI_E32) : SG_RI_E64, SG_E3);
   static constexpr int T = L / E;
   static constexpr int LL = lds_len<L>::value;
@@ -889,8 +905,8 @@ struct rowinv_cfg {
   static constexpr int G = (G0 < GL ? G0 : GL) < 1 ? 1 : (G0 < GL ? G0 : GL);
 };
 
-template <typename R, typename Out, int M>
-__global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
+template <typename R, typename Out, int M, int VA = 0>
+__global__ void __launch_bounds__((rowinv_cfg<R, M, VA>::G * rowinv_cfg<R, M, VA>::T))
     SG_WPE(R, RI)
     k_row_inv(const cx<R>* __restrict__ V, Out* __restrict__ fx, Out* __restrict__ fy, int nrows, int tj,
               const cx<R>* __restrict__ r2m, const cx<R>* __restrict__ tw, const sg_bgrid* __restrict__ bg) {
@@ -900,7 +916,7 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M>::G * rowinv_cfg<R, M>::T))
     fx += d.off;
     fy += d.off;
   }
-  using C = rowinv_cfg<R, M>;
+  using C = rowinv_cfg<R, M, VA>;
   constexpr int E = C::E, T = C::T, LL = C::LL, NB = C::NB;
   __shared__ cx<R> smem[C::G * C::RS];
   // G rows per workgroup, interleaved lane by lane (thread t of row g is
@@ -1417,11 +1433,11 @@ static hipError_t launch_row_fwd_t(const In* src, int64_t src_ld, cx<R>* X, int 
   return hipGetLastError();
 }
 
-template <typename R, int N>
+template <typename R, int N, int VA = 0>
 static hipError_t launch_col_t(const cx<R>* X, cx<R>* V, int M, int tj, const void* tx, const void* ty, int kind,
                                const cx<R>* r2n, int solve, const cx<R>* tw, const sg_bgrid* bg, int ngrids,
                                int tile, hipStream_t st) {
-  using C = col_cfg<R, N>;
+  using C = col_cfg<R, N, VA>;
   using TO = typename tabs<R>::odd;
   const int P = pow2_div(M, (tile > 0 && tile <= C::P) ? tile : C::P);
   const dim3 grid(M / P, bg ? ngrids : 1);
@@ -1429,30 +1445,30 @@ static hipError_t launch_col_t(const cx<R>* X, cx<R>* V, int M, int tj, const vo
   const TO* toy = (const TO*)ty;
   // modes: 0 = k 1, 1 = k 2, 2 = k 3, 3 = k 4, 4 = k 5 (solve = k for k >= 3)
   if (solve == 4)
-    hipLaunchKernelGGL((k_col<R, TO, N, 3>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
+    hipLaunchKernelGGL((k_col<R, TO, N, 3, VA>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
                        tw, bg);
   else if (solve == 5)
-    hipLaunchKernelGGL((k_col<R, TO, N, 4>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
+    hipLaunchKernelGGL((k_col<R, TO, N, 4, VA>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
                        tw, bg);
   else if (kind == 1)
-    hipLaunchKernelGGL((k_col<R, TO, N, 1>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
+    hipLaunchKernelGGL((k_col<R, TO, N, 1, VA>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
                        tw, bg);
   else if (solve)
-    hipLaunchKernelGGL((k_col<R, TO, N, 2>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
+    hipLaunchKernelGGL((k_col<R, TO, N, 2, VA>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
                        tw, bg);
   else
-    hipLaunchKernelGGL((k_col<R, TO, N, 0>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
+    hipLaunchKernelGGL((k_col<R, TO, N, 0, VA>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
                        tw, bg);
   return hipGetLastError();
 }
 
-template <typename R, typename Out, int M>
+template <typename R, typename Out, int M, int VA = 0>
 static hipError_t launch_row_inv_t(const cx<R>* V, Out* fx, Out* fy, int nrows, int tj, const cx<R>* r2m,
                                    const cx<R>* tw, const sg_bgrid* bg, int ngrids, int tile, hipStream_t st) {
-  using C = rowinv_cfg<R, M>;
+  using C = rowinv_cfg<R, M, VA>;
   const int G = pick_tile(tile, C::G, nrows);
   const int blocks = (nrows + G - 1) / G;
-  hipLaunchKernelGGL((k_row_inv<R, Out, M>), dim3(blocks, bg ? ngrids : 1), dim3(G * C::T), 0, st, V, fx, fy, nrows,
+  hipLaunchKernelGGL((k_row_inv<R, Out, M, VA>), dim3(blocks, bg ? ngrids : 1), dim3(G * C::T), 0, st, V, fx, fy, nrows,
                      tj, r2m, tw, bg);
   return hipGetLastError();
 }
@@ -1510,10 +1526,13 @@ static hipError_t row_fwd_dispatch(int M, const In* src, int64_t ld, cx<R>* X, i
 template <typename R>
 static hipError_t col_dispatch(int N, const cx<R>* X, cx<R>* V, int M, int tj, const void* tx, const void* ty,
                                int kind, const cx<R>* r2n, int solve, const cx<R>* tw, const sg_bgrid* bg,
-                               int ngrids, int tile, hipStream_t st) {
+                               int ngrids, int tile, int variant, hipStream_t st) {
   switch (N) {
-#define CASE(SZ) \
-  case SZ:       \
+#define CASE(SZ)                                                                                        \
+  case SZ:                                                                                              \
+    if (sizeof(R) == 4 && variant == 1 && col_variants<SZ>())                                           \
+      return launch_col_t<R, SZ, col_variants<SZ>() ? 1 : 0>(X, V, M, tj, tx, ty, kind, r2n, solve, tw, bg, \
+                                                              ngrids, tile, st);                        \
     return launch_col_t<R, SZ>(X, V, M, tj, tx, ty, kind, r2n, solve, tw, bg, ngrids, tile, st);
     SG_SIZES(CASE)
 #undef CASE
@@ -1527,10 +1546,14 @@ static hipError_t col_dispatch(int N, const cx<R>* X, cx<R>* V, int M, int tj, c
 #if SG_IN_PART(1)
 template <typename R, typename Out>
 static hipError_t row_inv_dispatch(int M, const cx<R>* V, Out* fx, Out* fy, int nrows, int tj, const cx<R>* r2m,
-                                   const cx<R>* tw, const sg_bgrid* bg, int ngrids, int tile, hipStream_t st) {
+                                   const cx<R>* tw, const sg_bgrid* bg, int ngrids, int tile, int variant,
+                                   hipStream_t st) {
   switch (M) {
-#define CASE(SZ) \
-  case SZ:       \
+#define CASE(SZ)                                                                                            \
+  case SZ:                                                                                                  \
+    if (sizeof(R) == 4 && variant == 1 && rowinv_variants<SZ>())                                            \
+      return launch_row_inv_t<R, Out, SZ, rowinv_variants<SZ>() ? 1 : 0>(V, fx, fy, nrows, tj, r2m, tw, bg, \
+                                                                          ngrids, tile, st);                \
     return launch_row_inv_t<R, Out, SZ>(V, fx, fy, nrows, tj, r2m, tw, bg, ngrids, tile, st);
     SG_ROW_SIZES(CASE)
 #undef CASE
@@ -1558,12 +1581,12 @@ hipError_t sg_launch_row_fwd(int prec, int M, const void* src, int64_t ld, void*
 #if SG_IN_PART(2)
 hipError_t sg_launch_col(int prec, int N, const void* X, void* V, int M, int tj, const void* tx, const void* ty,
                          int kind, const void* r2n, int solve, const void* tw, const sg_bgrid* bg, int ngrids,
-                         int tile, hipStream_t st) {
+                         int tile, int variant, hipStream_t st) {
   if (prec == 0)
     return col_dispatch<double>(N, (const cx<double>*)X, (cx<double>*)V, M, tj, tx, ty, kind,
-                                (const cx<double>*)r2n, solve, (const cx<double>*)tw, bg, ngrids, tile, st);
+                                (const cx<double>*)r2n, solve, (const cx<double>*)tw, bg, ngrids, tile, 0, st);
   return col_dispatch<float>(N, (const cx<float>*)X, (cx<float>*)V, M, tj, tx, ty, kind, (const cx<float>*)r2n,
-                             solve, (const cx<float>*)tw, bg, ngrids, tile, st);
+                             solve, (const cx<float>*)tw, bg, ngrids, tile, variant, st);
 }
 
 int sg_row_tile(int prec, int M, int N) {
@@ -1576,24 +1599,24 @@ int sg_row_tile(int prec, int M, int N) {
 
 #if SG_IN_PART(1)
 hipError_t sg_launch_row_inv(int prec, int M, const void* V, void* fx, void* fy, int nrows, int tj, const void* r2m,
-                             const void* tw, const sg_bgrid* bg, int ngrids, int tile, hipStream_t st) {
+                             const void* tw, const sg_bgrid* bg, int ngrids, int tile, int variant, hipStream_t st) {
   if (prec == 0)
     return row_inv_dispatch<double, double>(M, (const cx<double>*)V, (double*)fx, (double*)fy, nrows, tj,
-                                            (const cx<double>*)r2m, (const cx<double>*)tw, bg, ngrids, tile, st);
+                                            (const cx<double>*)r2m, (const cx<double>*)tw, bg, ngrids, tile, 0, st);
   return row_inv_dispatch<float, float>(M, (const cx<float>*)V, (float*)fx, (float*)fy, nrows, tj,
-                                        (const cx<float>*)r2m, (const cx<float>*)tw, bg, ngrids, tile, st);
+                                        (const cx<float>*)r2m, (const cx<float>*)tw, bg, ngrids, tile, variant, st);
 }
 
 // Largest tile of a pass (0 = A rows, 1 = B columns, 2 = C rows) for a
 // transform length (M for A and C, N for B); 0 for an unsupported length.
 template <typename R>
-static int max_tile_t(int pass, int len) {
+static int max_tile_t(int pass, int len, int v) {
   switch (len) {
-#define CASE(SZ)                                         \
-  case SZ:                                               \
-    if (pass == 0) return rowfwd_cfg<R, R, SZ>::G;       \
-    if (pass == 1) return SZ > 4096 ? 1 : col_cfg<R, SZ>::P; \
-    return rowinv_cfg<R, SZ>::G;
+#define CASE(SZ)                                                                       \
+  case SZ:                                                                             \
+    if (pass == 0) return rowfwd_cfg<R, R, SZ>::G;                                     \
+    if (pass == 1) return SZ > 4096 ? 1 : (v ? col_cfg<R, SZ, 1>::P : col_cfg<R, SZ>::P); \
+    return v ? rowinv_cfg<R, SZ, 1>::G : rowinv_cfg<R, SZ>::G;
     SG_ROW_SIZES(CASE)
 #undef CASE
     default:
@@ -1601,7 +1624,29 @@ static int max_tile_t(int pass, int len) {
   }
 }
 
-int sg_max_tile(int prec, int pass, int len) { return prec == 0 ? max_tile_t<double>(pass, len) : max_tile_t<float>(pass, len); }
+int sg_variants(int prec, int pass, int len) {
+  if (prec == 0) return 1;
+  switch (len) {
+#define CASE(SZ)                                                        \
+  case SZ:                                                              \
+    if (pass == 1) return (SZ <= 4096 && col_variants<SZ>()) ? 2 : 1; \
+    if (pass == 2) return rowinv_variants<SZ>() ? 2 : 1;                \
+    return 1;
+    SG_ROW_SIZES(CASE)
+#undef CASE
+    default:
+      return 0;
+  }
+}
+
+int sg_default_variant(int prec, int pass, int len) {
+  return (prec == 1 && pass == 2 && len >= SG_RI_BIG32 && sg_variants(prec, pass, len) > 1) ? 1 : 0;
+}
+
+int sg_max_tile(int prec, int pass, int len, int variant) {
+  if (variant < 0 || variant >= sg_variants(prec, pass, len)) return 0;
+  return prec == 0 ? max_tile_t<double>(pass, len, 0) : max_tile_t<float>(pass, len, variant);
+}
 
 #endif
 
@@ -1694,7 +1739,8 @@ static int tw_build(const void* roots, int stride, void* out, hipStream_t st) {
 }
 
 // pass: 0 = forward rows (length M/2), 1 = columns (N), 2 = inverse rows (M),
-// 3 = plan-time spectrum columns (N, FP64).  len = M or N.  roots: the
+// 3 = plan-time spectrum columns (N, FP64), 4 = inverse rows in launch
+// variant 1 (FP32).  len = M or N.  roots: the
 // table of the 2*len-th roots in the pass precision.  With out == NULL only
 // the entry count is returned; otherwise the table is filled on st.
 template <typename R>
@@ -1706,12 +1752,14 @@ static int tw_dispatch(int pass, int len, const void* roots, void* out, hipStrea
     if (pass == 1) return tw_build<R, SZ, col_cfg<R, SZ>::E>(roots, 2, out, st);                         \
     if (pass == 2) return tw_build<R, SZ, rowinv_cfg<R, SZ>::E>(roots, 2, out, st);                      \
     if (pass == 3) return tw_build<R, SZ, spec_cfg<SZ>::E>(roots, 2, out, st);                           \
+    if (pass == 4) return tw_build<R, SZ, rowinv_cfg<R, SZ, 1>::E>(roots, 2, out, st);                   \
     return -1;
     SG_SIZES(CASE)
 #undef CASE
     case 8192:  // row passes only (the columns of this length take the four-step pass)
       if (pass == 0) return tw_build<R, 4096, rowfwd_cfg<R, R, 8192>::E>(roots, 4, out, st);
       if (pass == 2) return tw_build<R, 8192, rowinv_cfg<R, 8192>::E>(roots, 2, out, st);
+      if (pass == 4) return tw_build<R, 8192, rowinv_cfg<R, 8192, 1>::E>(roots, 2, out, st);
       return 0;
     default:
       return -1;
@@ -1720,6 +1768,7 @@ static int tw_dispatch(int pass, int len, const void* roots, void* out, hipStrea
 
 int sg_twiddles(int prec, int pass, int len, const void* roots, void* out, hipStream_t st) {
   if (pass == 3 && prec != 0) return -1;
+  if (pass == 4 && (prec != 1 || sg_variants(1, 2, len) < 2)) return -1;
   return prec == 0 ? tw_dispatch<double>(pass, len, roots, out, st) : tw_dispatch<float>(pass, len, roots, out, st);
 }
 

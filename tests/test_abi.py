@@ -65,3 +65,4 @@ def test_status_strings_and_arg_errors():
     assert L.sg_bspline_coeffs(None, None, None) == 1
     assert L.sg_forces_adjoint(None, None, None, None) == 1
     assert L.sg_plan_layout(None, None) == 1
+    assert L.sg_plan_tuning(None, 0, None) == 1
