@@ -35,6 +35,10 @@
  *    message for sg_last_error_message().  After a device error
  *    (SG_ERR_DEVICE) the plan is sticky: every later call on it returns
  *    SG_ERR_STATE until it is destroyed.
+ *  - Diagnostics from the environment: SG_LOG=1 prints every plan's launch
+ *    choices and every error message to stderr; SG_ROCTX=1 marks the entry
+ *    points and the passes of an eager step with roctx ranges (rocprofv3
+ *    --marker-trace), from libroctx64 loaded at first use.
  */
 #ifndef SG_H
 #define SG_H

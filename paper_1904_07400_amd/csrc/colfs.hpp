@@ -39,6 +39,26 @@ template <int N>
 __device__ __forceinline__ bool fs_tab_direct(int qq, int h) {
   return h == 0 ? qq <= N / 2 : qq < N / 2;
 }
+// The same two for row bin qq = base + off, base in [0, SPAN) per thread,
+// off a compile-time constant per register: where the whole range [off,
+// off + SPAN) lies on one side of the reflection, the test and the index
+// choice fold at compile time (all but one register of a D3 thread).
+template <int N, int SPAN>
+__device__ __forceinline__ bool fs_tab_direct_at(int base, int off, int h) {
+  const int lim = h == 0 ? N / 2 : N / 2 - 1;  // direct iff qq <= lim
+  if (off + SPAN - 1 <= lim) return true;
+  if (off > lim) return false;
+  return base + off <= lim;
+}
+template <int N, int SPAN>
+__device__ __forceinline__ int fs_tab_index_at(int base, int off, int h) {
+  const int lim = h == 0 ? N / 2 : N / 2 - 1;
+  const int o = h == 0 ? 0 : N / 2 + 1, m = h == 0 ? N : N - 1;  // reflected entry: o + m - qq
+  if (off + SPAN - 1 <= lim) return o + off + base;
+  if (off > lim) return o + m - off - base;
+  const int qq = base + off;
+  return qq <= lim ? o + qq : o + m - qq;
+}
 
 // z * i A (A: a double, a float, or a float hi+lo pair), times sgn
 __device__ __forceinline__ cx<double> fs_iA(cx<double> z, double a, double sgn) {
@@ -90,9 +110,13 @@ struct colfs_cfg {
 #ifndef SG_COLFS_WPE_D2048
 #define SG_COLFS_WPE_D2048 2
 #endif
+#ifndef SG_COLFS_WPE_F4096
+#define SG_COLFS_WPE_F4096 1
+#endif
 template <typename R, int N>
 struct colfs_wpe {
-  static constexpr int value = (sizeof(R) == 8 && N == 2048) ? SG_COLFS_WPE_D2048 : 1;
+  static constexpr int value =
+      (sizeof(R) == 8 && N == 2048) ? SG_COLFS_WPE_D2048 : ((sizeof(R) == 4 && N == 4096) ? SG_COLFS_WPE_F4096 : 1);
 };
 
 template <typename R, typename TO, int N, int MODE, int E, int SLOTS, int COMP, bool PF = false>
@@ -108,6 +132,7 @@ __global__ void __launch_bounds__(N / E) SG_WAVES_PER_EU(colfs_wpe<R, N>::value)
   constexpr int T = C::T, SL = C::SL;
   constexpr int NG = COMP == 0 ? 4 : 2;  // spectra after the products
   static_assert(SLOTS == 4 || SLOTS == 2 || (SLOTS == 1 && COMP != 0), "LDS plan");
+  static_assert(S::d3_split_ok(), "D3 index split");
   if (bg) {
     const sg_bgrid d = grid_desc(bg);
     X = reinterpret_cast<const cx<R>*>(d.X);
@@ -138,11 +163,12 @@ __global__ void __launch_bounds__(N / E) SG_WAVES_PER_EU(colfs_wpe<R, N>::value)
     if constexpr (pre) {
       const TO* rx = tox + (int64_t)cc * (N + 1);
       const TO* ry = toy + (int64_t)cc * (N + 1);
+      const int db = S::d3_base(t);
 #pragma unroll
       for (int i = 0; i < NT; ++i)
 #pragma unroll
         for (int r = 0; r < E; ++r)
-          tt[i][r] = (comp_of(i) ? ry : rx)[(unsigned)fs_tab_index<TO, N>(S::d3_index(t, r), half_of(i))];
+          tt[i][r] = (comp_of(i) ? ry : rx)[(unsigned)fs_tab_index_at<N, S::D3_SPAN>(db, S::d3_off(r), half_of(i))];
     }
   };
   fs_tw<N, E, R, C::KEEP> tw;
@@ -196,11 +222,11 @@ __global__ void __launch_bounds__(N / E) SG_WAVES_PER_EU(colfs_wpe<R, N>::value)
       const int n1 = j % S::B1, n2 = j / S::B1;
       const int l = n2 % S::LB2, ep = n2 / S::LB2;
       const int tp = (n1 / S::S1) * 64 + n1 % S::S1 + S::S1 * l;
-      smem[pad(tp * E + ep)] = cx<R>{(R)d[e].x, (R)d[e].y};
+      smem[fspad(tp * E + ep)] = cx<R>{(R)d[e].x, (R)d[e].y};
     }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) a[e] = smem[pad(t * E + e)];
+    for (int e = 0; e < E; ++e) a[e] = smem[fspad(t * E + e)];
   }
 
   // ---- forward: fe = FFT(a), fo = FFT(a w_2N^j) (D1 -> D3)
@@ -251,15 +277,16 @@ __global__ void __launch_bounds__(N / E) SG_WAVES_PER_EU(colfs_wpe<R, N>::value)
         f[1][r] = cmul(f[1][r], cmul(wq, pho));
       }
     }
+    const int db = S::d3_base(t);
 #pragma unroll
     for (int i = 0; i < NG; ++i)
 #pragma unroll
       for (int r = 0; r < E; ++r) {
-        const int qq = S::d3_index(t, r), h = half_of(i), cy = comp_of(i);
-        const R sgn = fs_tab_direct<N>(qq, h) ? (R)1 : (cy ? -ex : ex);
+        const int h = half_of(i), cy = comp_of(i);
+        const R sgn = fs_tab_direct_at<N, S::D3_SPAN>(db, S::d3_off(r), h) ? (R)1 : (cy ? -ex : ex);
         TO ent;
         if constexpr (pre) ent = tv[i][r];
-        else ent = (cy ? rowy : rowx)[(unsigned)opaque(fs_tab_index<TO, N>(qq, h))];
+        else ent = (cy ? rowy : rowx)[(unsigned)opaque(fs_tab_index_at<N, S::D3_SPAN>(db, S::d3_off(r), h))];
         g[i][r] = fs_iA(f[h][r], ent, sgn);
       }
   } else {
@@ -278,7 +305,7 @@ __global__ void __launch_bounds__(N / E) SG_WAVES_PER_EU(colfs_wpe<R, N>::value)
       for (int r = 0; r < E; ++r) {
         const int qq = S::d3_index(t, r);
         const int qm = h == 0 ? (qq == 0 ? 0 : N - qq) : N - 1 - qq;
-        const cx<R> u = f[h][r], um = conj(part[pad(qm)]);
+        const cx<R> u = f[h][r], um = conj(part[fspad(qm)]);
         cx<R> c0v{(R)0.5 * (u.x + um.x), (R)0.5 * (u.y + um.y)};
         cx<R> cmv{(R)0.5 * (u.y - um.y), (R)-0.5 * (u.x - um.x)};
         if constexpr (kind == 1) {
@@ -306,7 +333,7 @@ __global__ void __launch_bounds__(N / E) SG_WAVES_PER_EU(colfs_wpe<R, N>::value)
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int r = 0; r < E; ++r) smem[h * SL + pad(S::d3_index(t, r))] = f[h][r];
+        for (int r = 0; r < E; ++r) smem[h * SL + fspad(S::d3_index(t, r))] = f[h][r];
       __syncthreads();
       product(0, smem);
       product(1, smem + SL);
@@ -315,7 +342,7 @@ __global__ void __launch_bounds__(N / E) SG_WAVES_PER_EU(colfs_wpe<R, N>::value)
       for (int h = 0; h < 2; ++h) {
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < E; ++r) smem[pad(S::d3_index(t, r))] = f[h][r];
+        for (int r = 0; r < E; ++r) smem[fspad(S::d3_index(t, r))] = f[h][r];
         __syncthreads();
         product(h, smem);
       }
@@ -444,7 +471,7 @@ __global__ void __launch_bounds__(N / E)
     if (c == 0) {
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < E; ++r) smem[pad(S::d3_index(t, r))] = f[0][r];
+      for (int r = 0; r < E; ++r) smem[fspad(S::d3_index(t, r))] = f[0][r];
       __syncthreads();
     }
 #pragma unroll
@@ -456,7 +483,7 @@ __global__ void __launch_bounds__(N / E)
       int nv = 1;
       if (c == 0) {
         const int qm = h == 0 ? (qq == 0 ? 0 : N - qq) : (N - 1 - qq);
-        const cx<double> u = f[0][r], um = conj(smem[pad(qm)]);
+        const cx<double> u = f[0][r], um = conj(smem[fspad(qm)]);
         vals[0] = cx<double>{0.5 * (u.x + um.x), 0.5 * (u.y + um.y)};
         vals[1] = cx<double>{0.5 * (u.y - um.y), -0.5 * (u.x - um.x)};
         rows[0] = 0;
@@ -575,6 +602,7 @@ __global__ void __launch_bounds__(N / E)
   // conjugate-spectrum products of one half, summed over the components
   auto products = [&](int h, const cx<R> (&fx)[E], const cx<R> (&fy)[E], cx<R> (&hh)[E]) {
     if (!packed) {
+      const int db = S::d3_base(t);
 #pragma unroll
       for (int r = 0; r < E; ++r) {
         const int qq = S::d3_index(t, r);
@@ -585,8 +613,8 @@ __global__ void __launch_bounds__(N / E)
           zx = cmulc(zx, ph);
           zy = cmulc(zy, ph);
         }
-        const bool dir = fs_tab_direct<N>(qq, h);
-        const int ti = fs_tab_index<TO, N>(qq, h);
+        const bool dir = fs_tab_direct_at<N, S::D3_SPAN>(db, S::d3_off(r), h);
+        const int ti = fs_tab_index_at<N, S::D3_SPAN>(db, S::d3_off(r), h);
         const R sx = dir ? (R)-1 : -ex, sy = dir ? (R)-1 : ex;  // conj(i A) = -i A
         hh[r] = fs_iA(zx, rowx[(unsigned)opaque(ti)], sx) + fs_iA(zy, rowy[(unsigned)opaque(ti)], sy);
       }
@@ -602,10 +630,10 @@ __global__ void __launch_bounds__(N / E)
         for (int r = 0; r < E; ++r) {
           const int q = S::d3_index(t, r);
           if (SLOTS == 2) {
-            smem[pad(q)] = fx[r];
-            smem[SL + pad(q)] = fy[r];
+            smem[fspad(q)] = fx[r];
+            smem[SL + fspad(q)] = fy[r];
           } else {
-            smem[pad(q)] = i ? fy[r] : fx[r];
+            smem[fspad(q)] = i ? fy[r] : fx[r];
           }
         }
         __syncthreads();
@@ -614,12 +642,12 @@ __global__ void __launch_bounds__(N / E)
           const int qq = S::d3_index(t, r);
           const int qm = h == 0 ? (qq == 0 ? 0 : N - qq) : N - 1 - qq;
           if (SLOTS == 2) {
-            umx[r] = conj(smem[pad(qm)]);
-            umy[r] = conj(smem[SL + pad(qm)]);
+            umx[r] = conj(smem[fspad(qm)]);
+            umy[r] = conj(smem[SL + fspad(qm)]);
           } else if (i == 0) {
-            umx[r] = conj(smem[pad(qm)]);
+            umx[r] = conj(smem[fspad(qm)]);
           } else {
-            umy[r] = conj(smem[pad(qm)]);
+            umy[r] = conj(smem[fspad(qm)]);
           }
         }
       }
@@ -692,12 +720,12 @@ __global__ void __launch_bounds__(N / E)
     // the y-solve (its LDS in the same slot, after the barrier)
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) smem[pad(S::d1_index(t, e))] = acc[e];
+    for (int e = 0; e < E; ++e) smem[fspad(S::d1_index(t, e))] = acc[e];
     __syncthreads();
     double2 d[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const cx<R> v = smem[pad(t * E + e)];
+      const cx<R> v = smem[fspad(t * E + e)];
       d[e] = make_double2(band_scale(SYS) * (double)v.x, band_scale(SYS) * (double)v.y);
     }
     __syncthreads();

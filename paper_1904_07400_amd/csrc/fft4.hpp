@@ -26,13 +26,29 @@
 //  D3 (frequency order): s = lane % S3, l = lane / S3, k2 = w S3 + s;
 //     register r = i LB1 + b holds k = k2 + B2 ((l E/LB1 + i) + E b).
 // LDS: an exchange area holds NA slots of SLOT padded elements (array i at
-// slot i); index j of a slot lives at pad(j).
+// slot i); index j of a slot lives at fspad(j) = j + D1 (j >> K1) + D2 (j >> K2).
 #pragma once
 #include "fft.hpp"
 #include "kcommon.hpp"
 
 namespace sg {
 
+// The LDS layout of the exchange slots (compile-time knobs; the default is
+// one skew element per 32).  Every shift is far below log2(64 E), so a
+// wave's indices [w 64 E, (w+1) 64 E) map to its own part of a slot.
+#ifndef SG_FS_K1
+#define SG_FS_K1 5
+#endif
+#ifndef SG_FS_D1
+#define SG_FS_D1 1
+#endif
+#ifndef SG_FS_K2
+#define SG_FS_K2 30
+#endif
+#ifndef SG_FS_D2
+#define SG_FS_D2 0
+#endif
+__host__ __device__ constexpr int fspad(int i) { return i + SG_FS_D1 * (i >> SG_FS_K1) + SG_FS_D2 * (i >> SG_FS_K2); }
 // Shape of the four-step split for length N with E elements per thread:
 // step-1 transforms of length B2 = 8 E on 8 lanes, step-3 transforms of
 // length B1 = N / B2 on LB1 = B1 / E lanes.
@@ -47,7 +63,7 @@ struct fs_shape {
   static constexpr int S3 = 64 / LB1;
   static constexpr int Q1 = E / LB2, Q3 = E / LB1;
   static constexpr int WAVE = 64 * E;  // elements of one wave (one array)
-  static constexpr int SLOT = N + (N >> SG_LDS_PAD);
+  static constexpr int SLOT = fspad(N);
   static_assert(T % 64 == 0, "a slice is whole waves");
   static_assert(LB1 >= 1 && LB1 <= E && (64 % LB1) == 0, "step-3 transforms must fit one wave");
   static_assert(B1 * B2 == N, "N = B1 * B2");
@@ -61,15 +77,31 @@ struct fs_shape {
   __host__ __device__ static constexpr int d3_index(int t, int r) {
     return ((t >> 6) * S3 + (t & 63) % S3) + B2 * (((t & 63) / S3) * Q3 + r / LB1 + E * (r % LB1));
   }
+  // the same split into a per-thread part in [0, D3_SPAN) and a per-register
+  // part (a compile-time constant once the register loop is unrolled)
+  static constexpr int D3_SPAN = B2 * (E - Q3 + 1);
+  __host__ __device__ static constexpr int d3_base(int t) {
+    return ((t >> 6) * S3 + (t & 63) % S3) + B2 * (((t & 63) / S3) * Q3);
+  }
+  __host__ __device__ static constexpr int d3_off(int r) { return B2 * (r / LB1 + E * (r % LB1)); }
+  static constexpr bool d3_split_ok() {
+    for (int t = 0; t < T; ++t) {
+      if (d3_base(t) < 0 || d3_base(t) >= D3_SPAN) return false;
+      for (int r = 0; r < E; ++r)
+        if (d3_index(t, r) != d3_base(t) + d3_off(r)) return false;
+    }
+    return true;
+  }
 };
 
-// pad() of a compile-time index.
-__host__ __device__ constexpr int padc(int i) { return i + (i >> SG_LDS_PAD); }
 // The LDS indices below are written as a per-thread base plus compile-time
 // offsets (immediate offsets of the LDS instructions), using
-//   pad(x + y) = pad(x) + padc(y)  when y % 32 == 0,
-//   pad(x + y) = pad(x) + y        when x % E == 0, y < E, E | 32,
-// so that each access pattern takes one address register.
+//   fspad(x + y) = fspad(x) + fspad(y)
+// whenever adding y to x carries across no multiple of 2^K1 or 2^K2 (y a
+// multiple of both, or below 2^K1 with x a multiple of 2^K1, ...), so that
+// each access pattern takes one address register.  Every split below is of
+// that kind for the shapes in use (for the default layout and the others a
+// build may choose; the emulation tests check the results).
 
 // Wave-local barrier: orders this wave's LDS accesses (the LDS operations of
 // one wave complete in order) and keeps the compiler from moving memory
@@ -92,10 +124,10 @@ __device__ __forceinline__ void fs_sub_fwd(cx<R> (&v)[NA][E], cx<R>* area, int b
 #pragma unroll
   for (int i = 0; i < NA; ++i) dft<E, INV>(v[i]);
   wave_sync();  // the wave's earlier reads of the region come first
-  static_assert(32 % E == 0 && (E * LB) % 32 == 0, "index decomposition");
+  static_assert((1 << SG_FS_K1) % E == 0 && (E * LB) % 32 == 0, "index decomposition");
   // base is a multiple of B = E LB (>= 32)
-  cx<R>* wr = area + pad(base + l * E);     // + i SLOT + a
-  cx<R>* rd = area + pad(base) + l * Q;     // + i SLOT + padc(ll E) + q
+  cx<R>* wr = area + fspad(base + l * E);     // + i SLOT + a
+  cx<R>* rd = area + fspad(base) + l * Q;     // + i SLOT + fspad(ll E) + q
 #pragma unroll
   for (int i = 0; i < NA; ++i)
 #pragma unroll
@@ -109,7 +141,7 @@ __device__ __forceinline__ void fs_sub_fwd(cx<R> (&v)[NA][E], cx<R>* area, int b
       const cx<R> w = ll == 0 ? cx<R>{(R)1, (R)0} : tw[r];
 #pragma unroll
       for (int i = 0; i < NA; ++i) {
-        const cx<R> u = rd[i * SLOT + padc(ll * E) + q];
+        const cx<R> u = rd[i * SLOT + fspad(ll * E) + q];
         v[i][r] = (ll == 0) ? u : (INV ? cmulc(u, w) : cmul(u, w));
       }
     }
@@ -129,9 +161,9 @@ __device__ __forceinline__ void fs_sub_bwd(cx<R> (&v)[NA][E], cx<R>* area, int b
   for (int i = 0; i < NA; ++i)
 #pragma unroll
     for (int q = 0; q < Q; ++q) dft<LB, INV>(&v[i][q * LB]);
-  static_assert(32 % E == 0 && (E * LB) % 32 == 0, "index decomposition");
-  cx<R>* wr = area + pad(base) + l * Q;     // + i SLOT + padc(ll E) + q
-  cx<R>* rd = area + pad(base + l * E);     // + i SLOT + a
+  static_assert((1 << SG_FS_K1) % E == 0 && (E * LB) % 32 == 0, "index decomposition");
+  cx<R>* wr = area + fspad(base) + l * Q;     // + i SLOT + fspad(ll E) + q
+  cx<R>* rd = area + fspad(base + l * E);     // + i SLOT + a
   wave_sync();  // the wave's earlier reads of the region come first
 #pragma unroll
   for (int q = 0; q < Q; ++q)
@@ -142,7 +174,7 @@ __device__ __forceinline__ void fs_sub_bwd(cx<R> (&v)[NA][E], cx<R>* area, int b
 #pragma unroll
       for (int i = 0; i < NA; ++i) {
         const cx<R> u = v[i][r];
-        wr[i * SLOT + padc(ll * E) + q] = (ll == 0) ? u : (INV ? cmulc(u, w) : cmul(u, w));
+        wr[i * SLOT + fspad(ll * E) + q] = (ll == 0) ? u : (INV ? cmulc(u, w) : cmul(u, w));
       }
     }
   wave_sync();
@@ -279,24 +311,24 @@ __device__ __forceinline__ void fs_cross13(cx<R> (&v)[NA][E], cx<R>* xa, bool sy
     const int s = lane % S::S1, l = lane / S::S1;
     const int n1 = w * S::S1 + s;
     static_assert(S::B1 % 32 == 0, "index decomposition");
-    cx<R>* wr = xa + pad(l * S::Q1 * S::B1 + n1);  // + i SLOT + padc((q + E b) B1)
+    cx<R>* wr = xa + fspad(l * S::Q1 * S::B1 + n1);  // + i SLOT + fspad((q + E b) B1)
 #pragma unroll
     for (int i = 0; i < NA; ++i)
 #pragma unroll
       for (int q = 0; q < S::Q1; ++q)
 #pragma unroll
-        for (int b = 0; b < S::LB2; ++b) wr[i * S::SLOT + padc((q + E * b) * S::B1)] = v[i][q * S::LB2 + b];
+        for (int b = 0; b < S::LB2; ++b) wr[i * S::SLOT + fspad((q + E * b) * S::B1)] = v[i][q * S::LB2 + b];
   }
   __syncthreads();
   {
     const int s = lane % S::S3, l = lane / S::S3;
     const int k2 = w * S::S3 + s;
     static_assert(32 % S::LB1 == 0, "index decomposition");
-    const cx<R>* rd = xa + pad(k2 * S::B1) + l;  // + i SLOT + padc(LB1 e)
+    const cx<R>* rd = xa + fspad(k2 * S::B1) + l;  // + i SLOT + fspad(LB1 e)
 #pragma unroll
     for (int i = 0; i < NA; ++i)
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[i][e] = rd[i * S::SLOT + padc(S::LB1 * e)];
+      for (int e = 0; e < E; ++e) v[i][e] = rd[i * S::SLOT + fspad(S::LB1 * e)];
   }
 }
 
@@ -326,18 +358,18 @@ __device__ __forceinline__ void fs_cross31(cx<R> (&v)[NA][E], cx<R>* xa, bool sy
   {
     const int k2 = w * S::S3 + lane % S::S3, l = lane / S::S3;
     static_assert(S::B2 % 32 == 0, "index decomposition");
-    cx<R>* wr = xa + pad(l * S::B2 + k2);  // + i SLOT + padc(LB1 e B2)
+    cx<R>* wr = xa + fspad(l * S::B2 + k2);  // + i SLOT + fspad(LB1 e B2)
 #pragma unroll
     for (int i = 0; i < NA; ++i)
 #pragma unroll
-      for (int e = 0; e < E; ++e) wr[i * S::SLOT + padc(S::LB1 * e * S::B2)] = v[i][e];
+      for (int e = 0; e < E; ++e) wr[i * S::SLOT + fspad(S::LB1 * e * S::B2)] = v[i][e];
   }
   __syncthreads();
   {
     const int s = lane % S::S1, l = lane / S::S1;
     const int n1 = w * S::S1 + s;
     const auto to = tw.outer();
-    const cx<R>* rd = xa + pad(n1 * S::B2) + l * S::Q1;  // + i SLOT + q + padc(E b)
+    const cx<R>* rd = xa + fspad(n1 * S::B2) + l * S::Q1;  // + i SLOT + q + fspad(E b)
 #pragma unroll
     for (int q = 0; q < S::Q1; ++q)
 #pragma unroll
@@ -345,7 +377,7 @@ __device__ __forceinline__ void fs_cross31(cx<R> (&v)[NA][E], cx<R>* xa, bool sy
         const int r = q * S::LB2 + b;
         const cx<R> w = to[r];
 #pragma unroll
-        for (int i = 0; i < NA; ++i) v[i][r] = cmulc(rd[i * S::SLOT + q + padc(E * b)], w);
+        for (int i = 0; i < NA; ++i) v[i][r] = cmulc(rd[i * S::SLOT + q + fspad(E * b)], w);
       }
   }
 }

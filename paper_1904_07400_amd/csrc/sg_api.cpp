@@ -1,5 +1,6 @@
 // Host side of the C ABI declared in include/sg.h: plans, validation,
 // workspace, plan-time weight spectra, per-step launch sequences.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
@@ -31,6 +32,17 @@ namespace {
 
 thread_local std::string g_msg;
 
+// Diagnostics from the environment, read at each use: SG_LOG (non-empty,
+// not "0") prints every plan's launch choices and every error to stderr;
+// SG_ROCTX likewise marks the entry points (and the passes of an eager
+// step) with roctx ranges, for rocprofv3 --marker-trace, from libroctx64
+// loaded at first use (no link-time dependency; nothing happens if it is
+// missing).
+bool env_on(const char* name) {
+  const char* v = getenv(name);
+  return v && *v && strcmp(v, "0") != 0;
+}
+
 sg_status fail(sg_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -38,8 +50,50 @@ sg_status fail(sg_status s, const char* fmt, ...) {
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
   g_msg = buf;
+  if (env_on("SG_LOG")) fprintf(stderr, "sg: error %d: %s\n", (int)s, buf);
   return s;
 }
+
+struct Roctx {
+  int (*push)(const char*) = nullptr;
+  int (*pop)() = nullptr;
+};
+const Roctx& roctx() {
+  static const Roctx r = [] {
+    Roctx x;
+    void* h = dlopen("libroctx64.so", RTLD_NOW | RTLD_LOCAL);
+    if (!h) h = dlopen("/opt/rocm/lib/libroctx64.so", RTLD_NOW | RTLD_LOCAL);
+    if (h) {
+      x.push = (int (*)(const char*))dlsym(h, "roctxRangePushA");
+      x.pop = (int (*)())dlsym(h, "roctxRangePop");
+      if (!x.push || !x.pop) x = Roctx{};
+    }
+    return x;
+  }();
+  return r;
+}
+// A roctx range for the lifetime of the object, when SG_ROCTX asks for them.
+class Range {
+ public:
+  explicit Range(const char* msg) : on_(env_on("SG_ROCTX") && roctx().push) {
+    if (on_) roctx().push(msg);
+  }
+  Range(const char* fmt, int a, int b, int c) : on_(env_on("SG_ROCTX") && roctx().push) {
+    if (on_) {
+      char buf[96];
+      snprintf(buf, sizeof buf, fmt, a, b, c);
+      roctx().push(buf);
+    }
+  }
+  ~Range() {
+    if (on_) roctx().pop();
+  }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+
+ private:
+  bool on_;
+};
 
 // Device address of scratch on the current device (once per device).
 std::mutex g_scratch_mu;
@@ -756,6 +810,7 @@ const char* sg_last_error_message(void) { return g_msg.c_str(); }
 
 sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_precision prec, void* hip_stream,
                          uint32_t flags) {
+  Range range("sg_plan_create");
   g_msg.clear();
   g_alloc_count = 0;
   if (!out) return fail(SG_ERR_ARG, "out is NULL");
@@ -995,6 +1050,18 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
     g_msg = keep;
     return s;
   }
+  if (env_on("SG_LOG")) {
+    fprintf(stderr, "sg: plan %p: %d grids, %s, %lld device bytes, %zu classes\n", (void*)p, (int)p->grids.size(),
+            prec == SG_FP64 ? "FP64" : "FP32-split", (long long)p->bytes, p->classes.size());
+    static const char* src[3] = {"defaults", "timed", "stored"};
+    for (const GridClass& c : p->classes) {
+      const GridPlan& G = p->grids[c.members[0]];
+      fprintf(stderr,
+              "sg:   %dx%d k=%d grids=%zu: columns %s, variants %d/%d/%d, tiles %d/%d/%d (%s), spectra %d B per bin\n",
+              c.M, c.N, c.k, c.members.size(), G.fs ? "four-step" : "Stockham", c.var[0], c.var[1], c.var[2], c.tile[0],
+              c.tile[1], c.tile[2], src[c.src], G.tab_bytes);
+    }
+  }
   *out = p;
   return SG_OK;
 }
@@ -1073,6 +1140,7 @@ sg_status sg_bspline_coeffs(sg_plan p, const void* sigma, void* coeffs) {
 
 sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy) {
   g_msg.clear();
+  Range range("sg_forces");
   sg_status s = step_entry(p);
   if (s != SG_OK) return s;
   if (!sigma || !fx || !fy) return fail(SG_ERR_ARG, "sigma, fx or fy is NULL");
@@ -1123,6 +1191,7 @@ sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy) {
   }
   for (const GridClass& c : p->classes) {
     // one launch per pass for every grid of the class, timing marks around them
+    Range crange("class %dx%d k=%d", c.M, c.N, c.k);
     hipError_t e = mark(p);
     const GridPlan& G = p->grids[c.members[0]];
     const int solve = c.k >= 3 ? c.k : 0;
@@ -1143,6 +1212,7 @@ sg_status sg_forces(sg_plan p, const void* sigma, void* fx, void* fy) {
 
 sg_status sg_forces_noalloc(sg_plan p, const void* sigma, void* fx, void* fy) {
   g_msg.clear();
+  Range range("sg_forces_noalloc");
   sg_status s = step_entry(p);
   if (s != SG_OK) return s;
   if (!sigma || !fx || !fy) return fail(SG_ERR_ARG, "sigma, fx or fy is NULL");
@@ -1246,6 +1316,7 @@ sg_status sg_plan_pass_times(sg_plan p, double* ms, int64_t* calls) {
 }
 
 sg_status sg_forces_adjoint(sg_plan p, const void* gfx, const void* gfy, void* gsigma) {
+  Range range("sg_forces_adjoint");
   g_msg.clear();
   sg_status s = step_entry(p);
   if (s != SG_OK) return s;

@@ -8,6 +8,12 @@
 #ifndef SG_COLFS_SPLIT_F4096
 #define SG_COLFS_SPLIT_F4096 0
 #endif
+#ifndef SG_COLFS_E_F4096
+#define SG_COLFS_E_F4096 8
+#endif
+#ifndef SG_COLFS_SLOTS_F4096
+#define SG_COLFS_SLOTS_F4096 4
+#endif
 #ifndef SG_COLFS_SPLIT_D4096
 #define SG_COLFS_SPLIT_D4096 0
 #endif
@@ -41,7 +47,7 @@ struct colfs_sel<double, 2048> {
 template <>
 struct colfs_sel<float, 4096> {
   static constexpr bool ok = true;
-  static constexpr int E = 8, SLOTS = 4, SPLIT = SG_COLFS_SPLIT_F4096;
+  static constexpr int E = SG_COLFS_E_F4096, SLOTS = SG_COLFS_SLOTS_F4096, SPLIT = SG_COLFS_SPLIT_F4096;
 };
 template <>
 struct colfs_sel<float, 8192> {

@@ -8,7 +8,8 @@ cache; a second plan, with or without the flag, takes the stored choices
 (source 2) and gives bit-identical forces, as do one-grid plans; a fresh
 process reads the file and times nothing; SG_TUNE=off keeps the defaults;
 malformed cache lines are skipped; the tuned plan meets the FP32-split bar
-against the FP64 path.
+against the FP64 path.  Also the diagnostics from the environment: SG_LOG
+(launch choices and errors on stderr) and SG_ROCTX (roctx ranges).
 """
 import json
 import os
@@ -165,3 +166,36 @@ def test_tune_off_and_malformed_cache(tmp_path, monkeypatch):
     # quick: tiles timed, variants left at their defaults; the same results
     assert src_q == 1 and var_q == (0, 0, 0) and all(t >= 1 for t in tiles_q)
     assert np.array_equal(fq[0], f0[0]) and np.array_equal(fq[1], f0[1])
+
+
+def test_log_and_roctx_ranges():
+    """SG_LOG prints each plan's launch choices and each error to stderr;
+    SG_ROCTX marks the entry points with roctx ranges (run here without a
+    profiler attached: the calls must succeed and change nothing)."""
+    script = (
+        "import sys\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "import torch\n"
+        "import paper_1904_07400_amd as sg\n"
+        "p = sg.Plan([(256, 128, -1.0, 1.0, -0.5, 0.5, 3), (2048, 2048, -1.0, 1.0, -1.0, 1.0, 1)], sg.SG_FP32_SPLIT)\n"
+        "s = torch.zeros(p.total, device='cuda')\n"
+        "fx, fy = p.forces(s)\n"
+        "g = torch.empty_like(s)\n"
+        "p.adjoint(fx, fy, g)\n"
+        "torch.cuda.synchronize()\n"
+        "print('zero forces', float(fx.abs().max()), float(g.abs().max()))\n"
+        "try:\n"
+        "    sg.Plan([(100, 64, -1.0, 1.0, -1.0, 1.0, 3)], sg.SG_FP32_SPLIT)\n"
+        "except sg.SGError as e:\n"
+        "    print('refused', e.status)\n"
+        "p.close()\n")
+    env = dict(os.environ, SG_LOG="1", SG_ROCTX="1")
+    env.pop("SG_TUNE", None)
+    env.pop("SG_TUNE_CACHE", None)
+    r = subprocess.run([sys.executable, "-c", script], env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "zero forces 0.0 0.0" in r.stdout and "refused 2" in r.stdout, r.stdout
+    assert "sg: plan" in r.stderr and "2 grids, FP32-split" in r.stderr, r.stderr[-2000:]
+    assert "256x128 k=3 grids=1: columns Stockham" in r.stderr, r.stderr[-2000:]
+    assert "2048x2048 k=1 grids=1: columns four-step" in r.stderr and "spectra 4 B per bin" in r.stderr
+    assert "sg: error 2:" in r.stderr, r.stderr[-2000:]
