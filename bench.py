@@ -564,6 +564,8 @@ def main():
     kname = {"A": "k_row_fwd", "B": "k_colfs" if n in (4096, 8192) else "k_col", "C": "k_row_inv"}[name]
     step_gbs = sum(bpc.values()) * cells / (ms32 * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": kname,
+                "byte_model": "algorithmic (read X 8, weight spectra 4 + 4, write V 16 B/cell for pass B; "
+                              "step 12 + 32 + 24 B/cell); traffic: FETCH_SIZE + WRITE_SIZE of the committed profile",
                 "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(kname, n),
                 "bytes_per_cell": bpc[name], "kernel_ms": round(pass32[dom], 4),
