@@ -97,8 +97,10 @@ struct colfs_cfg {
 // slots, each phase that writes LDS some other wave may still use starts
 // with a workgroup barrier.
 // COMP: 0 both force components; 1 the x component only, Yx left in V(p);
-// 2 the y component, combined with the Yx of a COMP = 1 launch into V(p),
-// V(2M - p) (two launches, half the registers of one).
+// 2 the y component, combined with the Yx of a COMP = 1 pass into V(p),
+// V(2M - p) (half the registers of COMP 0).  k_colfs_xy runs COMP 1 and 2
+// for the same column in one launch, so that the second pass finds the
+// column and Yx in L2.
 // PF: a workgroup loops over columns b, b + gridDim.x, ... (in the order
 // that keeps an XCD's columns together) and loads the next column and its
 // table entries while it transforms the current one; the phases w_2N^j stay
@@ -119,11 +121,14 @@ struct colfs_wpe {
       (sizeof(R) == 8 && N == 2048) ? SG_COLFS_WPE_D2048 : ((sizeof(R) == 4 && N == 4096) ? SG_COLFS_WPE_F4096 : 1);
 };
 
-template <typename R, typename TO, int N, int MODE, int E, int SLOTS, int COMP, bool PF = false>
-__global__ void __launch_bounds__(N / E) SG_WAVES_PER_EU(colfs_wpe<R, N>::value)
-    k_colfs(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
-            const TO* __restrict__ toy, const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ twfs,
-            const sg_bgrid* __restrict__ bg) {
+// OPQ: the thread index through opaque() (as in the prefetching loop), so
+// that a second pass in the same launch recomputes its index arithmetic
+// instead of keeping the first pass's live across it.
+template <typename R, typename TO, int N, int MODE, int E, int SLOTS, int COMP, bool PF, bool OPQ = false>
+__device__ __forceinline__ void colfs_body(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj,
+                                           const TO* __restrict__ tox, const TO* __restrict__ toy,
+                                           const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ twfs,
+                                           const sg_bgrid* __restrict__ bg, cx<R>* smem) {
   constexpr int kind = (MODE == 1 || MODE == 3) ? 1 : 0;
   constexpr bool solve = MODE >= 2;
   constexpr int SYS = MODE == 2 ? 3 : (MODE == 3 ? 4 : 5);
@@ -140,12 +145,11 @@ __global__ void __launch_bounds__(N / E) SG_WAVES_PER_EU(colfs_wpe<R, N>::value)
     tox = reinterpret_cast<const TO*>(d.tabx);
     toy = reinterpret_cast<const TO*>(d.taby);
   }
-  __shared__ cx<R> smem[C::LDS];
   // exchange areas: A0 (slots 0, 1) and A1 (slots 2, 3, or A0 again)
   cx<R>* A0 = smem;
   cx<R>* A1 = SLOTS == 4 ? smem + 2 * SL : smem;
   constexpr bool cautious = SLOTS < 4;
-  const int t0 = threadIdx.x;
+  const int t0 = OPQ ? opaque((int)threadIdx.x) : (int)threadIdx.x;
   constexpr bool pre = C::KEEP;
   static_assert(!PF || (pre && COMP == 0), "the prefetching loop keeps the table entries in registers");
   constexpr int NT = COMP == 0 ? 4 : 2;  // tables used: (x even, y even, x odd, y odd) or one component's halves
@@ -435,6 +439,30 @@ __global__ void __launch_bounds__(N / E) SG_WAVES_PER_EU(colfs_wpe<R, N>::value)
     __syncthreads();  // this column's last LDS reads come before the next column's writes
   }
   }
+}
+
+template <typename R, typename TO, int N, int MODE, int E, int SLOTS, int COMP, bool PF = false>
+__global__ void __launch_bounds__(N / E) SG_WAVES_PER_EU(colfs_wpe<R, N>::value)
+    k_colfs(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
+            const TO* __restrict__ toy, const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ twfs,
+            const sg_bgrid* __restrict__ bg) {
+  __shared__ cx<R> smem[colfs_cfg<R, N, E, SLOTS>::LDS];
+  colfs_body<R, TO, N, MODE, E, SLOTS, COMP, PF>(X, V, M, tj, tox, toy, r2n, twfs, bg, smem);
+}
+
+// Both force components of a column in one launch: the x pass (Yx into
+// V(p)), a barrier (the LDS of the first pass is the second's), then the y
+// pass, which rereads the column and reads Yx back, each thread the
+// elements it wrote itself, mostly from L2.
+template <typename R, typename TO, int N, int MODE, int E, int SLOTS>
+__global__ void __launch_bounds__(N / E) SG_WAVES_PER_EU(colfs_wpe<R, N>::value)
+    k_colfs_xy(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
+               const TO* __restrict__ toy, const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ twfs,
+               const sg_bgrid* __restrict__ bg) {
+  __shared__ cx<R> smem[colfs_cfg<R, N, E, SLOTS>::LDS];
+  colfs_body<R, TO, N, MODE, E, SLOTS, 1, false, true>(X, V, M, tj, tox, toy, r2n, twfs, bg, smem);
+  __syncthreads();
+  colfs_body<R, TO, N, MODE, E, SLOTS, 2, false, true>(X, V, M, tj, tox, toy, r2n, twfs, bg, smem);
 }
 
 // Plan-time spectrum columns of the long columns (FP64): column c of the

@@ -21,6 +21,10 @@
 #ifndef SG_COLFS_PF
 #define SG_COLFS_PF 1
 #endif
+// component split (FP32 columns of 8192): both passes in one launch (1) or two
+#ifndef SG_COLFS_XY
+#define SG_COLFS_XY 1
+#endif
 // ... and for columns of 2048 (two workgroups per compute unit)
 #ifndef SG_COLFS_PF2048
 #define SG_COLFS_PF2048 0
@@ -102,7 +106,12 @@ static void launch_colfs_k(const cx<R>* X, cx<R>* V, int M, int tj, const TO* to
 template <typename R, typename TO, int N, int MODE>
 static hipError_t launch_colfs_m(const cx<R>* X, cx<R>* V, int M, int tj, const TO* tox, const TO* toy,
                                  const cx<R>* r2n, const cx<R>* tw, const sg_bgrid* bg, int ngrids, hipStream_t st) {
-  if constexpr (colfs_sel<R, N>::SPLIT) {
+  using Sel = colfs_sel<R, N>;
+  if constexpr (Sel::SPLIT && SG_COLFS_XY && sizeof(R) == 4) {
+    // both component passes of a column in one launch
+    hipLaunchKernelGGL((k_colfs_xy<R, TO, N, MODE, Sel::E, Sel::SLOTS>), dim3(M, bg ? ngrids : 1), dim3(N / Sel::E),
+                       0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+  } else if constexpr (Sel::SPLIT) {
     launch_colfs_k<R, TO, N, MODE, 1>(X, V, M, tj, tox, toy, r2n, tw, bg, ngrids, st);
     launch_colfs_k<R, TO, N, MODE, 2>(X, V, M, tj, tox, toy, r2n, tw, bg, ngrids, st);
   } else {

@@ -4,7 +4,8 @@
 // (0 the column pass k_colfs, 1 the adjoint column pass k_colfs_adj, 2 the
 // plan-time spectrum columns k_specfs), EMU_R (float|double), EMU_N, EMU_E,
 // EMU_SLOTS, EMU_MODE, EMU_TO (table element type), EMU_SPLIT (1: the
-// component-split pair of column-pass launches, x then y).
+// component-split pair of column-pass launches, x then y; 2: both in one
+// launch, k_colfs_xy).
 #include <hip/hip_runtime.h>
 
 #include <stdio.h>
@@ -51,7 +52,12 @@ static void run_one(int M, int tj, std::vector<cx<R>>& X, std::vector<cx<R>>& V,
 template <int SP>
 static void run_all(int M, int tj, std::vector<cx<R>>& X, std::vector<cx<R>>& V, std::vector<TO>& tx,
                     std::vector<TO>& ty, std::vector<cx<R>>& r2n, std::vector<cx<R>>& tw) {
-  if constexpr (SP) {
+  if constexpr (SP == 2) {
+    emu::launch(dim3(M), dim3(N / E), [&] {
+      k_colfs_xy<R, TO, N, MODE, E, SLOTS>(X.data(), V.data(), M, tj, tx.data(), ty.data(), r2n.data(), tw.data(),
+                                           nullptr);
+    });
+  } else if constexpr (SP) {
     run_one<1>(M, tj, X, V, tx, ty, r2n, tw);
     run_one<2>(M, tj, X, V, tx, ty, r2n, tw);
   } else {
