@@ -191,7 +191,8 @@ struct GridPlan {
   void* twB = nullptr;
   void* twC = nullptr;
   void* twC1 = nullptr;     // inverse rows in launch variant 1 (FP32, where it exists)
-  bool fs = false;          // columns by the four-step pass (long columns)
+  bool fs = false;          // columns by the four-step pass (long columns, and 1536 in FP32)
+  bool fs_adj = false;      // ... in the adjoint as well (the long columns)
   void* twfs = nullptr;     // its twiddle table
   int tab_bytes = 8;        // bytes per spectrum entry: double, float hi + lo, or float
 };
@@ -873,12 +874,15 @@ sg_status sg_plan_create(sg_plan* out, const sg_grid* grids, int32_t ngrids, sg_
     {
       const char* env = getenv("SG_COLFS");
       const bool off = env && strcmp(env, "0") == 0 && G.N <= 4096;
-      G.fs = sg_colfs_supported(prec == SG_FP64 ? 0 : 1, G.N) && !off;
+      const int sup = off ? 0 : sg_colfs_supported(prec == SG_FP64 ? 0 : 1, G.N);
+      G.fs = sup != 0;
+      G.fs_adj = sup == 1;
     }
     // one real per bin on a quarter of the lattice: FP64; hi+lo FP32; or, for
-    // the four-step pass of FP32-split plans without SG_FLAG_SPECTRA_SPLIT,
-    // FP32.  For even k the bin phase is applied in the column pass.
-    G.tab_bytes = (prec == SG_FP32_SPLIT && G.fs && !(flags & SG_FLAG_SPECTRA_SPLIT)) ? 4 : 8;
+    // FP32-split plans without SG_FLAG_SPECTRA_SPLIT whose columns take the
+    // four-step pass both ways, FP32.  For even k the bin phase is applied
+    // in the column pass.
+    G.tab_bytes = (prec == SG_FP32_SPLIT && G.fs_adj && !(flags & SG_FLAG_SPECTRA_SPLIT)) ? 4 : 8;
     const size_t tab_el = (size_t)G.tab_bytes;
     const size_t tab_n = (size_t)(G.M + 1) * (G.N + 1);
     // grids of equal size, order, cell shape and table form share one pair of spectra
@@ -1334,7 +1338,7 @@ sg_status sg_forces_adjoint(sg_plan p, const void* gfx, const void* gfy, void* g
         sg_launch_row_fwd(prec, c.M, gfx, c.M, nullptr, c.N, G.r2m, 0, 0, G.twA, c.desc, ng, c.tile[0], p->st);
     if (e == hipSuccess)
       e = sg_launch_row_fwd(prec, c.M, gfy, c.M, nullptr, c.N, G.r2m, 0, 0, G.twA, c.desc_y, ng, c.tile[0], p->st);
-    if (e == hipSuccess && G.fs) {
+    if (e == hipSuccess && G.fs_adj) {
       e = sg_launch_colfs_adj(prec, c.N, nullptr, nullptr, nullptr, c.M, tj, nullptr, nullptr, G.kind, G.tab_bytes, G.r2n,
                               solve, G.twfs, c.desc, ng, p->st);
       if (e == hipSuccess)

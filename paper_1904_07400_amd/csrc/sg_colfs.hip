@@ -1,9 +1,11 @@
 // Launches of the four-step column pass (colfs.hpp) for the long columns:
-// N = 2048, 4096 and 8192, FP32 and FP64.  One workgroup of N / E threads
-// per column; for a batch, blockIdx.y is the grid of the class.
+// N = 2048, 4096 and 8192, FP32 and FP64, one workgroup of N / E threads per
+// column; and of the radix-3 form for columns of 1536, FP32 (colfs3.hpp,
+// forward only), one workgroup of three waves per column.  For a batch,
+// blockIdx.y is the grid of the class.
 #include <type_traits>
 
-#include "colfs.hpp"
+#include "colfs3.hpp"
 
 #ifndef SG_COLFS_SPLIT_F4096
 #define SG_COLFS_SPLIT_F4096 0
@@ -155,12 +157,24 @@ static int colfs_twiddles_t(double* re, double* im) {
 using namespace sg;
 
 int sg_colfs_supported(int prec, int N) {
-  (void)prec;
-  return (N == 2048 || N == 4096 || N == 8192) ? 1 : 0;
+  if (N == 2048 || N == 4096 || N == 8192) return 1;
+  return (N == 1536 && prec == 1) ? 2 : 0;
 }
 
 int sg_colfs_twiddles(int prec, int N, double* re, double* im) {
   if (!sg_colfs_supported(prec, N)) return -1;
+  if (N == 1536) {
+    // the three waves' 512-point transforms (null re, im: the size only)
+    if (re && im)
+      fs_fill_twiddles<kC3L, kC3E>(
+        [](int m, int L, double* cr, double* ci) {
+          const long double a = 6.283185307179586476925286766559005768L * (long double)m / (long double)L;
+          *cr = (double)cosl(a);
+          *ci = (double)-sinl(a);
+        },
+        re, im);
+    return fs_shape<kC3L, kC3E>::TW_SIZE;
+  }
   if (prec == 0)
     return N == 2048 ? colfs_twiddles_t<double, 2048>(re, im)
                      : (N == 4096 ? colfs_twiddles_t<double, 4096>(re, im) : colfs_twiddles_t<double, 8192>(re, im));
@@ -179,9 +193,36 @@ static hipError_t colfs_len(int N, F f) {
 }
 }  // namespace sg
 
+namespace sg {
+template <typename TO>
+static hipError_t launch_colfs3(const cx<float>* X, cx<float>* V, int M, int tj, const void* tx, const void* ty,
+                                int kind, const cx<float>* r2n, int solve, const cx<float>* tw, const sg_bgrid* bg,
+                                int ngrids, hipStream_t st) {
+  const TO* tox = (const TO*)tx;
+  const TO* toy = (const TO*)ty;
+  const dim3 grid(M, bg ? ngrids : 1), blk(kC3T);
+  if (solve == 4)
+    hipLaunchKernelGGL((k_colfs3<float, TO, 3>), grid, blk, 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+  else if (solve == 5)
+    hipLaunchKernelGGL((k_colfs3<float, TO, 4>), grid, blk, 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+  else if (kind == 1)
+    hipLaunchKernelGGL((k_colfs3<float, TO, 1>), grid, blk, 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+  else if (solve)
+    hipLaunchKernelGGL((k_colfs3<float, TO, 2>), grid, blk, 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+  else
+    hipLaunchKernelGGL((k_colfs3<float, TO, 0>), grid, blk, 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+  return hipGetLastError();
+}
+}  // namespace sg
+
 hipError_t sg_launch_colfs(int prec, int N, const void* X, void* V, int M, int tj, const void* tx, const void* ty,
                            int kind, int tab_bytes, const void* r2n, int solve, const void* tw, const sg_bgrid* bg,
                            int ngrids, hipStream_t st) {
+  if (N == 1536) {
+    if (prec != 1 || tab_bytes != 8) return hipErrorInvalidValue;
+    return launch_colfs3<float2>((const cx<float>*)X, (cx<float>*)V, M, tj, tx, ty, kind, (const cx<float>*)r2n,
+                                 solve, (const cx<float>*)tw, bg, ngrids, st);
+  }
   if (prec == 0) {
     if (tab_bytes != 8) return hipErrorInvalidValue;
     const cx<double>* Xd = (const cx<double>*)X;

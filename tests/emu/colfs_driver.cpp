@@ -2,7 +2,8 @@
 // the kernel's inputs from a file written by the test, runs the kernel over
 // every column, writes its output.  Configuration at compile time: EMU_KERNEL
 // (0 the column pass k_colfs, 1 the adjoint column pass k_colfs_adj, 2 the
-// plan-time spectrum columns k_specfs), EMU_R (float|double), EMU_N, EMU_E,
+// plan-time spectrum columns k_specfs, 3 the column pass of 1536, k_colfs3),
+// EMU_R (float|double), EMU_N, EMU_E,
 // EMU_SLOTS, EMU_MODE, EMU_TO (table element type), EMU_SPLIT (1: the
 // component-split pair of column-pass launches, x then y; 2: both in one
 // launch, k_colfs_xy).
@@ -15,7 +16,7 @@
 #include <type_traits>
 #include <vector>
 
-#include "colfs.hpp"
+#include "colfs3.hpp"
 
 using namespace sg;
 using R = EMU_R;
@@ -68,8 +69,7 @@ static void run_all(int M, int tj, std::vector<cx<R>>& X, std::vector<cx<R>>& V,
 template <int K>
 static void run_kernel(FILE* f, FILE* o, int M, int tj, std::vector<cx<R>>& tw, std::vector<double>& re,
                        std::vector<double>& im) {
-  using S = fs_shape<N, E>;
-  if constexpr (K == 0) {
+  if constexpr (K == 0 || K == 3) {
     std::vector<cx<R>> X, r2n;
     std::vector<TO> tx, ty;
     rd(f, X, (size_t)M * N);
@@ -77,7 +77,14 @@ static void run_kernel(FILE* f, FILE* o, int M, int tj, std::vector<cx<R>>& tw, 
     rd(f, ty, (size_t)(M + 1) * (N + 1));
     rd(f, r2n, (size_t)2 * N);
     std::vector<cx<R>> V((size_t)2 * M * N, cx<R>{(R)0, (R)0});
-    run_all<SPLIT>(M, tj, X, V, tx, ty, r2n, tw);
+    if constexpr (K == 3) {
+      static_assert(K == 3 && N == kC3N && E == kC3E, "k_colfs3 is the column pass of 1536");
+      emu::launch(dim3(M), dim3(kC3T), [&] {
+        k_colfs3<R, TO, MODE>(X.data(), V.data(), M, tj, tx.data(), ty.data(), r2n.data(), tw.data(), nullptr);
+      });
+    } else {
+      run_all<SPLIT>(M, tj, X, V, tx, ty, r2n, tw);
+    }
     fwrite(V.data(), sizeof(cx<R>), V.size(), o);
   } else if constexpr (K == 1) {
     std::vector<cx<R>> Xx, Xy, r2n;
@@ -94,7 +101,10 @@ static void run_kernel(FILE* f, FILE* o, int M, int tj, std::vector<cx<R>>& tw, 
     });
     fwrite(Y.data(), sizeof(cx<R>), Y.size(), o);
   } else {
-    // spectrum columns: S (M columns of 2N), FP64; tables as TO
+    // spectrum columns: S (M columns of 2N), FP64; tables as TO (the length
+    // depends on K, so that other kernels' builds do not instantiate it)
+    constexpr int NS = K == 2 ? N : 2048;
+    using S = fs_shape<NS, E>;
     std::vector<cx<double>> Sg, r2n;
     rd(f, Sg, (size_t)M * 2 * N);
     rd(f, r2n, (size_t)2 * N);
@@ -103,8 +113,8 @@ static void run_kernel(FILE* f, FILE* o, int M, int tj, std::vector<cx<R>>& tw, 
     const int fp32 = std::is_same<TO, double>::value ? 0 : (std::is_same<TO, float>::value ? 2 : 1);
     std::vector<TO> tab((size_t)(M + 1) * (N + 1));
     const int kind = (MODE == 1 || MODE == 3) ? 1 : 0;
-    emu::launch(dim3(M), dim3(N / E), [&] {
-      k_specfs<N, E>(Sg.data(), M, tab.data(), kind, fp32, 0.25, r2n.data(), twd.data());
+    emu::launch(dim3(M), dim3(NS / E), [&] {
+      k_specfs<NS, E>(Sg.data(), M, tab.data(), kind, fp32, 0.25, r2n.data(), twd.data());
     });
     fwrite(tab.data(), sizeof(TO), tab.size(), o);
   }
@@ -118,10 +128,12 @@ int main(int argc, char** argv) {
   const int M = atoi(argv[1]);
   FILE* f = fopen(argv[2], "rb");
   if (!f) return 2;
-  using S = fs_shape<N, E>;
-  // the four-step twiddle table from long double roots, rounded once
+  // the four-step twiddle table from long double roots, rounded once (for
+  // k_colfs3: that of its 512-point sub-transforms)
+  constexpr int TN = EMU_KERNEL == 3 ? kC3L : N;
+  using S = fs_shape<TN, E>;
   std::vector<double> re(S::TW_SIZE), im(S::TW_SIZE);
-  fs_fill_twiddles<N, E>(
+  fs_fill_twiddles<TN, E>(
       [](int m, int L, double* cr, double* ci) {
         const long double a = 6.283185307179586476925286766559005768L * m / L;
         *cr = (double)cosl(a);

@@ -58,6 +58,8 @@ inline Block* block = nullptr;
 inline void __syncthreads() { emu::block->all->arrive_and_wait(); }
 inline void __builtin_amdgcn_wave_barrier() { emu::block->waves[emu::tid.x / 64]->arrive_and_wait(); }
 #define __builtin_amdgcn_fence(...) ((void)0)
+// the kernels apply it to wave-uniform values only
+inline int __builtin_amdgcn_readfirstlane(int v) { return v; }
 
 inline void sincospi(double x, double* s, double* c) {
   const long double pi = 3.141592653589793238462643383279502884L;

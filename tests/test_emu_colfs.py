@@ -1,12 +1,12 @@
 """CPU emulation of the four-step column kernels (paper_1904_07400_amd/csrc/
-colfs.hpp), built with g++ and ThreadSanitizer: one host thread per GPU
+colfs.hpp, colfs3.hpp), built with g++ and ThreadSanitizer: one host thread per GPU
 thread, workgroup barriers and wave-local barriers as real barriers.  Each
 case checks the kernel's output against the column pass written from its
 definition in numpy (tests/emu/colpass_ref.py), and that ThreadSanitizer
 reports no data race on the LDS (an access that no barrier orders against
 another thread's access to the same element).  Covers the shapes the GPU
 runs (N = 2048, 4096 and 8192, FP32 and FP64, every LDS plan and the
-component split) on a few columns each."""
+component split; the radix-3 form for N = 1536) on a few columns each."""
 import os
 import shutil
 import subprocess
@@ -73,8 +73,22 @@ FWD = [(32, 4096, 8, 4, 3, "float2", 0, 0), (32, 4096, 8, 4, 2, "float", 0, 0), 
 @pytest.mark.parametrize("prec,N,E,slots,k,to,split,pf", FWD,
                          ids=[f"fp{c[0]}-{c[1]}-s{c[3]}-k{c[4]}-{c[5]}-split{c[6]}-pf{c[7]}" for c in FWD])
 def test_column_pass(tmp_path, prec, N, E, slots, k, to, split, pf):
+    _column_case(tmp_path, 0, prec, N, E, slots, k, to, split, pf)
+
+
+# the radix-3 column pass of 1536 (k_colfs3, FP32): every order, both table forms
+FWD3 = [(3, "float2"), (1, "float2"), (2, "float2"), (4, "float"), (5, "float2")]
+
+
+@pytest.mark.skipif(GXX is None, reason="g++ not found")
+@pytest.mark.parametrize("k,to", FWD3, ids=[f"k{c[0]}-{c[1]}" for c in FWD3])
+def test_column_pass_1536(tmp_path, k, to):
+    _column_case(tmp_path, 3, 32, 1536, 8, 4, k, to, 0, 0)
+
+
+def _column_case(tmp_path, kernel, prec, N, E, slots, k, to, split, pf):
     M = 5 if pf else 4  # the prefetching loop: two workgroups over five columns
-    exe = _build(str(tmp_path), 0, prec, N, E, slots, k, to, split, pf)
+    exe = _build(str(tmp_path), kernel, prec, N, E, slots, k, to, split, pf)
     rng = np.random.default_rng(k * 11 + N)
     X = rng.standard_normal((M, N)) + 1j * rng.standard_normal((M, N))
     tx, ty, stored = _tables(rng, M, N, to)

@@ -113,6 +113,12 @@ CASES = [
     (4, 48, 192, (-1, 1, -1, 1), "random"),
     (5, 384, 96, (-1, 1, -0.5, 0.5), "clumps"),
     (4, 12, 12, (-1, 1, -1, 1), "random"),
+    # columns of 1536 (FP32: the radix-3 column pass of three waves), every order
+    (1, 8, 1536, (-0.5, 0.5, -96, 96), "random"),
+    (2, 8, 1536, (-0.5, 0.5, -96, 96), "random"),
+    (3, 16, 1536, (-1, 1, -96, 96), "random"),
+    (4, 8, 1536, (-0.5, 0.5, -96, 96), "random"),
+    (5, 8, 1536, (-0.5, 0.5, -96, 96), "random"),
 ]
 
 
