@@ -108,17 +108,22 @@ struct colfs_cfg {
 // (loads complete in order).  Needs the table entries in registers (KEEP).
 // Minimum waves per SIMD the registers of k_colfs must allow: 2 for FP64
 // columns of 2048 (two workgroups of four waves per compute unit; left
-// alone it takes more than 256 registers, one wave per SIMD), else no cap.
+// alone it takes more than 256 registers, one wave per SIMD), 3 for FP32
+// columns of 2048 (three workgroups with two LDS slots each), else no cap.
 #ifndef SG_COLFS_WPE_D2048
 #define SG_COLFS_WPE_D2048 2
 #endif
 #ifndef SG_COLFS_WPE_F4096
 #define SG_COLFS_WPE_F4096 1
 #endif
+#ifndef SG_COLFS_WPE_F2048
+#define SG_COLFS_WPE_F2048 3
+#endif
 template <typename R, int N>
 struct colfs_wpe {
   static constexpr int value =
-      (sizeof(R) == 8 && N == 2048) ? SG_COLFS_WPE_D2048 : ((sizeof(R) == 4 && N == 4096) ? SG_COLFS_WPE_F4096 : 1);
+      sizeof(R) == 8 ? (N == 2048 ? SG_COLFS_WPE_D2048 : 1)
+                     : (N == 4096 ? SG_COLFS_WPE_F4096 : (N == 2048 ? SG_COLFS_WPE_F2048 : 1));
 };
 
 // OPQ: the thread index through opaque() (as in the prefetching loop), so

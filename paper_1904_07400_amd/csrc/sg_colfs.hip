@@ -40,10 +40,16 @@ template <typename R, int N>
 struct colfs_sel {
   static constexpr bool ok = false;
 };
+// FP32 columns of 2048: two slots (34 KB of LDS) and registers capped at
+// three waves per SIMD (colfs_wpe), so that three workgroups share a
+// compute unit
+#ifndef SG_COLFS_SLOTS_F2048
+#define SG_COLFS_SLOTS_F2048 2
+#endif
 template <>
 struct colfs_sel<float, 2048> {
   static constexpr bool ok = true;
-  static constexpr int E = 8, SLOTS = 4, SPLIT = 0;
+  static constexpr int E = 8, SLOTS = SG_COLFS_SLOTS_F2048, SPLIT = 0;
 };
 template <>
 struct colfs_sel<double, 2048> {

@@ -66,6 +66,7 @@ FWD = [(32, 4096, 8, 4, 3, "float2", 0, 0), (32, 4096, 8, 4, 2, "float", 0, 0), 
        (32, 8192, 16, 2, 4, "float", 1, 0), (64, 4096, 8, 2, 3, "double", 1, 0), (64, 8192, 16, 1, 2, "double", 1, 0),
        (32, 4096, 8, 4, 3, "float", 0, 1), (32, 4096, 8, 4, 1, "float", 0, 1),
        (32, 2048, 8, 4, 3, "float", 0, 0), (32, 2048, 8, 4, 2, "float2", 0, 0), (64, 2048, 8, 2, 5, "double", 0, 0),
+       (32, 2048, 8, 2, 3, "float", 0, 0), (32, 2048, 8, 2, 2, "float", 0, 0), (32, 2048, 8, 2, 1, "float2", 0, 0),
        (32, 8192, 16, 2, 3, "float", 2, 0), (32, 8192, 16, 2, 2, "float2", 2, 0)]
 
 
