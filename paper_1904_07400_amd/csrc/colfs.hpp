@@ -110,6 +110,10 @@ struct colfs_cfg {
 // columns of 2048 (two workgroups of four waves per compute unit; left
 // alone it takes more than 256 registers, one wave per SIMD), 3 for FP32
 // columns of 2048 (three workgroups with two LDS slots each), else no cap.
+// SG_FWD_OPQ: see colfs_body
+#ifndef SG_FWD_OPQ
+#define SG_FWD_OPQ 1
+#endif
 #ifndef SG_COLFS_WPE_D2048
 #define SG_COLFS_WPE_D2048 2
 #endif
@@ -195,9 +199,12 @@ __device__ __forceinline__ void colfs_body(const cx<R>* __restrict__ X, cx<R>* _
   // the loop body stays in the body instead of being hoisted out of the loop
   // and held in registers across it
   const int t = PF ? opaque(t0) : t0;
-  auto w2n_at = [&](int e) -> cx<R> {
+  // a copy of t per phase (SG_FWD_OPQ), as in the adjoint: the products and
+  // the output recompute their indices instead of keeping the load's
+  auto fresh_t = [&]() { return SG_FWD_OPQ ? opaque(t) : t; };
+  auto w2n_at = [&](int tt, int e) -> cx<R> {
     if constexpr (PF) return w2k[e];
-    else return r2n[(unsigned)opaque(S::d1_index(t, e))];
+    else return r2n[(unsigned)opaque(S::d1_index(tt, e))];
   };
   const int c = xcd_tile(it, M);
   const bool packed = (c == 0);
@@ -243,7 +250,7 @@ __device__ __forceinline__ void colfs_body(const cx<R>* __restrict__ X, cx<R>* _
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     f[0][e] = a[e];
-    f[1][e] = cmul(a[e], w2n_at(e));
+    f[1][e] = cmul(a[e], w2n_at(t, e));
   }
   if constexpr (SLOTS == 1) {
 #pragma unroll
@@ -274,6 +281,7 @@ __device__ __forceinline__ void colfs_body(const cx<R>* __restrict__ X, cx<R>* _
     rho = fs_half_phase<R>(1.0 / (2.0 * N));
   }
   if (!packed) {
+    const int tq = fresh_t();
     if constexpr (kind == 1) {
       // even k: the bin phases exp(-i pi (p/2M + q/2N)), shared by x and y
       const cx<R> pho = cmul(php, rho);
@@ -281,12 +289,12 @@ __device__ __forceinline__ void colfs_body(const cx<R>* __restrict__ X, cx<R>* _
       for (int r = 0; r < E; ++r) {
         // exp(-i pi q'/N); without the prefetched tables (long columns, FP64)
         // each load is issued at its use, to bound the registers in flight
-        const cx<R> wq = r2n[(unsigned)(pre ? S::d3_index(t, r) : opaque(S::d3_index(t, r)))];
+        const cx<R> wq = r2n[(unsigned)(pre ? S::d3_index(tq, r) : opaque(S::d3_index(tq, r)))];
         f[0][r] = cmul(f[0][r], cmul(wq, php));
         f[1][r] = cmul(f[1][r], cmul(wq, pho));
       }
     }
-    const int db = S::d3_base(t);
+    const int db = S::d3_base(tq);
 #pragma unroll
     for (int i = 0; i < NG; ++i)
 #pragma unroll
@@ -412,10 +420,11 @@ __device__ __forceinline__ void colfs_body(const cx<R>* __restrict__ X, cx<R>* _
   cx<R>* va = V + (int64_t)(pa & 1) * M * tj + (int64_t)(pa >> 1) * tj;
   cx<R>* vb = V + (int64_t)(pb & 1) * M * tj + (int64_t)(pb >> 1) * tj;
   const int64_t jstride = (int64_t)2 * M * tj;
+  const int ts = fresh_t();
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int j = S::d1_index(t, e);
-    const cx<R> w = w2n_at(e);
+    const int j = S::d1_index(ts, e);
+    const cx<R> w = w2n_at(ts, e);
     const int64_t o = (int64_t)(j / tj) * jstride + (j % tj);
     if constexpr (COMP == 1) {
       va[o] = g[0][e] + cmulc(g[1][e], w);  // Yx, kept for the y launch
@@ -557,6 +566,12 @@ __global__ void __launch_bounds__(N / E)
 // packed row spectra of gC in tiles of tj rows, bin p of row j at
 // ((j/tj*2 + p%2)*(M/2) + p/2)*tj + j%tj.  SLOTS (1 or 2) arrays go through
 // each exchange; every exchange waits for the area to be free.
+// SG_ADJ_OPQ: each phase (forward loads, products, output) takes the thread
+// index through its own opaque move, so that its per-register indices are
+// recomputed there instead of held in registers across the kernel.
+#ifndef SG_ADJ_OPQ
+#define SG_ADJ_OPQ 1
+#endif
 template <typename R, typename TO, int N, int MODE, int E, int SLOTS>
 __global__ void __launch_bounds__(N / E)
     k_colfs_adj(const cx<R>* __restrict__ Xx, const cx<R>* __restrict__ Xy, cx<R>* __restrict__ Y, int M, int tj,
@@ -593,10 +608,12 @@ __global__ void __launch_bounds__(N / E)
     rho = fs_half_phase<R>(1.0 / (2.0 * N));
   }
   // forward transforms of one half of both components (D1 -> D3)
+  auto fresh_t = [&]() { return SG_ADJ_OPQ ? opaque(t) : t; };
   auto forward = [&](int h, cx<R> (&fx)[E], cx<R> (&fy)[E]) {
+    const int tl = fresh_t();
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int j = S::d1_index(t, e);
+      const int j = S::d1_index(tl, e);
       const cx<R> w = h ? r2n[(unsigned)opaque(j)] : cx<R>{(R)1, (R)0};
       fx[e] = cmul(colx[(unsigned)j], w);
       fy[e] = cmul(coly[(unsigned)j], w);
@@ -635,10 +652,11 @@ __global__ void __launch_bounds__(N / E)
   // conjugate-spectrum products of one half, summed over the components
   auto products = [&](int h, const cx<R> (&fx)[E], const cx<R> (&fy)[E], cx<R> (&hh)[E]) {
     if (!packed) {
-      const int db = S::d3_base(t);
+      const int tl = fresh_t();
+      const int db = S::d3_base(tl);
 #pragma unroll
       for (int r = 0; r < E; ++r) {
-        const int qq = S::d3_index(t, r);
+        const int qq = S::d3_index(tl, r);
         cx<R> zx = fx[r], zy = fy[r];
         if constexpr (kind == 1) {
           const cx<R> wq = r2n[(unsigned)opaque(qq)];
@@ -744,8 +762,9 @@ __global__ void __launch_bounds__(N / E)
     }
   }
   cx<R> acc[E];
+  const int to = fresh_t();
 #pragma unroll
-  for (int e = 0; e < E; ++e) acc[e] = hs[0][e] + cmulc(hs[1][e], r2n[(unsigned)opaque(S::d1_index(t, e))]);
+  for (int e = 0; e < E; ++e) acc[e] = hs[0][e] + cmulc(hs[1][e], r2n[(unsigned)opaque(S::d1_index(to, e))]);
   cx<R>* out = Y + (int64_t)(c & 1) * (M / 2) * tj + (int64_t)(c >> 1) * tj;
   const int64_t jstride = (int64_t)M * tj;
   if constexpr (solve) {
@@ -753,7 +772,7 @@ __global__ void __launch_bounds__(N / E)
     // the y-solve (its LDS in the same slot, after the barrier)
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) smem[fspad(S::d1_index(t, e))] = acc[e];
+    for (int e = 0; e < E; ++e) smem[fspad(S::d1_index(to, e))] = acc[e];
     __syncthreads();
     double2 d[E];
 #pragma unroll
@@ -771,7 +790,7 @@ __global__ void __launch_bounds__(N / E)
   } else {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int j = S::d1_index(t, e);
+      const int j = S::d1_index(to, e);
       out[(int64_t)(j / tj) * jstride + (j % tj)] = acc[e];
     }
   }

@@ -56,6 +56,12 @@
 #ifndef SG_RI_PRE
 #define SG_RI_PRE 1
 #endif
+// the inverse row pass takes its thread index through an opaque move for
+// its loads and its stores, so that their indices are not held across the
+// transforms
+#ifndef SG_RI_OPQ
+#define SG_RI_OPQ 1
+#endif
 #ifndef SG_RI_E64
 #define SG_RI_E64 16
 #endif
@@ -905,9 +911,22 @@ struct rowinv_cfg {
   static constexpr int G = (G0 < GL ? G0 : GL) < 1 ? 1 : (G0 < GL ? G0 : GL);
 };
 
+// Minimum waves per SIMD of the inverse row pass: SG_RI_WPE_BIG for the FP32
+// rows of 2048 and 4096 in launch variant 1 (two workgroups of 512 threads
+// per compute unit at 128 registers), else SG_RI_WPE32 / SG_RI_WPE64
+#ifndef SG_RI_WPE_BIG
+#define SG_RI_WPE_BIG 4
+#endif
+template <typename R, int M, int VA>
+struct rowinv_wpe {
+  static constexpr int value = (rowinv_cfg<R, M, VA>::BIG && (M == 2048 || M == 4096))
+                                   ? SG_RI_WPE_BIG
+                                   : (sizeof(R) == 4 ? SG_RI_WPE32 : SG_RI_WPE64);
+};
+
 template <typename R, typename Out, int M, int VA = 0>
 __global__ void __launch_bounds__((rowinv_cfg<R, M, VA>::G * rowinv_cfg<R, M, VA>::T))
-    SG_WPE(R, RI)
+    __attribute__((amdgpu_waves_per_eu(rowinv_wpe<R, M, VA>::value)))
     k_row_inv(const cx<R>* __restrict__ V, Out* __restrict__ fx, Out* __restrict__ fy, int nrows, int tj,
               const cx<R>* __restrict__ r2m, const cx<R>* __restrict__ tw, const sg_bgrid* __restrict__ bg) {
   if (bg) {  // batched: grid blockIdx.y of the class
@@ -935,8 +954,9 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M, VA>::G * rowinv_cfg<R, M, VA
   cx<R> v2[2][E], wr[NB == 2 ? E : 1];
   auto load_half = [&](int half) {
     const cx<R>* base = V + ((int64_t)jb * 2 + half) * M * tj + jj;
+    const int tl = SG_RI_OPQ ? opaque(t) : t;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v2[half][e] = base[(int64_t)(t + e * T) * tj];
+    for (int e = 0; e < E; ++e) v2[half][e] = base[(int64_t)(tl + e * T) * tj];
   };
   load_half(0);
   if constexpr (PRE) load_half(1);
@@ -953,9 +973,10 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M, VA>::G * rowinv_cfg<R, M, VA
     fft<true, M, T>(v2[1], lds, tw, t);
   }
   if (active) {
+    const int ts = SG_RI_OPQ ? opaque(t) : t;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int n = t + e * T;
+      const int n = ts + e * T;
       const cx<R> r = v2[0][e] + cmulc(v2[1][e], NB == 2 ? wr[e] : r2m[n]);
       fx[(int64_t)row * M + n] = (Out)r.x;
       fy[(int64_t)row * M + n] = (Out)r.y;
