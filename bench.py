@@ -77,12 +77,14 @@ def time_plan(sg, torch, grid, prec, sigma_np, steps, warmup, flags=0):
 
 KERNEL_SOURCES = ["paper_1904_07400_amd/csrc/sg_kernels.hip", "paper_1904_07400_amd/csrc/sg_colfs.hip",
                   "paper_1904_07400_amd/csrc/fft.hpp", "paper_1904_07400_amd/csrc/fft4.hpp",
-                  "paper_1904_07400_amd/csrc/colfs.hpp", "paper_1904_07400_amd/csrc/kcommon.hpp",
+                  "paper_1904_07400_amd/csrc/colfs.hpp", "paper_1904_07400_amd/csrc/colfs3.hpp",
+                  "paper_1904_07400_amd/csrc/kcommon.hpp",
                   "paper_1904_07400_amd/csrc/tridiag.hpp", "paper_1904_07400_amd/csrc/sg_internal.h",
                   "paper_1904_07400_amd/build.py"]
 # per-step kernels of the three passes (pass B: the four-step column kernel
-# for columns of 4096 and 8192, the radix kernel otherwise)
-PASS_KERNELS = r"k_(row_fwd|colfs|col|row_inv)<"
+# for columns of 2048, 4096 and 8192, its radix-3 form for 1536, the
+# Stockham kernel otherwise)
+PASS_KERNELS = r"k_(row_fwd|colfs3|colfs|col|row_inv)<"
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "forces_4096_k3_fp32_traffic.md")
 
 
