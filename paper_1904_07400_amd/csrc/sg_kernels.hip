@@ -16,6 +16,8 @@
 //
 // Plan time: weights of Eq. (eqnwB) on the padded 2M x 2N lattice (FP64),
 // then the same row/column transforms in FP64 to get their spectra.
+#include <type_traits>
+
 #include "fft.hpp"
 #include "kcommon.hpp"
 #include "sg_internal.h"
@@ -386,7 +388,9 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
   }
   using C = rowfwd_cfg<R, In, M>;
   constexpr int L = C::L, E = C::E, T = C::T, SLOT = C::SLOT, EC = C::EC, NB = C::NB;
-  __shared__ cx<R> smem[C::G * SLOT * NB];
+  // G * SLOT * NB elements, sized at launch (dyn_lds)
+  extern __shared__ __align__(16) unsigned char sg_dyn_lds[];
+  cx<R>* const smem = reinterpret_cast<cx<R>*>(sg_dyn_lds);
   const int G = blockDim.x / T;  // rows per workgroup (<= C::G)
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int row0 = xcd_tile(blockIdx.x, gridDim.x) * G, row = row0 + g;
@@ -669,7 +673,9 @@ __global__ void __launch_bounds__((col_cfg<R, N, VA>::P * col_cfg<R, N, VA>::T))
   }
   using C = col_cfg<R, N, VA>;
   constexpr int E = C::E, T = C::T, LL = C::SLOT, NBUF = C::NBUF;
-  __shared__ cx<R> smem[C::P * LL * NBUF];
+  // P * LL * NBUF elements, sized at launch (dyn_lds)
+  extern __shared__ __align__(16) unsigned char sg_dyn_lds[];
+  cx<R>* const smem = reinterpret_cast<cx<R>*>(sg_dyn_lds);
   const int P = blockDim.x / T;  // columns per workgroup (<= C::P, divides M)
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -937,6 +943,8 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M, VA>::G * rowinv_cfg<R, M, VA
   }
   using C = rowinv_cfg<R, M, VA>;
   constexpr int E = C::E, T = C::T, LL = C::LL, NB = C::NB;
+  // static, for the compiled maximum of rows (LDS sized at launch measured
+  // slower here: its 128 registers then spill)
   __shared__ cx<R> smem[C::G * C::RS];
   // G rows per workgroup, interleaved lane by lane (thread t of row g is
   // thread t G + g), so that the G rows' elements of one bin, adjacent in a
@@ -1433,6 +1441,23 @@ struct tabs {
 
 // rows (or columns) per workgroup: the requested tile if it is in [1, cap],
 // else cap, and never more than n
+// LDS of the forward row kernel and of the Stockham column kernel: sized at
+// launch for the rows (columns) per workgroup actually launched, so that a smaller
+// tile than the compiled maximum leaves room for more workgroups per compute
+// unit.  The first launch of each kernel allows its largest size (LDS above
+// 64 KB per workgroup is opt-in on some runtimes; an error there is cleared,
+// and an oversized launch then reports its own).
+template <auto K>
+static void dyn_lds_optin(int max_bytes) {
+  static const bool once = [max_bytes] {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(K), hipFuncAttributeMaxDynamicSharedMemorySize, max_bytes) !=
+        hipSuccess)
+      (void)hipGetLastError();
+    return true;
+  }();
+  (void)once;
+}
+
 static inline int pick_tile(int tile, int cap, int n) {
   int g = (tile > 0 && tile <= cap) ? tile : cap;
   return g < n ? g : n;
@@ -1445,12 +1470,16 @@ static hipError_t launch_row_fwd_t(const In* src, int64_t src_ld, cx<R>* X, int 
   using C = rowfwd_cfg<R, In, M>;
   const int G = pick_tile(tile, C::G, nrows);
   const int blocks = (nrows + G - 1) / G;
-  if (solve >= 4)
-    hipLaunchKernelGGL((k_row_fwd<R, In, M, true>), dim3(blocks, bg ? ngrids : 1), dim3(G * C::T), 0, st, src,
+  constexpr int row_bytes = C::SLOT * C::NB * (int)sizeof(cx<R>);
+  if (solve >= 4) {
+    dyn_lds_optin<&k_row_fwd<R, In, M, true>>(C::G * row_bytes);
+    hipLaunchKernelGGL((k_row_fwd<R, In, M, true>), dim3(blocks, bg ? ngrids : 1), dim3(G * C::T), G * row_bytes,
+                       st, src, src_ld, X, nrows, nrows, r2m, solve, full, tw, bg);
+  } else {
+    dyn_lds_optin<&k_row_fwd<R, In, M>>(C::G * row_bytes);
+    hipLaunchKernelGGL((k_row_fwd<R, In, M>), dim3(blocks, bg ? ngrids : 1), dim3(G * C::T), G * row_bytes, st, src,
                        src_ld, X, nrows, nrows, r2m, solve, full, tw, bg);
-  else
-    hipLaunchKernelGGL((k_row_fwd<R, In, M>), dim3(blocks, bg ? ngrids : 1), dim3(G * C::T), 0, st, src, src_ld, X,
-                       nrows, nrows, r2m, solve, full, tw, bg);
+  }
   return hipGetLastError();
 }
 
@@ -1464,22 +1493,24 @@ static hipError_t launch_col_t(const cx<R>* X, cx<R>* V, int M, int tj, const vo
   const dim3 grid(M / P, bg ? ngrids : 1);
   const TO* tox = (const TO*)tx;
   const TO* toy = (const TO*)ty;
+  constexpr int col_bytes = C::SLOT * C::NBUF * (int)sizeof(cx<R>);
+  const int lds = P * col_bytes;
   // modes: 0 = k 1, 1 = k 2, 2 = k 3, 3 = k 4, 4 = k 5 (solve = k for k >= 3)
+  auto go = [&](auto mode) {
+    constexpr int MD = decltype(mode)::value;
+    dyn_lds_optin<&k_col<R, TO, N, MD, VA>>(C::P * col_bytes);
+    hipLaunchKernelGGL((k_col<R, TO, N, MD, VA>), grid, dim3(P * C::T), lds, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+  };
   if (solve == 4)
-    hipLaunchKernelGGL((k_col<R, TO, N, 3, VA>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
-                       tw, bg);
+    go(std::integral_constant<int, 3>{});
   else if (solve == 5)
-    hipLaunchKernelGGL((k_col<R, TO, N, 4, VA>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
-                       tw, bg);
+    go(std::integral_constant<int, 4>{});
   else if (kind == 1)
-    hipLaunchKernelGGL((k_col<R, TO, N, 1, VA>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
-                       tw, bg);
+    go(std::integral_constant<int, 1>{});
   else if (solve)
-    hipLaunchKernelGGL((k_col<R, TO, N, 2, VA>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
-                       tw, bg);
+    go(std::integral_constant<int, 2>{});
   else
-    hipLaunchKernelGGL((k_col<R, TO, N, 0, VA>), grid, dim3(P * C::T), 0, st, X, V, M, tj, tox, toy, r2n,
-                       tw, bg);
+    go(std::integral_constant<int, 0>{});
   return hipGetLastError();
 }
 
