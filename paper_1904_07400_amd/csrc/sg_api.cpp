@@ -542,16 +542,22 @@ sg_status time_tile(sg_plan p, GridClass& c, int pass, int tile, const void* sig
   const int reps = 5;
   float best = 1e30f;
   hipError_t e = hipSuccess;
+  auto launch = [&](int ps) -> hipError_t {
+    if (ps == 0)
+      return sg_launch_row_fwd(prec, c.M, sig, c.M, nullptr, c.N, G.r2m, solve, 0, G.twA, c.desc, ng, t3[0], p->st);
+    if (ps == 1) return launch_cols(p, c, t3[1], p->st);
+    return launch_rows_inv(p, c, fx, fy, t3[2], p->st, c.desc);
+  };
+  // each repetition runs the class's whole step and times the pass under
+  // test inside it, so that the pass meets the caches as a step leaves them
+  // (a pass repeated on its own rewrites lines it has just written, which
+  // favours tiles whose stores are shorter pieces)
   for (int r = 0; r <= reps && e == hipSuccess; ++r) {
-    e = hipEventRecord(a, p->st);
-    if (e != hipSuccess) break;
-    if (pass == 0)
-      e = sg_launch_row_fwd(prec, c.M, sig, c.M, nullptr, c.N, G.r2m, solve, 0, G.twA, c.desc, ng, t3[0], p->st);
-    else if (pass == 1)
-      e = launch_cols(p, c, t3[1], p->st);
-    else
-      e = launch_rows_inv(p, c, fx, fy, t3[2], p->st, c.desc);
-    if (e == hipSuccess) e = hipEventRecord(b, p->st);
+    for (int ps = 0; ps < 3 && e == hipSuccess; ++ps) {
+      if (ps == pass) e = hipEventRecord(a, p->st);
+      if (e == hipSuccess) e = launch(ps);
+      if (e == hipSuccess && ps == pass) e = hipEventRecord(b, p->st);
+    }
     if (e == hipSuccess) e = hipEventSynchronize(b);
     float t = 0.0f;
     if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
