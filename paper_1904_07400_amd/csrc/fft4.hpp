@@ -49,6 +49,13 @@ namespace sg {
 #define SG_FS_D2 0
 #endif
 __host__ __device__ constexpr int fspad(int i) { return i + SG_FS_D1 * (i >> SG_FS_K1) + SG_FS_D2 * (i >> SG_FS_K2); }
+// A block of B consecutive indices that starts at a multiple of B lies within
+// one padding period (2^SG_FS_K1 indices) or covers whole ones: fspad then
+// splits over the block's index arithmetic as the exchanges below assume
+// (blocks of 16 occur for N = 1024, 64 x 16).
+__host__ __device__ constexpr bool fs_block_ok(int B) {
+  return B % (1 << SG_FS_K1) == 0 || (1 << SG_FS_K1) % B == 0;
+}
 // Shape of the four-step split for length N with E elements per thread:
 // step-1 transforms of length B2 = 8 E on 8 lanes, step-3 transforms of
 // length B1 = N / B2 on LB1 = B1 / E lanes.
@@ -124,8 +131,8 @@ __device__ __forceinline__ void fs_sub_fwd(cx<R> (&v)[NA][E], cx<R>* area, int b
 #pragma unroll
   for (int i = 0; i < NA; ++i) dft<E, INV>(v[i]);
   wave_sync();  // the wave's earlier reads of the region come first
-  static_assert((1 << SG_FS_K1) % E == 0 && (E * LB) % 32 == 0, "index decomposition");
-  // base is a multiple of B = E LB (>= 32)
+  static_assert((1 << SG_FS_K1) % E == 0 && fs_block_ok(E * LB), "index decomposition");
+  // base is a multiple of B = E LB (fs_block_ok)
   cx<R>* wr = area + fspad(base + l * E);     // + i SLOT + a
   cx<R>* rd = area + fspad(base) + l * Q;     // + i SLOT + fspad(ll E) + q
 #pragma unroll
@@ -161,7 +168,7 @@ __device__ __forceinline__ void fs_sub_bwd(cx<R> (&v)[NA][E], cx<R>* area, int b
   for (int i = 0; i < NA; ++i)
 #pragma unroll
     for (int q = 0; q < Q; ++q) dft<LB, INV>(&v[i][q * LB]);
-  static_assert((1 << SG_FS_K1) % E == 0 && (E * LB) % 32 == 0, "index decomposition");
+  static_assert((1 << SG_FS_K1) % E == 0 && fs_block_ok(E * LB), "index decomposition");
   cx<R>* wr = area + fspad(base) + l * Q;     // + i SLOT + fspad(ll E) + q
   cx<R>* rd = area + fspad(base + l * E);     // + i SLOT + a
   wave_sync();  // the wave's earlier reads of the region come first
@@ -310,7 +317,7 @@ __device__ __forceinline__ void fs_cross13(cx<R> (&v)[NA][E], cx<R>* xa, bool sy
   {
     const int s = lane % S::S1, l = lane / S::S1;
     const int n1 = w * S::S1 + s;
-    static_assert(S::B1 % 32 == 0, "index decomposition");
+    static_assert(fs_block_ok(S::B1), "index decomposition");
     cx<R>* wr = xa + fspad(l * S::Q1 * S::B1 + n1);  // + i SLOT + fspad((q + E b) B1)
 #pragma unroll
     for (int i = 0; i < NA; ++i)

@@ -1,5 +1,5 @@
 // Launches of the four-step column pass (colfs.hpp) for the long columns:
-// N = 2048, 4096 and 8192, FP32 and FP64, one workgroup of N / E threads per
+// N = 2048, 4096 and 8192 (and 1024 in FP64), one workgroup of N / E threads per
 // column; and of the radix-3 form for columns of 1536, FP32 (colfs3.hpp,
 // forward only), one workgroup of three waves per column.  For a batch,
 // blockIdx.y is the grid of the class.
@@ -46,6 +46,16 @@ struct colfs_sel {
 #ifndef SG_COLFS_SLOTS_F2048
 #define SG_COLFS_SLOTS_F2048 2
 #endif
+template <>
+struct colfs_sel<float, 1024> {
+  static constexpr bool ok = true;
+  static constexpr int E = 8, SLOTS = 4, SPLIT = 0;
+};
+template <>
+struct colfs_sel<double, 1024> {
+  static constexpr bool ok = true;
+  static constexpr int E = 8, SLOTS = 2, SPLIT = 0;
+};
 template <>
 struct colfs_sel<float, 2048> {
   static constexpr bool ok = true;
@@ -162,8 +172,12 @@ static int colfs_twiddles_t(double* re, double* im) {
 
 using namespace sg;
 
+// 1: forward and adjoint; 2: forward only.  Columns of 1024 take the
+// four-step pass in FP64 only (FP32: the Stockham kernel, at 100-116
+// registers, measured faster).
 int sg_colfs_supported(int prec, int N) {
   if (N == 2048 || N == 4096 || N == 8192) return 1;
+  if (N == 1024) return prec == 0 ? 1 : 0;
   return (N == 1536 && prec == 1) ? 2 : 0;
 }
 
@@ -182,16 +196,21 @@ int sg_colfs_twiddles(int prec, int N, double* re, double* im) {
     return fs_shape<kC3L, kC3E>::TW_SIZE;
   }
   if (prec == 0)
-    return N == 2048 ? colfs_twiddles_t<double, 2048>(re, im)
-                     : (N == 4096 ? colfs_twiddles_t<double, 4096>(re, im) : colfs_twiddles_t<double, 8192>(re, im));
-  return N == 2048 ? colfs_twiddles_t<float, 2048>(re, im)
-                   : (N == 4096 ? colfs_twiddles_t<float, 4096>(re, im) : colfs_twiddles_t<float, 8192>(re, im));
+    return N == 1024 ? colfs_twiddles_t<double, 1024>(re, im)
+                     : N == 2048 ? colfs_twiddles_t<double, 2048>(re, im)
+                                 : (N == 4096 ? colfs_twiddles_t<double, 4096>(re, im)
+                                              : colfs_twiddles_t<double, 8192>(re, im));
+  return N == 1024 ? colfs_twiddles_t<float, 1024>(re, im)
+                   : N == 2048 ? colfs_twiddles_t<float, 2048>(re, im)
+                               : (N == 4096 ? colfs_twiddles_t<float, 4096>(re, im)
+                                            : colfs_twiddles_t<float, 8192>(re, im));
 }
 
 namespace sg {
 // f(integral_constant<N>) for the supported lengths
 template <typename F>
 static hipError_t colfs_len(int N, F f) {
+  if (N == 1024) return f(std::integral_constant<int, 1024>{});
   if (N == 2048) return f(std::integral_constant<int, 2048>{});
   if (N == 4096) return f(std::integral_constant<int, 4096>{});
   if (N == 8192) return f(std::integral_constant<int, 8192>{});

@@ -5,8 +5,9 @@ case checks the kernel's output against the column pass written from its
 definition in numpy (tests/emu/colpass_ref.py), and that ThreadSanitizer
 reports no data race on the LDS (an access that no barrier orders against
 another thread's access to the same element).  Covers the shapes the GPU
-runs (N = 2048, 4096 and 8192, FP32 and FP64, every LDS plan and the
-component split; the radix-3 form for N = 1536) on a few columns each."""
+runs (N = 2048, 4096 and 8192 in FP32 and FP64, 1024 in FP64, every LDS plan
+and the component split; the radix-3 form for N = 1536), and 1024 in FP32,
+which the library leaves to the Stockham kernel, on a few columns each."""
 import os
 import shutil
 import subprocess
@@ -67,6 +68,8 @@ FWD = [(32, 4096, 8, 4, 3, "float2", 0, 0), (32, 4096, 8, 4, 2, "float", 0, 0), 
        (32, 4096, 8, 4, 3, "float", 0, 1), (32, 4096, 8, 4, 1, "float", 0, 1),
        (32, 2048, 8, 4, 3, "float", 0, 0), (32, 2048, 8, 4, 2, "float2", 0, 0), (64, 2048, 8, 2, 5, "double", 0, 0),
        (32, 2048, 8, 2, 3, "float", 0, 0), (32, 2048, 8, 2, 2, "float", 0, 0), (32, 2048, 8, 2, 1, "float2", 0, 0),
+       (32, 1024, 8, 4, 3, "float", 0, 0), (32, 1024, 8, 4, 2, "float2", 0, 0), (64, 1024, 8, 2, 5, "double", 0, 0),
+       (64, 1024, 8, 2, 1, "double", 0, 0),
        (32, 8192, 16, 2, 3, "float", 2, 0), (32, 8192, 16, 2, 2, "float2", 2, 0)]
 
 
@@ -111,7 +114,7 @@ def _column_case(tmp_path, kernel, prec, N, E, slots, k, to, split, pf):
 
 ADJ = [(32, 4096, 8, 2, 3, "float2"), (32, 4096, 8, 2, 2, "float"), (32, 8192, 16, 2, 5, "float2"),
        (64, 8192, 16, 1, 3, "double"), (64, 4096, 8, 2, 4, "double"), (32, 2048, 8, 2, 3, "float"),
-       (64, 2048, 8, 2, 2, "double")]
+       (64, 2048, 8, 2, 2, "double"), (32, 1024, 8, 2, 3, "float"), (64, 1024, 8, 2, 4, "double")]
 
 
 @pytest.mark.skipif(GXX is None, reason="g++ not found")
