@@ -1,30 +1,32 @@
-// Column pass for columns of N = 3 * 512 = 1536 (FP32-split) on three waves:
-// a radix-3 step across the waves and, per wave, the 512-point four-step
+// Column pass for columns of N = 3 L (FP32-split), L = 512 (N = 1536) or 256
+// (N = 768), on three waves: a radix-3 step across the waves and, per wave, a
+// transform of length L that stays inside the wave: for 512 the four-step
 // transform of fft4.hpp (fs_shape<512, 8>: step 1 is eight 64-point
-// transforms on 8-lane groups, step 3 one 8-point DFT per lane in
-// registers), so that only the radix-3 steps cross waves.
+// transforms on 8-lane groups, step 3 one 8-point DFT per lane in registers),
+// for 256 four radix-4 Stockham stages.
 //
-// With w_L = exp(-2 pi i / L), n, k < 512, r, q < 3:
-//   forward (decimation in frequency): X[3k + q] = DFT_512(y_q)[k],
-//     y_q[n] = w_1536^(n q) sum_r w_3^(r q) x[n + 512 r];
-//   inverse (decimation in time): x[n + 512 r] = sum_q w_3^(-r q) u_q[n],
-//     u_q[n] = w_1536^(-n q) IDFT_512(X[3 . + q])[n].
+// With w_L = exp(-2 pi i / L), n, k < L, r, q < 3:
+//   forward (decimation in frequency): X[3k + q] = DFT_L(y_q)[k],
+//     y_q[n] = w_N^(n q) sum_r w_3^(r q) x[n + L r];
+//   inverse (decimation in time): x[n + L r] = sum_q w_3^(-r q) u_q[n],
+//     u_q[n] = w_N^(-n q) IDFT_L(X[3 . + q])[n].
 // Wave q computes y_q / u_q; thread t = 64 q + lane holds element e of the
-// sub-transform at n = lane + 64 e (its D1 order) and, after the forward,
-// register r at k = lane + 64 r (its D3 order), i.e. bin 3 (lane + 64 r) + q.
+// sub-transform at n = lane + 64 e (e < E = L / 64) and, after the forward,
+// register r at k = lane + 64 r, i.e. bin 3 (lane + 64 r) + q.
 //
 // The column is otherwise processed as in colfs.hpp (y-solve, forward of the
 // zero-padded 2N column as even and odd bins, products with the spectra,
 // four inverses cropped to N, V(p) and V(2M - p) in the tiled layout):
 //  - the odd-bin input x_j w_2N^j shares the radix-3 reads of x: its radix-3
 //    weights are (w_6 w_3^q)^r, its twiddle w_2N^(n (2q + 1));
-//  - the crop's w_2N^-j, j = n + 512 r, splits into w_2N^-n, applied with
-//    the inverse's twiddle by the writer, and w_6^-r, applied by the reader.
+//  - the crop's w_2N^-j, j = n + L r, splits into w_2N^-n, applied with the
+//    inverse's twiddle by the writer, and w_2N^(-L r) = w_6^-r, applied by
+//    the reader.
 // LDS: four slots of one padded column.  Slot 0 holds x for the forward
-// radix-3 step, slots 2 and 3 the waves' sub-transform areas ([512 q, 512 q +
-// 512) of each slot, touched by wave q only), all four the inverse radix-3
-// exchange.  Workgroup barriers: after x is written, before and after the
-// inverse exchange, and those of the y-solve.
+// radix-3 step, slots 2 and 3 the y-solve's scratch and then the waves'
+// sub-transform areas ([L q, L q + L) of each slot, touched by wave q only),
+// all four the inverse radix-3 exchange.  Workgroup barriers: after x is
+// written, before and after the inverse exchange, and those of the y-solve.
 #pragma once
 #include <type_traits>
 
@@ -32,11 +34,17 @@
 
 namespace sg {
 
-constexpr int kC3L = 512;           // sub-transform length
-constexpr int kC3N = 3 * kC3L;      // column length
-constexpr int kC3E = 8;             // elements per thread
-constexpr int kC3T = 3 * 64;        // threads per column
-constexpr int kC3SL = fspad(kC3N);  // slot (complex elements)
+// Shape per sub-transform length L (512 for columns of 1536, 256 for 768):
+// three waves of 64 lanes, E = L / 64 elements per lane
+template <int L>
+struct c3_shape {
+  static constexpr int N = 3 * L;        // column length
+  static constexpr int E = L / 64;       // elements per thread
+  static constexpr int T = 3 * 64;       // threads per column
+  static constexpr int SL = fspad(N);    // slot (complex elements)
+  static_assert(L == 512 || L == 256, "sub-transform lengths");
+};
+constexpr int kC3T = 3 * 64;
 
 // Minimum waves per SIMD the registers of k_colfs3 must allow (three
 // workgroups of three waves per compute unit fit its LDS)
@@ -82,8 +90,8 @@ __device__ __forceinline__ void c3_wave(int q, F f) {
 // n = lane + 64 e) -> D3 (register r at k = lane + 64 r).  area: this wave's
 // part of the first array's slot (array i at area + i * SL).
 template <int SL, int NA, typename R, typename TW>
-__device__ __forceinline__ void c3_sub_fwd(cx<R> (&v)[NA][kC3E], cx<R>* area, const TW& tw, int lane) {
-  constexpr int E = kC3E;
+__device__ __forceinline__ void c3_sub_fwd(cx<R> (&v)[NA][8], cx<R>* area, const TW& tw, int lane) {
+  constexpr int E = 8;
   const int s = lane % 8, l = lane / 8;
   // step 1: 64-point transforms over n2 for n1 = s, then w_512^(n1 k2)
   fs_sub_fwd<false, E, 8, SL, NA>(v, area, s * 64, tw.set1(), l);
@@ -114,8 +122,8 @@ __device__ __forceinline__ void c3_sub_fwd(cx<R> (&v)[NA][kC3E], cx<R>* area, co
 
 // The inverse (unnormalised) of c3_sub_fwd: D3 in, D1 out.
 template <int SL, int NA, typename R, typename TW>
-__device__ __forceinline__ void c3_sub_inv(cx<R> (&v)[NA][kC3E], cx<R>* area, const TW& tw, int lane) {
-  constexpr int E = kC3E;
+__device__ __forceinline__ void c3_sub_inv(cx<R> (&v)[NA][8], cx<R>* area, const TW& tw, int lane) {
+  constexpr int E = 8;
 #pragma unroll
   for (int i = 0; i < NA; ++i) dft<E, true>(v[i]);  // element e: n1 = e of k2 = lane
   // n1-major: (n1, k2) at index n1 * 64 + k2
@@ -136,17 +144,80 @@ __device__ __forceinline__ void c3_sub_inv(cx<R> (&v)[NA][kC3E], cx<R>* area, co
   fs_sub_bwd<true, E, 8, SL, NA>(v, area, s * 64, tw.set1(), l);
 }
 
-template <typename R, typename TO, int MODE>
+// 256-point transform of NA arrays on one wave (columns of 768): four radix-4
+// Stockham stages, 4 elements per lane, element e at index lane + 64 e in and
+// out (so the output order is that of c3_sub_fwd: register r at k = lane +
+// 64 r), exchanged through this wave's area (array i at area + i * SL) with
+// wave barriers only.  Stage twiddles w_(4 Ns)^(k r) = w_2N^((384 / Ns) k r)
+// from the 2N-roots table of N = 768; INV: conjugate twiddles and inverse
+// DFTs (unnormalised).
+template <bool INV, int SL, int NA, typename R>
+__device__ __forceinline__ void c3_stockham256(cx<R> (&v)[NA][4], cx<R>* area, const cx<R>* __restrict__ r2n,
+                                               int lane) {
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int Ns = 1 << (2 * st);  // 1, 4, 16, 64
+    const int k = lane & (Ns - 1);
+    cx<R> w[4];
+    if (st > 0) {
+#pragma unroll
+      for (int r = 1; r < 4; ++r) w[r] = r2n[(unsigned)((384 / Ns) * k * r)];
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      cx<R> a[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = v[i][r];
+      if (st > 0) {
+#pragma unroll
+        for (int r = 1; r < 4; ++r) a[r] = INV ? cmulc(a[r], w[r]) : cmul(a[r], w[r]);
+      }
+      dft<4, INV>(a);
+      if (st < 3) {
+        const int base = (lane / Ns) * Ns * 4 + k;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) area[i * SL + fspad(base + Ns * r)] = a[r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[i][r] = a[r];
+      }
+    }
+    if (st < 3) {
+      wave_sync();
+#pragma unroll
+      for (int i = 0; i < NA; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[i][e] = area[i * SL + fspad(lane + 64 * e)];
+      wave_sync();  // the reads come before the area's next writes
+    }
+  }
+}
+
+// The sub-transforms by length: the four-step one of 512, the Stockham one
+// of 256
+template <int L, int SL, int NA, typename R, typename TW>
+__device__ __forceinline__ void c3_fwd(cx<R> (&v)[NA][L / 64], cx<R>* area, const TW& tw, const cx<R>* r2n, int lane) {
+  if constexpr (L == 512) c3_sub_fwd<SL, NA>(v, area, tw, lane);
+  else c3_stockham256<false, SL, NA>(v, area, r2n, lane);
+}
+template <int L, int SL, int NA, typename R, typename TW>
+__device__ __forceinline__ void c3_inv(cx<R> (&v)[NA][L / 64], cx<R>* area, const TW& tw, const cx<R>* r2n, int lane) {
+  if constexpr (L == 512) c3_sub_inv<SL, NA>(v, area, tw, lane);
+  else c3_stockham256<true, SL, NA>(v, area, r2n, lane);
+}
+
+template <typename R, typename TO, int MODE, int L = 512>
 __global__ void __launch_bounds__(kC3T) SG_WAVES_PER_EU(SG_COLFS3_WPE)
     k_colfs3(const cx<R>* __restrict__ X, cx<R>* __restrict__ V, int M, int tj, const TO* __restrict__ tox,
              const TO* __restrict__ toy, const cx<R>* __restrict__ r2n, const cx<R>* __restrict__ twfs,
              const sg_bgrid* __restrict__ bg) {
-  constexpr int N = kC3N, L = kC3L, E = kC3E, T = kC3T, SL = kC3SL;
+  using S3 = c3_shape<L>;
+  constexpr int N = S3::N, E = S3::E, T = S3::T, SL = S3::SL;
   constexpr int kind = (MODE == 1 || MODE == 3) ? 1 : 0;
   constexpr bool solve = MODE >= 2;
   constexpr int SYS = MODE == 2 ? 3 : (MODE == 3 ? 4 : 5);
   constexpr bool pre = SG_COLFS3_PRE;
-  static_assert(band_smem<double2, T>::BYTES <= SL * (int)sizeof(cx<R>), "the solve's LDS fits one slot");
+  static_assert(band_smem<double2, T>::BYTES <= 2 * SL * (int)sizeof(cx<R>), "the solve's LDS fits slots 2, 3");
   __shared__ cx<R> smem[4 * SL];
   if (bg) {
     const sg_bgrid d = grid_desc(bg);
@@ -178,16 +249,17 @@ __global__ void __launch_bounds__(kC3T) SG_WAVES_PER_EU(SG_COLFS3_WPE)
 #pragma unroll
       for (int r = 0; r < E; ++r) tv[i][r] = ((i & 1) ? rowy : rowx)[(unsigned)fs_tab_index<TO, N>(bin(r), i >> 1)];
   }
-  fs_tw<L, E, R, true> tw;
-  tw.init(twfs, lane);
+  // the four-step twiddles of the 512-point sub-transforms (unused for 256)
+  fs_tw<512, 8, R, true> tw;
+  if constexpr (L == 512) tw.init(twfs, lane);
 
-  // ---- y-solve (FP64, chunks; its LDS in slot 3), then x to slot 0
+  // ---- y-solve (FP64, chunks; its LDS in slots 2, 3), then x to slot 0
   if constexpr (solve) {
     double2 d[E];
 #pragma unroll
     for (int e = 0; e < E; ++e)
       d[e] = make_double2(band_scale(SYS) * (double)a[e].x, band_scale(SYS) * (double)a[e].y);
-    band_solve<SYS, E, T, double2, false>(d, t, smem + 3 * SL);
+    band_solve<SYS, E, T, double2, false>(d, t, smem + 2 * SL);
 #pragma unroll
     for (int e = 0; e < E; ++e) a[e] = cx<R>{(R)d[e].x, (R)d[e].y};
   }
@@ -205,12 +277,12 @@ __global__ void __launch_bounds__(kC3T) SG_WAVES_PER_EU(SG_COLFS3_WPE)
       const cx<R> x0 = smem[fspad(n)], x1 = smem[fspad(n + L)], x2 = smem[fspad(n + 2 * L)];
       f[0][e] = c3_sum<2 * qc>(x0, x1, x2);
       f[1][e] = c3_sum<2 * qc + 1>(x0, x1, x2);
-      if constexpr (qc != 0) f[0][e] = cmul(f[0][e], r2n[(unsigned)(2 * qc * n)]);  // w_1536^(n q) = w_2N^(2 n q)
+      if constexpr (qc != 0) f[0][e] = cmul(f[0][e], r2n[(unsigned)(2 * qc * n)]);  // w_N^(n q) = w_2N^(2 n q)
       f[1][e] = cmul(f[1][e], r2n[(unsigned)((2 * qc + 1) * n)]);
     }
   });
   cx<R>* sub = smem + 2 * SL + fspad(q * L);  // wave q's area in slot 2 (array 1: slot 3)
-  c3_sub_fwd<SL, 2>(f, sub, tw, lane);
+  c3_fwd<L, SL, 2>(f, sub, tw, r2n, lane);
 
   // ---- products: g = (x even, y even, x odd, y odd)
   cx<R> g[4][E];
@@ -279,7 +351,7 @@ __global__ void __launch_bounds__(kC3T) SG_WAVES_PER_EU(SG_COLFS3_WPE)
   }
 
   // ---- inverse sub-transforms (each wave in its areas of slots 2, 3), then
-  // u_q = w_1536^(-n q) (even halves) and w_2N^(-n (2q + 1)) (odd halves)
+  // u_q = w_N^(-n q) (even halves) and w_2N^(-n (2q + 1)) (odd halves)
   {
     cx<R> g01[2][E], g23[2][E];
 #pragma unroll
@@ -289,8 +361,8 @@ __global__ void __launch_bounds__(kC3T) SG_WAVES_PER_EU(SG_COLFS3_WPE)
       g23[0][e] = g[2][e];
       g23[1][e] = g[3][e];
     }
-    c3_sub_inv<SL, 2>(g01, sub, tw, lane);
-    c3_sub_inv<SL, 2>(g23, sub, tw, lane);
+    c3_inv<L, SL, 2>(g01, sub, tw, r2n, lane);
+    c3_inv<L, SL, 2>(g23, sub, tw, r2n, lane);
     // (for q = 0 the even twiddle is the root 1, an exact product)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -302,7 +374,7 @@ __global__ void __launch_bounds__(kC3T) SG_WAVES_PER_EU(SG_COLFS3_WPE)
       g[3][e] = cmulc(g23[1][e], wo);
     }
   }
-  // ---- inverse radix-3 exchange: array i at slot i, u_q[n] at index 512 q + n
+  // ---- inverse radix-3 exchange: array i at slot i, u_q[n] at index L q + n
   __syncthreads();  // every wave is done with its areas and with slot 0
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -314,11 +386,11 @@ __global__ void __launch_bounds__(kC3T) SG_WAVES_PER_EU(SG_COLFS3_WPE)
   cx<R>* va = V + (int64_t)(pa & 1) * M * tj + (int64_t)(pa >> 1) * tj;
   cx<R>* vb = V + (int64_t)(pb & 1) * M * tj + (int64_t)(pb >> 1) * tj;
   const int64_t jstride = (int64_t)2 * M * tj;
-  // thread (wave r = q, lane): outputs j = n + 512 r, n = lane + 64 e
+  // thread (wave r = q, lane): outputs j = n + L r, n = lane + 64 e
   c3_wave(q, [&](auto Q) {
     constexpr int r3 = decltype(Q)::value;
     // w_3^(-q r) = exp(+2 pi i q r / 3): radix-3 weight c = exp(-2 pi i m / 6),
-    // m = (6 - 2 r) mod 6; the odd halves also take w_2N^(-512 r) = w_6^(-r)
+    // m = (6 - 2 r) mod 6; the odd halves also take w_2N^(-L r) = w_6^(-r)
     constexpr int m3 = (6 - 2 * r3) % 6;
     constexpr R s3 = (R)0.86602540378443864676;
     const cx<R> w6 = r3 == 0 ? cx<R>{(R)1, (R)0} : (r3 == 1 ? cx<R>{(R)0.5, s3} : cx<R>{(R)-0.5, s3});

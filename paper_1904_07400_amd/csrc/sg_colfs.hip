@@ -1,7 +1,7 @@
 // Launches of the four-step column pass (colfs.hpp) for the long columns:
 // N = 2048, 4096 and 8192 (and 1024 in FP64), one workgroup of N / E threads per
-// column; and of the radix-3 form for columns of 1536, FP32 (colfs3.hpp,
-// forward only), one workgroup of three waves per column.  For a batch,
+// column; and of the radix-3 form for columns of 1536 and 768, FP32
+// (colfs3.hpp, forward only), one workgroup of three waves per column.  For a batch,
 // blockIdx.y is the grid of the class.
 #include <type_traits>
 
@@ -172,28 +172,31 @@ static int colfs_twiddles_t(double* re, double* im) {
 
 using namespace sg;
 
-// 1: forward and adjoint; 2: forward only.  Columns of 1024 take the
+// 1: forward and adjoint; 2: forward only (the radix-3 columns of 1536 and
+// 768).  Columns of 1024 take the
 // four-step pass in FP64 only (FP32: the Stockham kernel, at 100-116
 // registers, measured faster).
 int sg_colfs_supported(int prec, int N) {
   if (N == 2048 || N == 4096 || N == 8192) return 1;
   if (N == 1024) return prec == 0 ? 1 : 0;
-  return (N == 1536 && prec == 1) ? 2 : 0;
+  return ((N == 1536 || N == 768) && prec == 1) ? 2 : 0;
 }
 
 int sg_colfs_twiddles(int prec, int N, double* re, double* im) {
   if (!sg_colfs_supported(prec, N)) return -1;
-  if (N == 1536) {
-    // the three waves' 512-point transforms (null re, im: the size only)
+  if (N == 1536 || N == 768) {
+    // the three waves' 512-point transforms (null re, im: the size only); the
+    // 256-point ones of 768 take their twiddles from the 2N-roots table and
+    // ignore it
     if (re && im)
-      fs_fill_twiddles<kC3L, kC3E>(
+      fs_fill_twiddles<512, 8>(
         [](int m, int L, double* cr, double* ci) {
           const long double a = 6.283185307179586476925286766559005768L * (long double)m / (long double)L;
           *cr = (double)cosl(a);
           *ci = (double)-sinl(a);
         },
         re, im);
-    return fs_shape<kC3L, kC3E>::TW_SIZE;
+    return fs_shape<512, 8>::TW_SIZE;
   }
   if (prec == 0)
     return N == 1024 ? colfs_twiddles_t<double, 1024>(re, im)
@@ -219,7 +222,7 @@ static hipError_t colfs_len(int N, F f) {
 }  // namespace sg
 
 namespace sg {
-template <typename TO>
+template <typename TO, int L>
 static hipError_t launch_colfs3(const cx<float>* X, cx<float>* V, int M, int tj, const void* tx, const void* ty,
                                 int kind, const cx<float>* r2n, int solve, const cx<float>* tw, const sg_bgrid* bg,
                                 int ngrids, hipStream_t st) {
@@ -227,15 +230,15 @@ static hipError_t launch_colfs3(const cx<float>* X, cx<float>* V, int M, int tj,
   const TO* toy = (const TO*)ty;
   const dim3 grid(M, bg ? ngrids : 1), blk(kC3T);
   if (solve == 4)
-    hipLaunchKernelGGL((k_colfs3<float, TO, 3>), grid, blk, 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+    hipLaunchKernelGGL((k_colfs3<float, TO, 3, L>), grid, blk, 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
   else if (solve == 5)
-    hipLaunchKernelGGL((k_colfs3<float, TO, 4>), grid, blk, 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+    hipLaunchKernelGGL((k_colfs3<float, TO, 4, L>), grid, blk, 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
   else if (kind == 1)
-    hipLaunchKernelGGL((k_colfs3<float, TO, 1>), grid, blk, 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+    hipLaunchKernelGGL((k_colfs3<float, TO, 1, L>), grid, blk, 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
   else if (solve)
-    hipLaunchKernelGGL((k_colfs3<float, TO, 2>), grid, blk, 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+    hipLaunchKernelGGL((k_colfs3<float, TO, 2, L>), grid, blk, 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
   else
-    hipLaunchKernelGGL((k_colfs3<float, TO, 0>), grid, blk, 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
+    hipLaunchKernelGGL((k_colfs3<float, TO, 0, L>), grid, blk, 0, st, X, V, M, tj, tox, toy, r2n, tw, bg);
   return hipGetLastError();
 }
 }  // namespace sg
@@ -243,10 +246,14 @@ static hipError_t launch_colfs3(const cx<float>* X, cx<float>* V, int M, int tj,
 hipError_t sg_launch_colfs(int prec, int N, const void* X, void* V, int M, int tj, const void* tx, const void* ty,
                            int kind, int tab_bytes, const void* r2n, int solve, const void* tw, const sg_bgrid* bg,
                            int ngrids, hipStream_t st) {
-  if (N == 1536) {
+  if (N == 1536 || N == 768) {
     if (prec != 1 || tab_bytes != 8) return hipErrorInvalidValue;
-    return launch_colfs3<float2>((const cx<float>*)X, (cx<float>*)V, M, tj, tx, ty, kind, (const cx<float>*)r2n,
-                                 solve, (const cx<float>*)tw, bg, ngrids, st);
+    auto go = [&](auto ll) {
+      return launch_colfs3<float2, decltype(ll)::value>((const cx<float>*)X, (cx<float>*)V, M, tj, tx, ty, kind,
+                                                        (const cx<float>*)r2n, solve, (const cx<float>*)tw, bg, ngrids,
+                                                        st);
+    };
+    return N == 1536 ? go(std::integral_constant<int, 512>{}) : go(std::integral_constant<int, 256>{});
   }
   if (prec == 0) {
     if (tab_bytes != 8) return hipErrorInvalidValue;

@@ -2,7 +2,7 @@
 // the kernel's inputs from a file written by the test, runs the kernel over
 // every column, writes its output.  Configuration at compile time: EMU_KERNEL
 // (0 the column pass k_colfs, 1 the adjoint column pass k_colfs_adj, 2 the
-// plan-time spectrum columns k_specfs, 3 the column pass of 1536, k_colfs3),
+// plan-time spectrum columns k_specfs, 3 the column pass of 1536 or 768, k_colfs3),
 // EMU_R (float|double), EMU_N, EMU_E,
 // EMU_SLOTS, EMU_MODE, EMU_TO (table element type), EMU_SPLIT (1: the
 // component-split pair of column-pass launches, x then y; 2: both in one
@@ -78,9 +78,9 @@ static void run_kernel(FILE* f, FILE* o, int M, int tj, std::vector<cx<R>>& tw, 
     rd(f, r2n, (size_t)2 * N);
     std::vector<cx<R>> V((size_t)2 * M * N, cx<R>{(R)0, (R)0});
     if constexpr (K == 3) {
-      static_assert(K == 3 && N == kC3N && E == kC3E, "k_colfs3 is the column pass of 1536");
+      static_assert(K == 3 && (N == 1536 || N == 768) && E == N / 192, "k_colfs3: columns of 1536 or 768");
       emu::launch(dim3(M), dim3(kC3T), [&] {
-        k_colfs3<R, TO, MODE>(X.data(), V.data(), M, tj, tx.data(), ty.data(), r2n.data(), tw.data(), nullptr);
+        k_colfs3<R, TO, MODE, N / 3>(X.data(), V.data(), M, tj, tx.data(), ty.data(), r2n.data(), tw.data(), nullptr);
       });
     } else {
       run_all<SPLIT>(M, tj, X, V, tx, ty, r2n, tw);
@@ -129,11 +129,11 @@ int main(int argc, char** argv) {
   FILE* f = fopen(argv[2], "rb");
   if (!f) return 2;
   // the four-step twiddle table from long double roots, rounded once (for
-  // k_colfs3: that of its 512-point sub-transforms)
-  constexpr int TN = EMU_KERNEL == 3 ? kC3L : N;
-  using S = fs_shape<TN, E>;
+  // k_colfs3: that of the 512-point sub-transforms, which 768 ignores)
+  constexpr int TN = EMU_KERNEL == 3 ? 512 : N, TE = EMU_KERNEL == 3 ? 8 : E;
+  using S = fs_shape<TN, TE>;
   std::vector<double> re(S::TW_SIZE), im(S::TW_SIZE);
-  fs_fill_twiddles<TN, E>(
+  fs_fill_twiddles<TN, TE>(
       [](int m, int L, double* cr, double* ci) {
         const long double a = 6.283185307179586476925286766559005768L * m / L;
         *cr = (double)cosl(a);

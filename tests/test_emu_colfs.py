@@ -6,7 +6,7 @@ definition in numpy (tests/emu/colpass_ref.py), and that ThreadSanitizer
 reports no data race on the LDS (an access that no barrier orders against
 another thread's access to the same element).  Covers the shapes the GPU
 runs (N = 2048, 4096 and 8192 in FP32 and FP64, 1024 in FP64, every LDS plan
-and the component split; the radix-3 form for N = 1536), and 1024 in FP32,
+and the component split; the radix-3 form for N = 1536 and 768), and 1024 in FP32,
 which the library leaves to the Stockham kernel, on a few columns each."""
 import os
 import shutil
@@ -80,14 +80,15 @@ def test_column_pass(tmp_path, prec, N, E, slots, k, to, split, pf):
     _column_case(tmp_path, 0, prec, N, E, slots, k, to, split, pf)
 
 
-# the radix-3 column pass of 1536 (k_colfs3, FP32): every order, both table forms
-FWD3 = [(3, "float2"), (1, "float2"), (2, "float2"), (4, "float"), (5, "float2")]
+# the radix-3 column pass of 1536 and 768 (k_colfs3, FP32): every order, both table forms
+FWD3 = [(1536, 3, "float2"), (1536, 1, "float2"), (1536, 2, "float2"), (1536, 4, "float"), (1536, 5, "float2"),
+        (768, 3, "float2"), (768, 1, "float"), (768, 2, "float2"), (768, 4, "float2"), (768, 5, "float")]
 
 
 @pytest.mark.skipif(GXX is None, reason="g++ not found")
-@pytest.mark.parametrize("k,to", FWD3, ids=[f"k{c[0]}-{c[1]}" for c in FWD3])
-def test_column_pass_1536(tmp_path, k, to):
-    _column_case(tmp_path, 3, 32, 1536, 8, 4, k, to, 0, 0)
+@pytest.mark.parametrize("N,k,to", FWD3, ids=[f"{c[0]}-k{c[1]}-{c[2]}" for c in FWD3])
+def test_column_pass_radix3(tmp_path, N, k, to):
+    _column_case(tmp_path, 3, 32, N, N // 192, 4, k, to, 0, 0)
 
 
 def _column_case(tmp_path, kernel, prec, N, E, slots, k, to, split, pf):

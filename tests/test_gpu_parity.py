@@ -119,6 +119,12 @@ CASES = [
     (3, 16, 1536, (-1, 1, -96, 96), "random"),
     (4, 8, 1536, (-0.5, 0.5, -96, 96), "random"),
     (5, 8, 1536, (-0.5, 0.5, -96, 96), "random"),
+    # columns of 768 (FP32: the radix-3 column pass with 256-point waves)
+    (1, 8, 768, (-0.5, 0.5, -48, 48), "random"),
+    (2, 16, 768, (-1, 1, -48, 48), "random"),
+    (3, 8, 768, (-0.5, 0.5, -48, 48), "random"),
+    (4, 8, 768, (-0.5, 0.5, -48, 48), "random"),
+    (5, 16, 768, (-1, 1, -48, 48), "random"),
 ]
 
 
