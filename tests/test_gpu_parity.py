@@ -125,6 +125,12 @@ CASES = [
     (3, 8, 768, (-0.5, 0.5, -48, 48), "random"),
     (4, 8, 768, (-0.5, 0.5, -48, 48), "random"),
     (5, 16, 768, (-1, 1, -48, 48), "random"),
+    # rows of 1536 and 768, every order but one
+    (1, 1536, 8, (-96, 96, -0.5, 0.5), "random"),
+    (3, 1536, 16, (-96, 96, -1, 1), "random"),
+    (4, 1536, 8, (-96, 96, -0.5, 0.5), "random"),
+    (2, 768, 8, (-48, 48, -0.5, 0.5), "random"),
+    (5, 768, 16, (-48, 48, -1, 1), "random"),
 ]
 
 
