@@ -93,6 +93,11 @@
 #ifndef SG_COL_NBUF32
 #define SG_COL_NBUF32 4
 #endif
+// skewed LDS layout of the forward row pass's transposed store (1: one slot
+// every 32 elements, 0: plain)
+#ifndef SG_RF_SKEW
+#define SG_RF_SKEW 1
+#endif
 // exchange buffers per row of the FP32 row passes (2: both half-length
 // transforms share their barriers)
 #ifndef SG_RF_NBUF32
@@ -490,20 +495,24 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
     zo[e] = cx<R>{(R)0.5 * (sum.x + dif.y), (R)0.5 * (sum.y - dif.x)};
   }
   __syncthreads();
-  // transposed store: chunk of EC e-values = bins [2 e0 T, 2 (e0+EC) T) of all G rows
+  // transposed store: chunk of EC e-values = bins [2 e0 T, 2 (e0+EC) T) of all G rows.
+  // The writes of one wave are 2G elements apart; with the one-per-32 skew
+  // (where the LDS holds it) they fall in distinct banks.
+  constexpr bool SKW = SG_RF_SKEW && (2 * T * EC + (2 * T * EC + 31) / 32 <= SLOT * NB);
 #pragma unroll
   for (int e0 = 0; e0 < E; e0 += EC) {
 #pragma unroll
     for (int e = e0; e < e0 + EC && e < E; ++e) {
       const int pl = 2 * (t + (e - e0) * T);
-      smem[pl * G + g] = xe[e];
-      smem[(pl + 1) * G + g] = zo[e];
+      const int i0 = pl * G + g, i1 = (pl + 1) * G + g;
+      smem[SKW ? pad(i0) : i0] = xe[e];
+      smem[SKW ? pad(i1) : i1] = zo[e];
     }
     __syncthreads();
     const int nchunk = 2 * T * (E - e0 < EC ? E - e0 : EC) * G;
     for (int idx = threadIdx.x; idx < nchunk; idx += blockDim.x) {
       const int pl = idx / G, gg = idx % G;
-      if (row0 + gg < nrows) X[(int64_t)(2 * e0 * T + pl) * ldx + row0 + gg] = smem[idx];
+      if (row0 + gg < nrows) X[(int64_t)(2 * e0 * T + pl) * ldx + row0 + gg] = smem[SKW ? pad(idx) : idx];
     }
     __syncthreads();
   }
