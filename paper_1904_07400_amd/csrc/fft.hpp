@@ -209,8 +209,15 @@ struct roots_t {
 #define SG_TW_EARLY_BYTES 64
 #endif
 
-// Twiddles of stage S of plan<L, L/T> held by one thread: w[u][q] for its
-// butterfly u and input q >= 1 (nothing for the first stage, Ns = 1).
+// FP32 stages of radix 8 and 16 load the twiddles of inputs q = 1, 2, 4
+// (and 8) only and form the others as products of those, at most two
+// products deep (fewer table loads; each product adds about one rounding)
+#ifndef SG_TW_DERIVE
+#define SG_TW_DERIVE 1
+#endif
+
+// Twiddles of stage S of plan<L, L/T> held by one thread: the table entries
+// it loads for each butterfly u (nothing for the first stage, Ns = 1).
 template <int L, int T, int S, typename R>
 struct stage_tw {
   using P = plan<L, L / T>;
@@ -219,9 +226,13 @@ struct stage_tw {
   static constexpr int NB = (L / T) / r;
   static constexpr int Ns = live ? P::ns_before(S) : 1;
   static constexpr bool has = live && Ns > 1;
+  static constexpr bool DER = SG_TW_DERIVE && sizeof(R) == 4 && (r == 8 || r == 16);
+  // entries loaded per butterfly: inputs q = 1, 2, 4 (, 8), or every q >= 1
+  static constexpr int NL = DER ? (r == 16 ? 4 : 3) : (r > 1 ? r - 1 : 1);
   // loaded one stage ahead when they take few registers, else at the stage
-  static constexpr bool early = has && NB * (r - 1) * (int)sizeof(cx<R>) <= SG_TW_EARLY_BYTES;
-  cx<R> w[early ? NB : 1][early ? r : 1];
+  static constexpr bool early = has && NB * NL * (int)sizeof(cx<R>) <= SG_TW_EARLY_BYTES;
+  cx<R> w[early ? NB : 1][early ? NL : 1];
+  static __device__ __forceinline__ constexpr int qload(int i) { return DER ? (1 << i) : i + 1; }
   __device__ __forceinline__ cx<R> fetch(const cx<R>* __restrict__ tw, int t, int u, int q) const {
     constexpr int off = P::tw_offset(S);
     const unsigned k = (unsigned)(t + u * T) % (unsigned)Ns;
@@ -232,13 +243,40 @@ struct stage_tw {
 #pragma unroll
       for (int u = 0; u < NB; ++u)
 #pragma unroll
-        for (int q = 1; q < r; ++q) w[u][q] = fetch(tw, t, u, q);
+        for (int i = 0; i < NL; ++i) w[u][i] = fetch(tw, t, u, qload(i));
     }
   }
-  // twiddle q of butterfly u: from registers, or loaded now
-  __device__ __forceinline__ cx<R> get(const cx<R>* __restrict__ tw, int t, int u, int q) const {
-    if constexpr (early) return w[u][q];
-    else return fetch(tw, t, u, q);
+  // loaded entry i of butterfly u: from registers, or loaded now
+  __device__ __forceinline__ cx<R> loaded(const cx<R>* __restrict__ tw, int t, int u, int i) const {
+    if constexpr (early) return w[u][i];
+    else return fetch(tw, t, u, qload(i));
+  }
+  // all twiddles of butterfly u: o[q] = w_{Ns r}^{k q}, q in [1, r)
+  __device__ __forceinline__ void all(const cx<R>* __restrict__ tw, int t, int u, cx<R>* o) const {
+    if constexpr (!DER) {
+#pragma unroll
+      for (int q = 1; q < r; ++q) o[q] = loaded(tw, t, u, q - 1);
+    } else {
+      o[1] = loaded(tw, t, u, 0);
+      o[2] = loaded(tw, t, u, 1);
+      o[4] = loaded(tw, t, u, 2);
+      o[3] = cmul(o[1], o[2]);
+      o[5] = cmul(o[4], o[1]);
+      o[6] = cmul(o[4], o[2]);
+      if constexpr (r == 16) {
+        o[8] = loaded(tw, t, u, 3);
+        o[7] = cmulc(o[8], o[1]);  // w^8 conj(w)
+        o[9] = cmul(o[8], o[1]);
+        o[10] = cmul(o[8], o[2]);
+        o[11] = cmul(o[8], o[3]);
+        o[12] = cmul(o[8], o[4]);
+        o[13] = cmul(o[12], o[1]);
+        o[14] = cmul(o[12], o[2]);
+        o[15] = cmul(o[8], o[7]);
+      } else {
+        o[7] = cmul(o[4], o[3]);
+      }
+    }
   }
 };
 
@@ -260,11 +298,10 @@ __device__ __forceinline__ void stockham_stage(cx<R>* v, cx<R>* lds, const W& tw
 #pragma unroll
     for (int q = 0; q < r; ++q) a[q] = v[u + q * NB];
     if constexpr (Ns > 1) {
+      cx<R> w[r];
+      tws.all(tw, t, u, w);
 #pragma unroll
-      for (int q = 1; q < r; ++q) {
-        const cx<R> w = tws.get(tw, t, u, q);
-        a[q] = INV ? cmulc(a[q], w) : cmul(a[q], w);
-      }
+      for (int q = 1; q < r; ++q) a[q] = INV ? cmulc(a[q], w[q]) : cmul(a[q], w[q]);
     }
     dft<r, INV>(a);
     if constexpr (last) {
@@ -327,11 +364,12 @@ __device__ __forceinline__ void stockham_stage2(cx<R>* v0, cx<R>* v1, cx<R>* lds
       a1[q] = v1[u + q * NB];
     }
     if constexpr (Ns > 1) {
+      cx<R> w[r];
+      tws.all(tw, t, u, w);
 #pragma unroll
       for (int q = 1; q < r; ++q) {
-        const cx<R> w = tws.get(tw, t, u, q);
-        a0[q] = INV ? cmulc(a0[q], w) : cmul(a0[q], w);
-        a1[q] = INV ? cmulc(a1[q], w) : cmul(a1[q], w);
+        a0[q] = INV ? cmulc(a0[q], w[q]) : cmul(a0[q], w[q]);
+        a1[q] = INV ? cmulc(a1[q], w[q]) : cmul(a1[q], w[q]);
       }
     }
     dft<r, INV>(a0);
@@ -396,10 +434,7 @@ __device__ __forceinline__ void stockham_stage_n(cx<R> (&v)[NA][L / T], cx<R>* l
   for (int u = 0; u < NB; ++u) {
     const int b = t + u * T;
     cx<R> w[r];
-    if constexpr (Ns > 1) {
-#pragma unroll
-      for (int q = 1; q < r; ++q) w[q] = tws.get(tw, t, u, q);
-    }
+    if constexpr (Ns > 1) tws.all(tw, t, u, w);
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       cx<R> a[r];
