@@ -209,11 +209,15 @@ struct roots_t {
 #define SG_TW_EARLY_BYTES 64
 #endif
 
-// FP32 stages of radix 8 and 16 load the twiddles of inputs q = 1, 2, 4
+// Stages of radix 8 and 16 load the twiddles of inputs q = 1, 2, 4
 // (and 8) only and form the others as products of those, at most two
 // products deep (fewer table loads; each product adds about one rounding)
 #ifndef SG_TW_DERIVE
 #define SG_TW_DERIVE 1
+#endif
+// the same for the FP64 stages
+#ifndef SG_TW_DERIVE64
+#define SG_TW_DERIVE64 1
 #endif
 
 // Twiddles of stage S of plan<L, L/T> held by one thread: the table entries
@@ -226,7 +230,7 @@ struct stage_tw {
   static constexpr int NB = (L / T) / r;
   static constexpr int Ns = live ? P::ns_before(S) : 1;
   static constexpr bool has = live && Ns > 1;
-  static constexpr bool DER = SG_TW_DERIVE && sizeof(R) == 4 && (r == 8 || r == 16);
+  static constexpr bool DER = (sizeof(R) == 4 ? SG_TW_DERIVE : SG_TW_DERIVE64) && (r == 8 || r == 16);
   // entries loaded per butterfly: inputs q = 1, 2, 4 (, 8), or every q >= 1
   static constexpr int NL = DER ? (r == 16 ? 4 : 3) : (r > 1 ? r - 1 : 1);
   // loaded one stage ahead when they take few registers, else at the stage
