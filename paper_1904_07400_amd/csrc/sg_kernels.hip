@@ -98,6 +98,13 @@
 #ifndef SG_RF_SKEW
 #define SG_RF_SKEW 1
 #endif
+// the row passes read entry s + j of their table of roots of unity as
+// entry s times entry j, j the same for the whole workgroup (a scalar load),
+// so that each thread reads one entry of its own per set (1) or every entry
+// (0)
+#ifndef SG_ROOT_SPLIT
+#define SG_ROOT_SPLIT 1
+#endif
 // exchange buffers per row of the FP32 row passes (2: both half-length
 // transforms share their barriers)
 #ifndef SG_RF_NBUF32
@@ -345,6 +352,14 @@ __global__ void k_weights(int k, double hx, double hy, int M, int N, double* __r
 
 #endif
 
+// entry s + j of a table of roots of unity (entry n = exp(+-2 pi i n / L)),
+// given ws = entry s
+template <typename R>
+__device__ __forceinline__ cx<R> root_at(const cx<R>* __restrict__ tab, cx<R> ws, int s, int j) {
+  if constexpr (SG_ROOT_SPLIT) return j == 0 ? ws : cmul(ws, tab[j]);
+  else return tab[s + j];
+}
+
 // ---------------------------------------------------------------- pass A --
 // Real FFT of length 2M of a row whose upper half is zero (or, with full,
 // of a row of 2M values), via the complex FFT of length M of
@@ -446,7 +461,7 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
     }
   } else {
 #pragma unroll
-    for (int e = 0; e < E; ++e) zo[e] = cmul(ze[e], r2m[2 * (t + e * T)]);  // w_M^n
+    for (int e = 0; e < E; ++e) zo[e] = cmul(ze[e], root_at(r2m, r2m[2 * t], 2 * t, 2 * e * T));  // w_M^n
   }
   cx<R> xe[E];
   if constexpr (NB == 2) {
@@ -476,7 +491,7 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
   for (int e = 0; e < E; ++e) {
     const int pp = t + e * T;                         // X bin p = 2 pp
     const cx<R> zp = ze[e], zm = conj(lds[pad(pp == 0 ? 0 : L - pp)]);
-    const cx<R> sum = zp + zm, dif = cmul(r2m[2 * pp], zp - zm);
+    const cx<R> sum = zp + zm, dif = cmul(root_at(r2m, r2m[2 * t], 2 * t, 2 * e * T), zp - zm);
     xe[e] = cx<R>{(R)0.5 * (sum.x + dif.y), (R)0.5 * (sum.y - dif.x)};
     if (pp == 0) xe[e] = cx<R>{zp.x + zp.y, zp.x - zp.y};
   }
@@ -491,7 +506,7 @@ __global__ void __launch_bounds__((rowfwd_cfg<R, In, M>::G * rowfwd_cfg<R, In, M
   for (int e = 0; e < E; ++e) {
     const int pp = t + e * T;                         // X bin p = 2 pp + 1
     const cx<R> zp = zo[e], zm = conj(lds2[pad(L - 1 - pp)]);
-    const cx<R> sum = zp + zm, dif = cmul(r2m[2 * pp + 1], zp - zm);
+    const cx<R> sum = zp + zm, dif = cmul(root_at(r2m, r2m[2 * t + 1], 2 * t + 1, 2 * e * T), zp - zm);
     zo[e] = cx<R>{(R)0.5 * (sum.x + dif.y), (R)0.5 * (sum.y - dif.x)};
   }
   __syncthreads();
@@ -981,7 +996,7 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M, VA>::G * rowinv_cfg<R, M, VA
     // phases of the odd half, loaded now so that their latency hides
     // behind the transforms
 #pragma unroll
-    for (int e = 0; e < E; ++e) wr[e] = r2m[t + e * T];
+    for (int e = 0; e < E; ++e) wr[e] = root_at(r2m, r2m[t], t, e * T);
     // both half-length inverses through the same stages
     fftn<true, M, T, 2>(v2, lds, LL, tw, t);
   } else {
@@ -994,7 +1009,7 @@ __global__ void __launch_bounds__((rowinv_cfg<R, M, VA>::G * rowinv_cfg<R, M, VA
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int n = ts + e * T;
-      const cx<R> r = v2[0][e] + cmulc(v2[1][e], NB == 2 ? wr[e] : r2m[n]);
+      const cx<R> r = v2[0][e] + cmulc(v2[1][e], NB == 2 ? wr[e] : root_at(r2m, r2m[ts], ts, e * T));
       fx[(int64_t)row * M + n] = (Out)r.x;
       fy[(int64_t)row * M + n] = (Out)r.y;
     }
@@ -1205,10 +1220,10 @@ __global__ void __launch_bounds__((rowc2r_cfg<R, M, HI>::G * rowfwd_cfg<R, R, M>
       const cx<R> x0 = xe;  // (X_0, X_M)
       ze[e] = cx<R>{x0.x + x0.y, x0.x - x0.y};
     } else {
-      const cx<R> sum = xe + me, dif = cmulc(xe - me, r2m[2 * pp]);
+      const cx<R> sum = xe + me, dif = cmulc(xe - me, root_at(r2m, r2m[2 * t], 2 * t, 2 * e * T));
       ze[e] = cx<R>{sum.x - dif.y, sum.y + dif.x};
     }
-    const cx<R> sum = xo + mo, dif = cmulc(xo - mo, r2m[2 * pp + 1]);
+    const cx<R> sum = xo + mo, dif = cmulc(xo - mo, root_at(r2m, r2m[2 * t + 1], 2 * t + 1, 2 * e * T));
     zo[e] = cx<R>{sum.x - dif.y, sum.y + dif.x};
   }
   fft<true, L, T>(ze, lds, tw, t);
@@ -1217,7 +1232,7 @@ __global__ void __launch_bounds__((rowc2r_cfg<R, M, HI>::G * rowfwd_cfg<R, R, M>
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int n = t + e * T;
-    ze[e] = ze[e] + cmulc(zo[e], r2m[2 * n]);
+    ze[e] = ze[e] + cmulc(zo[e], root_at(r2m, r2m[2 * t], 2 * t, 2 * e * T));
   }
   if (solve) {
 #pragma unroll
