@@ -188,6 +188,63 @@ def trace_summary(stats_csv, trace_csv):
     return "\n".join(out)
 
 
+def batch_trace_summary(trace_csv, per_step):
+    """Per-step spans and per-length kernel time of a rocprofv3 kernel trace of
+    `bench.py --batch-only`: of the FP32 per-step kernels, the graph replays
+    are the launches on streams other than the plan's, the eager steps the
+    first as many launches on the plan's stream after them; per_step =
+    launches per step (three per class)."""
+    import csv
+    import re
+    step_kernel = re.compile(r"sg::k_(row_fwd|row_inv|col|colfs|colfs3)<float")
+    rows = sorted((r for r in csv.DictReader(open(trace_csv)) if step_kernel.search(r["Kernel_Name"])),
+                  key=lambda r: int(r["Start_Timestamp"]))
+    home = rows[0]["Stream_Id"]
+    graph = [r for r in rows if r["Stream_Id"] != home]
+    last = max(int(r["Start_Timestamp"]) for r in graph)
+    eager = [r for r in rows if r["Stream_Id"] == home and int(r["Start_Timestamp"]) > last][:len(graph)]
+
+    def steps(rs):
+        return [rs[i:i + per_step] for i in range(0, len(rs) - per_step + 1, per_step)]
+
+    def span(st):
+        return (max(int(r["End_Timestamp"]) for r in st) - min(int(r["Start_Timestamp"]) for r in st)) / 1e6
+
+    def kind(name):
+        nm = re.sub(r"HIP_vector_type<(\w+), (\d)u>", r"\1\2", name)
+        m = re.search(r"sg::(k_\w+)<([^>]*)>", nm)
+        k, args = m.group(1), [a.strip() for a in m.group(2).split(",")]
+        if k == "k_row_fwd":
+            return "A", int(args[2]), k
+        if k == "k_row_inv":
+            return "C", int(args[2]), k
+        if k == "k_colfs3":
+            return "B", 3 * int(args[-1]), k
+        return "B", int(args[2]), k
+
+    gs, es = steps(graph), steps(eager)
+    out = ["- graph: " + str([round(span(s), 3) for s in gs]),
+           "- eager: " + str([round(span(s), 3) for s in es]), ""]
+    timed = es[2:] if len(es) > 2 else es
+    tab, bk = {}, {}
+    for st in timed:
+        for r in st:
+            ps, n, k = kind(r["Kernel_Name"])
+            us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 / len(timed)
+            tab.setdefault(n, {"A": 0.0, "B": 0.0, "C": 0.0})[ps] += us
+            if ps == "B":
+                bk[n] = k
+    out += ["| length | pass A | pass B | pass C | sum | pass B kernel |", "|---|---|---|---|---|---|"]
+    tot = {"A": 0.0, "B": 0.0, "C": 0.0}
+    for n in sorted(tab):
+        t = tab[n]
+        for ps in tot:
+            tot[ps] += t[ps]
+        out.append(f"| {n} | {t['A']:.0f} | {t['B']:.0f} | {t['C']:.0f} | {sum(t.values()):.0f} | `{bk.get(n, '')}` |")
+    out.append(f"| all | {tot['A']:.0f} | {tot['B']:.0f} | {tot['C']:.0f} | {sum(tot.values()):.0f} | |")
+    return "\n".join(out)
+
+
 def measured_traffic(kname, n):
     """HBM bytes per launch of the FP32 kernel from the committed counter
     profile, or None if there is none for this size or the kernels changed
@@ -497,11 +554,16 @@ def main():
                     help="print per-kernel HBM traffic from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--trace-summary", nargs=2, metavar=("STATS_CSV", "TRACE_CSV"),
                     help="print a table of a rocprofv3 --kernel-trace --stats run and exit")
+    ap.add_argument("--batch-trace-summary", nargs=2, metavar=("TRACE_CSV", "LAUNCHES_PER_STEP"),
+                    help="per-step spans and per-length kernel time of a --batch-only kernel trace")
     ap.add_argument("--sq-summary", nargs="+", metavar="PMC_CSV",
                     help="print per-kernel instruction counters of rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
     if args.trace_summary:
         print(trace_summary(*args.trace_summary))
+        return
+    if args.batch_trace_summary:
+        print(batch_trace_summary(args.batch_trace_summary[0], int(args.batch_trace_summary[1])))
         return
     if args.sq_summary:
         print(f"source hash: {kernel_source_hash()}")
